@@ -1,0 +1,691 @@
+/*
+ * PixelSNE CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 implementation of what PixelSNE computes (Kim et al.,
+ * "PixelSNE: Visualizing Fast with Just Enough Precision via Pixel-Aligned
+ * Stochastic Neighbor Embedding", arXiv:1611.02568).  It exists to check the
+ * GPU library; only the tests, the smoke check and the benchmark's CPU
+ * baseline may load it.  It shares no code, header or constant table with
+ * the GPU path.
+ *
+ * Every step follows the paper's order and notation:
+ *   - high-dimensional affinities P from a Gaussian kernel at a perplexity
+ *     (Section 2.2) over k nearest neighbours (Section 2.3);
+ *   - pixel coordinates z with 0 <= z < r (Eq. 1-2);
+ *   - the pixel-aligned quadtree (P-Quadtree, Section 3.1): the root is the
+ *     fixed screen, cells split down to unit pixels, each cell holds its
+ *     boundary (Eq. 6), member count and centre of mass (Eq. 7-8);
+ *   - Barnes-Hut repulsion by depth-first traversal with the opening
+ *     criterion (Eq. 11), leaf stop (Section 3.1, "Bounded tree depth");
+ *   - q in terms of z with the scale factors beta (Eq. 12-13) and the
+ *     gradient of Eq. 5 in the pixel frame;
+ *   - screen-driven scaling (Section 3.2).
+ *
+ * Readings where the paper is silent or garbled (each one is listed in the
+ * design notes): the opening test compares the cell diagonal with the
+ * unsquared distance; the test runs in the true (beta-weighted) metric; the
+ * leaf that holds point i excludes i itself; the tree root is [0, 2^L)^2 with
+ * unit-pixel leaves; pixel = clamp(floor(z), 0, r-1); optimiser constants are
+ * the usual Barnes-Hut-SNE ones (eta 200, momentum 0.5 -> 0.8 at 250, gains
+ * +0.2 / x0.8 floored at 0.01, exaggeration 12 for 250 iterations).
+ *
+ * Centre-of-mass sums and Z use compensated (Neumaier) summation so that the
+ * oracle's sums are accurate to a few ulp regardless of order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+
+int orc_version(void) { return 3; }
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* compensated summation                                               */
+/* ------------------------------------------------------------------ */
+typedef struct { double s, c; } csum;
+static inline void cs_add(csum* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static inline double cs_get(const csum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------ */
+/* k nearest neighbours, brute force (replaces the VP / RP trees of     */
+/* Section 2.3 and 3.3).  Squared Euclidean distance in FP64; the       */
+/* point itself is excluded; ties go to the smaller index.              */
+/* ------------------------------------------------------------------ */
+static inline int knn_less(double da, int32_t ja, double db, int32_t jb) {
+    return da < db || (da == db && ja < jb);
+}
+
+/* max-heap on (d, j) */
+static void heap_sift_down(double* d, int32_t* j, int m, int pos) {
+    for (;;) {
+        int l = 2 * pos + 1, r = l + 1, big = pos;
+        if (l < m && knn_less(d[big], j[big], d[l], j[l])) big = l;
+        if (r < m && knn_less(d[big], j[big], d[r], j[r])) big = r;
+        if (big == pos) return;
+        double td = d[pos]; d[pos] = d[big]; d[big] = td;
+        int32_t tj = j[pos]; j[pos] = j[big]; j[big] = tj;
+        pos = big;
+    }
+}
+static void heap_sift_up(double* d, int32_t* j, int pos) {
+    while (pos > 0) {
+        int p = (pos - 1) / 2;
+        if (!knn_less(d[p], j[p], d[pos], j[pos])) return;
+        double td = d[pos]; d[pos] = d[p]; d[p] = td;
+        int32_t tj = j[pos]; j[pos] = j[p]; j[p] = tj;
+        pos = p;
+    }
+}
+
+/* rows == NULL: all n rows.  Outputs idx/d2 are [nrows][k], ascending. */
+int orc_knn(const double* X, int64_t n, int32_t D, int32_t k, const int64_t* rows,
+            int64_t nrows, int32_t* idx_out, double* d2_out) {
+    if (!X || n < 2 || D < 1 || k < 1 || k > n - 1) return ORC_EINVAL;
+    if (!rows) nrows = n;
+    int64_t q;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (q = 0; q < nrows; q++) {
+        int64_t i = rows ? rows[q] : q;
+        double* hd = d2_out + q * k;
+        int32_t* hj = idx_out + q * k;
+        int m = 0;
+        const double* xi = X + i * (int64_t)D;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            const double* xj = X + j * (int64_t)D;
+            double s = 0.0;
+            for (int t = 0; t < D; t++) { double e = xi[t] - xj[t]; s += e * e; }
+            if (m < k) {
+                hd[m] = s; hj[m] = (int32_t)j; heap_sift_up(hd, hj, m); m++;
+            } else if (knn_less(s, (int32_t)j, hd[0], hj[0])) {
+                hd[0] = s; hj[0] = (int32_t)j; heap_sift_down(hd, hj, m, 0);
+            }
+        }
+        /* heap sort into ascending order */
+        for (int e = m - 1; e > 0; e--) {
+            double td = hd[0]; hd[0] = hd[e]; hd[e] = td;
+            int32_t tj = hj[0]; hj[0] = hj[e]; hj[e] = tj;
+            heap_sift_down(hd, hj, e, 0);
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Perplexity calibration (Section 2.2): for each row find the          */
+/* Gaussian precision b_i with entropy H(P_i) = ln(u) (natural log),   */
+/* p_{j|i} = exp(-b_i * delta_j) / sum, delta_j = d2_ij - min_j d2_ij   */
+/* (the shift cancels in the normalisation).  Bisection that doubles / */
+/* halves b until the root is bracketed, from b = 1; stops when         */
+/* |H - ln u| < tol or after max_iter evaluations.                      */
+/* ------------------------------------------------------------------ */
+int orc_perplexity(const double* d2, int64_t nrows, int32_t k, double perplexity, double tol,
+                   int32_t max_iter, double* P_out, double* beta_out, int32_t* iters_out) {
+    if (!d2 || !P_out || nrows < 1 || k < 1 || !(perplexity > 0)) return ORC_EINVAL;
+    const double target = log(perplexity);
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < nrows; i++) {
+        const double* d = d2 + i * k;
+        double* p = P_out + i * k;
+        double dmin = d[0];
+        for (int j = 1; j < k; j++) if (d[j] < dmin) dmin = d[j];
+        double b = 1.0, lo = 0.0, hi = 0.0;
+        int have_lo = 0, have_hi = 0, it;
+        double S = 0.0;
+        for (it = 0; it < max_iter; it++) {
+            S = 0.0; double SD = 0.0;
+            for (int j = 0; j < k; j++) {
+                double dj = d[j] - dmin;
+                double e = exp(-b * dj);
+                p[j] = e; S += e; SD += dj * e;
+            }
+            double H = log(S) + b * SD / S;
+            if (fabs(H - target) < tol || it == max_iter - 1) break;
+            if (H > target) {              /* too flat: sharpen */
+                lo = b; have_lo = 1;
+                b = have_hi ? 0.5 * (b + hi) : 2.0 * b;
+            } else {                       /* too peaked: flatten */
+                hi = b; have_hi = 1;
+                b = have_lo ? 0.5 * (b + lo) : 0.5 * b;
+            }
+        }
+        for (int j = 0; j < k; j++) p[j] /= S;
+        if (beta_out) beta_out[i] = b;
+        if (iters_out) iters_out[i] = it + 1;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Symmetrisation: p_ij = (p_{j|i} + p_{i|j}) / (2n) over the union of  */
+/* the directed kNN edges, zero diagonal, CSR with ascending columns.   */
+/* Both entries of a pair are formed from the same two summands, so the */
+/* result is exactly symmetric.  Returns nnz (< 0 on error).  Call once */
+/* with col == NULL to size the arrays.                                 */
+/* ------------------------------------------------------------------ */
+typedef struct { int32_t r, c; double v; } coo_t;
+static int coo_cmp(const void* a, const void* b) {
+    const coo_t* x = (const coo_t*)a; const coo_t* y = (const coo_t*)b;
+    if (x->r != y->r) return x->r < y->r ? -1 : 1;
+    if (x->c != y->c) return x->c < y->c ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k,
+                       int64_t* row_ptr, int32_t* col, double* val, int64_t cap) {
+    if (!idx || !Pc || n < 2 || k < 1) return ORC_EINVAL;
+    int64_t m = 2 * n * (int64_t)k;
+    coo_t* e = (coo_t*)malloc(sizeof(coo_t) * (size_t)m);
+    if (!e) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; i++)
+        for (int t = 0; t < k; t++) {
+            int32_t j = idx[i * k + t];
+            double v = Pc[i * k + t];
+            e[2 * (i * k + t)] = (coo_t){(int32_t)i, j, v};
+            e[2 * (i * k + t) + 1] = (coo_t){j, (int32_t)i, v};
+        }
+    qsort(e, (size_t)m, sizeof(coo_t), coo_cmp);
+    int64_t nnz = 0;
+    for (int64_t a = 0; a < m;) {
+        int64_t b = a + 1;
+        while (b < m && e[b].r == e[a].r && e[b].c == e[a].c) b++;
+        if (e[a].r != e[a].c) nnz++;
+        a = b;
+    }
+    if (col) {
+        if (cap < nnz || !row_ptr || !val) { free(e); return ORC_EINVAL; }
+        for (int64_t i = 0; i <= n; i++) row_ptr[i] = 0;
+        int64_t w = 0;
+        for (int64_t a = 0; a < m;) {
+            int64_t b = a + 1;
+            while (b < m && e[b].r == e[a].r && e[b].c == e[a].c) b++;
+            if (e[a].r != e[a].c) {
+                /* at most two summands (i->j and j->i), added once */
+                double s = e[a].v;
+                for (int64_t c = a + 1; c < b; c++) s += e[c].v;
+                col[w] = e[a].c;
+                val[w] = s / (2.0 * (double)n);
+                row_ptr[e[a].r + 1]++;
+                w++;
+            }
+            a = b;
+        }
+        for (int64_t i = 0; i < n; i++) row_ptr[i + 1] += row_ptr[i];
+    }
+    free(e);
+    return nnz;
+}
+
+/* ------------------------------------------------------------------ */
+/* Pixel assignment and Morton keys (Eq. 1-2, Section 3.1).             */
+/* pixel = clamp(floor(z), 0, r - 1); key interleaves x in even bits    */
+/* and y in odd bits, so the child index is 2*ybit + xbit (NW, NE, SW,  */
+/* SE with y pointing down the screen).                                 */
+/* ------------------------------------------------------------------ */
+static inline int32_t pixel_of(double z, int32_t r) {
+    double f = floor(z);
+    if (!(f >= 0.0)) return 0;           /* also catches NaN */
+    if (f > (double)(r - 1)) return r - 1;
+    return (int32_t)f;
+}
+
+static inline uint32_t morton2(uint32_t px, uint32_t py, int L) {
+    uint32_t key = 0;
+    for (int b = 0; b < L; b++) {
+        key |= ((px >> b) & 1u) << (2 * b);
+        key |= ((py >> b) & 1u) << (2 * b + 1);
+    }
+    return key;
+}
+
+static int log2_exact(int32_t r) {
+    if (r < 2 || (r & (r - 1))) return -1;
+    int L = 0;
+    while ((1 << L) < r) L++;
+    return L;
+}
+
+int orc_morton(const double* z, int64_t n, int32_t r, uint32_t* key) {
+    int L = log2_exact(r);
+    if (L < 0 || L > 16) return ORC_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        key[i] = morton2((uint32_t)pixel_of(z[2 * i], r), (uint32_t)pixel_of(z[2 * i + 1], r), L);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* P-Quadtree (Section 3.1).  Built by assigning each point, in index   */
+/* order, from the root down to its unit pixel; every cell on the way   */
+/* counts the point and accumulates its coordinates for the centre of  */
+/* mass (Eq. 8).                                                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t child[4];
+    int32_t level;
+    uint32_t prefix;
+    int64_t count;
+    csum sx, sy;
+} onode;
+
+typedef struct {
+    int32_t r, L;
+    int64_t n, nnodes, cap;
+    onode* nodes;
+    int32_t* leaf_of;       /* node id of each point's pixel */
+} otree;
+
+static int32_t tree_new_node(otree* t, int32_t level, uint32_t prefix) {
+    if (t->nnodes == t->cap) {
+        int64_t nc = t->cap ? 2 * t->cap : 1024;
+        onode* p = (onode*)realloc(t->nodes, sizeof(onode) * (size_t)nc);
+        if (!p) return -1;
+        t->nodes = p; t->cap = nc;
+    }
+    onode* c = &t->nodes[t->nnodes];
+    memset(c, 0, sizeof(*c));
+    c->child[0] = c->child[1] = c->child[2] = c->child[3] = -1;
+    c->level = level; c->prefix = prefix;
+    return (int32_t)t->nnodes++;
+}
+
+void orc_tree_free(void* h) {
+    otree* t = (otree*)h;
+    if (!t) return;
+    free(t->nodes); free(t->leaf_of); free(t);
+}
+
+void* orc_tree_build(const double* z, int64_t n, int32_t r) {
+    int L = log2_exact(r);
+    if (!z || n < 1 || L < 0 || L > 16) return NULL;
+    otree* t = (otree*)calloc(1, sizeof(otree));
+    if (!t) return NULL;
+    t->r = r; t->L = L; t->n = n;
+    t->leaf_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!t->leaf_of || tree_new_node(t, 0, 0) != 0) { orc_tree_free(t); return NULL; }
+    for (int64_t i = 0; i < n; i++) {
+        double zx = z[2 * i], zy = z[2 * i + 1];
+        uint32_t px = (uint32_t)pixel_of(zx, r), py = (uint32_t)pixel_of(zy, r);
+        int32_t c = 0;
+        for (int l = 0;; l++) {
+            onode* nd = &t->nodes[c];
+            nd->count++;
+            cs_add(&nd->sx, zx);
+            cs_add(&nd->sy, zy);
+            if (l == L) break;
+            int sh = L - 1 - l;           /* bit that splits this cell */
+            int q = (int)(((py >> sh) & 1u) << 1 | ((px >> sh) & 1u));
+            int32_t ch = nd->child[q];
+            if (ch < 0) {
+                uint32_t pre = (nd->prefix << 2) | (uint32_t)q;
+                ch = tree_new_node(t, l + 1, pre);
+                if (ch < 0) { orc_tree_free(t); return NULL; }
+                t->nodes[c].child[q] = ch;   /* nodes may have moved */
+            }
+            c = ch;
+        }
+        t->leaf_of[i] = c;
+    }
+    return t;
+}
+
+int32_t orc_tree_depth(const void* h) { return ((const otree*)h)->L; }
+int64_t orc_tree_num_nodes(const void* h) { return ((const otree*)h)->nnodes; }
+
+/* number of occupied cells at each level 0..L */
+int orc_tree_level_sizes(const void* h, int64_t* sizes) {
+    const otree* t = (const otree*)h;
+    for (int l = 0; l <= t->L; l++) sizes[l] = 0;
+    for (int64_t c = 0; c < t->nnodes; c++) sizes[t->nodes[c].level]++;
+    return ORC_OK;
+}
+
+typedef struct { uint32_t prefix; int64_t id; } pref_t;
+static int pref_cmp(const void* a, const void* b) {
+    const pref_t* x = (const pref_t*)a; const pref_t* y = (const pref_t*)b;
+    return x->prefix < y->prefix ? -1 : (x->prefix > y->prefix ? 1 : 0);
+}
+
+/* cells of one level ascending by Morton prefix: prefix, count, sums */
+int orc_tree_level(const void* h, int32_t level, uint32_t* prefix, int64_t* count, double* sum) {
+    const otree* t = (const otree*)h;
+    if (level < 0 || level > t->L) return ORC_EINVAL;
+    int64_t m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++) if (t->nodes[c].level == level) m++;
+    pref_t* v = (pref_t*)malloc(sizeof(pref_t) * (size_t)(m ? m : 1));
+    if (!v) return ORC_ENOMEM;
+    m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++)
+        if (t->nodes[c].level == level) { v[m].prefix = t->nodes[c].prefix; v[m].id = c; m++; }
+    qsort(v, (size_t)m, sizeof(pref_t), pref_cmp);
+    for (int64_t a = 0; a < m; a++) {
+        const onode* nd = &t->nodes[v[a].id];
+        if (prefix) prefix[a] = nd->prefix;
+        if (count) count[a] = nd->count;
+        if (sum) { sum[2 * a] = cs_get(&nd->sx); sum[2 * a + 1] = cs_get(&nd->sy); }
+    }
+    free(v);
+    return ORC_OK;
+}
+
+/* stable order of points by Morton key (ties by index) */
+typedef struct { uint32_t key; int64_t i; } kp_t;
+static int kp_cmp(const void* a, const void* b) {
+    const kp_t* x = (const kp_t*)a; const kp_t* y = (const kp_t*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);
+}
+
+int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted, int64_t* perm) {
+    int L = log2_exact(r);
+    if (L < 0) return ORC_EINVAL;
+    kp_t* v = (kp_t*)malloc(sizeof(kp_t) * (size_t)n);
+    if (!v) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; i++) {
+        v[i].key = morton2((uint32_t)pixel_of(z[2 * i], r), (uint32_t)pixel_of(z[2 * i + 1], r), L);
+        v[i].i = i;
+    }
+    qsort(v, (size_t)n, sizeof(kp_t), kp_cmp);
+    for (int64_t s = 0; s < n; s++) {
+        if (key_sorted) key_sorted[s] = v[s].key;
+        if (perm) perm[s] = v[s].i;
+    }
+    free(v);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Barnes-Hut repulsion on the P-Quadtree (Eq. 5 second term, Eq. 11,  */
+/* Eq. 12).  For point i, depth-first from the root, children in order  */
+/* 0..3.  At a cell with side w (pixels) and representative point c:    */
+/*   dz = z_i - c,  d2 = beta1 dz1^2 + beta2 dz2^2   (Eq. 12 metric)    */
+/*   diag2 = w^2 (beta1 + beta2)                      (cell diagonal^2)  */
+/*   a leaf is always used; an inner cell is used iff                    */
+/*   diag2 < theta^2 * d2  (diagonal / distance < theta), else recurse.  */
+/* A used cell adds m*w_ic to Z_i and m*w_ic^2*dz to R_i, w = 1/(1+d2).  */
+/* m = N_c, except in the leaf holding i: m = N_c - 1 and c is the mean */
+/* of the other points (the cell centre in CELL_CENTER mode); skipped   */
+/* when m = 0.                                                          */
+/* com_mode 0: centre of mass (Eq. 8); 1: geometric cell centre         */
+/* (Section 3.1 "simply approximate the center of mass").               */
+/* visits counts every cell reached by the traversal.                    */
+/* ------------------------------------------------------------------ */
+int orc_repulsion(const void* h, const double* z, const double* beta, double theta,
+                  int32_t com_mode, double* R, double* Zi, int64_t* visits) {
+    const otree* t = (const otree*)h;
+    if (!t || !z || !beta || !(theta >= 0.0) || theta >= 1.0) return ORC_EINVAL;
+    const int L = t->L;
+    const double b1 = beta[0], b2 = beta[1], th2 = theta * theta;
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i = 0; i < t->n; i++) {
+        const double zx = z[2 * i], zy = z[2 * i + 1];
+        const int32_t own = t->leaf_of[i];
+        double rx = 0.0, ry = 0.0, zsum = 0.0;
+        int64_t nv = 0;
+        int32_t stack[4 * 20];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            const int32_t c = stack[--sp];
+            const onode* nd = &t->nodes[c];
+            nv++;
+            const double w = (double)(1u << (L - nd->level));
+            double m = (double)nd->count, cx, cy;
+            if (com_mode == 1) {
+                uint32_t x0 = 0, y0 = 0;
+                for (int b = 0; b < nd->level; b++) {
+                    x0 |= ((nd->prefix >> (2 * b)) & 1u) << b;
+                    y0 |= ((nd->prefix >> (2 * b + 1)) & 1u) << b;
+                }
+                cx = (double)x0 * w + 0.5 * w;
+                cy = (double)y0 * w + 0.5 * w;
+            } else {
+                cx = cs_get(&nd->sx) / m;
+                cy = cs_get(&nd->sy) / m;
+            }
+            int use;
+            if (nd->level == L) {
+                use = 1;
+                if (c == own) {
+                    m -= 1.0;
+                    if (m <= 0.0) continue;
+                    if (com_mode != 1) {
+                        cx = (cs_get(&nd->sx) - zx) / m;
+                        cy = (cs_get(&nd->sy) - zy) / m;
+                    }
+                }
+            } else {
+                double dx = zx - cx, dy = zy - cy;
+                double d2 = b1 * dx * dx + b2 * dy * dy;
+                double diag2 = w * w * (b1 + b2);
+                use = diag2 < th2 * d2;
+            }
+            if (use) {
+                double dx = zx - cx, dy = zy - cy;
+                double d2 = b1 * dx * dx + b2 * dy * dy;
+                double q = 1.0 / (1.0 + d2);
+                zsum += m * q;
+                rx += m * q * q * dx;
+                ry += m * q * q * dy;
+            } else {
+                for (int ch = 3; ch >= 0; ch--)
+                    if (nd->child[ch] >= 0) stack[sp++] = nd->child[ch];
+            }
+        }
+        R[2 * i] = rx; R[2 * i + 1] = ry;
+        Zi[i] = zsum;
+        if (visits) visits[i] = nv;
+    }
+    return ORC_OK;
+}
+
+/* Z = sum_i Z_i, compensated, in index order */
+double orc_sum(const double* v, int64_t n) {
+    csum a = {0, 0};
+    for (int64_t i = 0; i < n; i++) cs_add(&a, v[i]);
+    return cs_get(&a);
+}
+
+/* ------------------------------------------------------------------ */
+/* Attraction (Eq. 5 first term over the sparse P of Section 2.3):      */
+/* A_i = sum_{j in row i} p_ij w_ij (z_i - z_j), w from Eq. 12.         */
+/* ------------------------------------------------------------------ */
+int orc_attraction(const double* z, int64_t n, const double* beta, const int64_t* row_ptr,
+                   const int32_t* col, const double* val, double* A) {
+    if (!z || !beta || !row_ptr || !col || !val || !A) return ORC_EINVAL;
+    const double b1 = beta[0], b2 = beta[1];
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; i++) {
+        double ax = 0.0, ay = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            int32_t j = col[e];
+            double dx = z[2 * i] - z[2 * (int64_t)j], dy = z[2 * i + 1] - z[2 * (int64_t)j + 1];
+            double q = 1.0 / (1.0 + b1 * dx * dx + b2 * dy * dy);
+            ax += val[e] * q * dx;
+            ay += val[e] * q * dy;
+        }
+        A[2 * i] = ax; A[2 * i + 1] = ay;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Screen-driven scaling (Section 3.2): per axis                        */
+/*   gamma_d = max_i zh_d - min_i zh_d + eps,                            */
+/*   z_d = r (zh_d - min_i zh_d) / gamma_d.                              */
+/* Writes z, gamma[2], zmin[2].                                          */
+/* ------------------------------------------------------------------ */
+int orc_normalize(const double* zh, int64_t n, int32_t r, double eps, double* z,
+                  double* gamma, double* zmin) {
+    if (!zh || !z || n < 1) return ORC_EINVAL;
+    for (int d = 0; d < 2; d++) {
+        double lo = zh[d], hi = zh[d];
+        for (int64_t i = 1; i < n; i++) {
+            double v = zh[2 * i + d];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        double g = hi - lo + eps;
+        for (int64_t i = 0; i < n; i++) z[2 * i + d] = (double)r * (zh[2 * i + d] - lo) / g;
+        if (gamma) gamma[d] = g;
+        if (zmin) zmin[d] = lo;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gradient in the pixel frame.  With y = s * z (per axis) and          */
+/* beta_d = s_d^2, Eq. 5 becomes dC/dy_i,d = 4 s_d B_i,d with            */
+/*   B_i = alpha * A_i - R_i / Z,                                        */
+/* alpha the early-exaggeration factor on P.                            */
+/* Outputs B (and optionally A, R, Z_i, visits, Z).                      */
+/* ------------------------------------------------------------------ */
+int orc_gradient(const double* z, int64_t n, int32_t r, const double* s, double theta,
+                 int32_t com_mode, double alpha, const int64_t* row_ptr, const int32_t* col,
+                 const double* val, double* B, double* A_out, double* R_out, double* Zi_out,
+                 int64_t* visits, double* Z_out) {
+    double beta[2] = {s[0] * s[0], s[1] * s[1]};
+    void* h = orc_tree_build(z, n, r);
+    if (!h) return ORC_ENOMEM;
+    double* A = A_out ? A_out : (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* R = R_out ? R_out : (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* Zi = Zi_out ? Zi_out : (double*)malloc(sizeof(double) * (size_t)n);
+    int rc = ORC_ENOMEM;
+    if (A && R && Zi) {
+        rc = orc_repulsion(h, z, beta, theta, com_mode, R, Zi, visits);
+        if (rc == ORC_OK) rc = orc_attraction(z, n, beta, row_ptr, col, val, A);
+        if (rc == ORC_OK) {
+            double Z = orc_sum(Zi, n);
+            if (Z_out) *Z_out = Z;
+            for (int64_t i = 0; i < 2 * n; i++) B[i] = alpha * A[i] - R[i] / Z;
+        }
+    }
+    if (!A_out) free(A);
+    if (!R_out) free(R);
+    if (!Zi_out) free(Zi);
+    orc_tree_free(h);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Optimisation loop.  Per iteration t (0-based):                        */
+/*   B from the current z (above);                                      */
+/*   gains: g += 0.2 where sign(B) != sign(u), else g *= 0.8; g >= gmin; */
+/*   u = mu_t u - eta g B;  zh = z + u;                                  */
+/*   screen scaling of zh -> z, s *= gamma / r, u *= r / gamma.          */
+/* The pixel-frame step equals a y-frame step on dC/dy / 4 because     */
+/* y = s z and the gradient carries the factor s (Eq. 12-13).           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t r;
+    double theta;
+    int32_t com_mode;
+    double eta, mom0, mom1;
+    int32_t mom_switch;
+    double exaggeration;
+    int32_t exag_iters;
+    double min_gain, eps;
+} orc_params;
+
+static inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+int orc_iterate(const orc_params* p, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                const double* val, double* z, double* u, double* g, double* s, int32_t t0,
+                int32_t n_iter, double* Z_hist) {
+    if (!p || !z || !u || !g || !s) return ORC_EINVAL;
+    double* B = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    double* zh = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!B || !zh) { free(B); free(zh); return ORC_ENOMEM; }
+    int rc = ORC_OK;
+    for (int32_t it = 0; it < n_iter; it++) {
+        int32_t t = t0 + it;
+        double alpha = t < p->exag_iters ? p->exaggeration : 1.0;
+        double mu = t < p->mom_switch ? p->mom0 : p->mom1;
+        double Z;
+        rc = orc_gradient(z, n, p->r, s, p->theta, p->com_mode, alpha, row_ptr, col, val, B,
+                          NULL, NULL, NULL, NULL, &Z);
+        if (rc != ORC_OK) break;
+        if (Z_hist) Z_hist[it] = Z;
+        for (int64_t e = 0; e < 2 * n; e++) {
+            double gn = (sgn(B[e]) != sgn(u[e])) ? g[e] + 0.2 : g[e] * 0.8;
+            if (gn < p->min_gain) gn = p->min_gain;
+            g[e] = gn;
+            u[e] = mu * u[e] - p->eta * gn * B[e];
+            zh[e] = z[e] + u[e];
+        }
+        double gamma[2], zmin[2];
+        orc_normalize(zh, n, p->r, p->eps, z, gamma, zmin);
+        for (int d = 0; d < 2; d++) {
+            s[d] *= gamma[d] / (double)p->r;
+            for (int64_t i = 0; i < n; i++) u[2 * i + d] *= (double)p->r / gamma[d];
+        }
+    }
+    free(B); free(zh);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* KL objective (Eq. 4) with q from Eq. 12 and the exact normaliser:    */
+/*   C = sum_nnz p ln p - sum_nnz p ln w_ij + ln Z,  Z = sum_{i!=j} w_ij */
+/* over all ordered pairs (O(n^2)).  P must sum to 1.                    */
+/* ------------------------------------------------------------------ */
+double orc_kl(const double* z, int64_t n, const double* s, const int64_t* row_ptr,
+              const int32_t* col, const double* val) {
+    const double b1 = s[0] * s[0], b2 = s[1] * s[1];
+    double* zrow = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!zrow) return NAN;
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < n; i++) {
+        csum a = {0, 0};
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = z[2 * i] - z[2 * j], dy = z[2 * i + 1] - z[2 * j + 1];
+            cs_add(&a, 1.0 / (1.0 + b1 * dx * dx + b2 * dy * dy));
+        }
+        zrow[i] = cs_get(&a);
+    }
+    double Z = orc_sum(zrow, n);
+    csum c = {0, 0};
+    for (i = 0; i < n; i++)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            int32_t j = col[e];
+            double p = val[e];
+            if (p <= 0.0) continue;
+            double dx = z[2 * i] - z[2 * (int64_t)j], dy = z[2 * i + 1] - z[2 * (int64_t)j + 1];
+            double w = 1.0 / (1.0 + b1 * dx * dx + b2 * dy * dy);
+            cs_add(&c, p * log(p) - p * log(w));
+        }
+    free(zrow);
+    return cs_get(&c) + log(Z);
+}

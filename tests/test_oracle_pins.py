@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, the textbook exact t-SNE (an independent NumPy implementation), finite
+differences of the objective, invariants, library routines, and pure-Python
+brute force on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact_tsne as ex
+from paper_1611_02568_amd import datagen
+
+
+def _distinct_pixel_positions(n, r, seed, centre=False):
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(r * r, size=n, replace=False)
+    px = np.stack([flat % r, flat // r], 1).astype(np.float64)
+    if centre:
+        return px + 0.5
+    return px + rng.uniform(0.0, 1.0, (n, 2)) * (1 - 1e-9)
+
+
+def _dense_P(orc, n, D, u, seed):
+    X, _ = datagen.small_mixture(n=n, D=D, K=3, seed=seed)
+    idx, d2 = orc.knn(X, n - 1)
+    Pc, _, _ = orc.perplexity(d2, u)
+    return orc.symmetrize(idx, Pc, n)
+
+
+# --------------------------------------------------------------------------
+# V1: two points -- KL = 0 and zero gradient in closed form
+# --------------------------------------------------------------------------
+def test_two_points_closed_form(orc):
+    X = np.array([[0.0, 0.0], [3.0, 4.0]])
+    idx, d2 = orc.knn(X, 1)
+    assert idx.ravel().tolist() == [1, 0] and d2.ravel().tolist() == [25.0, 25.0]
+    Pc, _, _ = orc.perplexity(d2, 1.0)
+    P = orc.symmetrize(idx, Pc, 2)
+    assert P[2].tolist() == [0.5, 0.5]
+    z = np.array([[10.3, 200.7], [400.2, 31.9]])
+    s = np.array([0.01, 0.02])
+    g = orc.gradient(z, 512, s, P, theta=0.5)
+    w = 1.0 / (1.0 + np.sum(((z[0] - z[1]) * s) ** 2))
+    assert abs(g["Z"] - 2 * w) <= 1e-15 * 2 * w
+    assert np.max(np.abs(g["B"])) <= 1e-15 * np.max(np.abs(g["A"]))
+    assert abs(orc.kl(z, s, P)) <= 1e-15
+
+
+# --------------------------------------------------------------------------
+# V2: theta = 0 with one point per pixel reduces to exact t-SNE repulsion
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [3, 10, 50, 200])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_theta0_equals_exact_repulsion(orc, n, mode):
+    r = 256
+    z = _distinct_pixel_positions(n, r, seed=100 + n, centre=(mode == 1))
+    s = np.array([0.013, 0.021])
+    beta = s * s
+    tree = orc.Tree(z, r)
+    R, Zi, vis = tree.repulsion(beta, 0.0, com_mode=mode)
+    Ry, Z = ex.repulsion(z * s)
+    # y-frame repulsion = s * pixel-frame repulsion (Eq. 12)
+    np.testing.assert_allclose(R * s, Ry, rtol=1e-12, atol=1e-14 * np.abs(Ry).max())
+    assert abs(Zi.sum() - Z) <= 1e-12 * Z
+    # sum of exact pairwise repulsion vanishes (antisymmetry)
+    assert np.all(np.abs(R.sum(0)) <= 1e-10 * np.abs(R).sum(0))
+
+
+# --------------------------------------------------------------------------
+# V3: the gradient is the derivative of the KL objective (finite differences)
+# --------------------------------------------------------------------------
+def test_gradient_matches_kl_finite_differences(orc):
+    n, r = 12, 4096
+    P = _dense_P(orc, n, 5, 4.0, seed=7)
+    z = _distinct_pixel_positions(n, r, seed=8)
+    s = np.array([5.0 / r, 3.0 / r])
+    g = orc.gradient(z, r, s, P, theta=0.0)
+    grad_y = 4.0 * g["B"] * s                      # dC/dy from the pixel-frame bracket
+    Pd = ex.dense_from_csr(P, n)
+    h = 1e-6
+    fd = np.zeros_like(z)
+    fd_np = np.zeros_like(z)
+    for i in range(n):
+        for d in range(2):
+            zp = z.copy(); zp[i, d] += h / s[d]
+            zm = z.copy(); zm[i, d] -= h / s[d]
+            fd[i, d] = (orc.kl(zp, s, P) - orc.kl(zm, s, P)) / (2 * h)
+            fd_np[i, d] = (ex.kl(zp * s, Pd) - ex.kl(zm * s, Pd)) / (2 * h)
+    scale = np.abs(grad_y).max()
+    assert np.max(np.abs(fd - grad_y)) <= 1e-6 * scale
+    assert np.max(np.abs(fd_np - grad_y)) <= 1e-6 * scale
+    # and the textbook analytic gradient agrees to rounding
+    np.testing.assert_allclose(grad_y, ex.gradient(z * s, Pd), rtol=1e-10, atol=1e-13 * scale)
+
+
+# --------------------------------------------------------------------------
+# V4: invariants of P and of the forces
+# --------------------------------------------------------------------------
+def test_P_invariants(orc):
+    X, _ = datagen.small_mixture(n=400, D=20, seed=3)
+    n, u, k = 400, 10.0, 30
+    idx, d2 = orc.knn(X, k)
+    Pc, beta, it = orc.perplexity(d2, u)
+    # row entropy equals ln(u) to the search tolerance
+    H = -np.sum(Pc * np.log(np.where(Pc > 0, Pc, 1.0)), axis=1)
+    assert np.max(np.abs(H - math.log(u))) < 1e-5
+    np.testing.assert_allclose(Pc.sum(1), 1.0, rtol=1e-14)
+    rp, col, val = orc.symmetrize(idx, Pc, n)
+    Pd = ex.dense_from_csr((rp, col, val), n)
+    assert np.array_equal(Pd, Pd.T)                      # bitwise symmetric
+    assert np.all(np.diag(Pd) == 0)
+    assert abs(val.sum() - 1.0) < 1e-12
+    assert np.all(np.diff(rp) >= k) and np.all(np.diff(rp) <= 2 * k)
+    for i in range(0, n, 37):                            # columns ascending, no duplicates
+        c = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(c) > 0)
+
+
+def test_attraction_sums_to_zero(orc):
+    X, _ = datagen.small_mixture(n=300, D=10, seed=4)
+    P = orc.build_P(X, 10.0)
+    z = datagen.uniform_pixels(300, 512, seed=5)
+    A = orc.attraction(z, np.array([1e-4, 3e-4]), P)
+    assert np.all(np.abs(A.sum(0)) <= 1e-12 * np.abs(A).sum(0))
+
+
+# --------------------------------------------------------------------------
+# V5: tree structure against brute force
+# --------------------------------------------------------------------------
+def _interleave_numpy(px, py, L):
+    key = np.zeros(px.shape, np.uint64)
+    for b in range(L):
+        key |= ((px.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        key |= ((py.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return key
+
+
+@pytest.mark.parametrize("gen", ["uniform", "clustered"])
+def test_tree_against_bruteforce(orc, gen):
+    r, n = 128, 3000
+    L = 7
+    z = (datagen.uniform_pixels(n, r, seed=11) if gen == "uniform"
+         else datagen.clustered_pixels(n, r, seed=12, spread=0.01))
+    px = np.clip(np.floor(z), 0, r - 1).astype(np.int64)
+    key = _interleave_numpy(px[:, 0], px[:, 1], L)
+    assert np.array_equal(orc.morton(z, r).astype(np.uint64), key)
+    ks, perm = orc.sorted_order(z, r)
+    ref_perm = np.lexsort((np.arange(n), key))
+    assert np.array_equal(perm, ref_perm)
+    assert np.array_equal(ks.astype(np.uint64), key[ref_perm])
+    tree = orc.Tree(z, r)
+    assert tree.L == L
+    prev = None
+    for l in range(L + 1):
+        pre, cnt, sm = tree.level(l)
+        w = 2 ** (L - l)
+        cell = key >> np.uint64(2 * (L - l))
+        upre, inv = np.unique(cell, return_inverse=True)
+        assert np.array_equal(pre.astype(np.uint64), upre)
+        assert np.array_equal(cnt, np.bincount(inv))
+        assert cnt.sum() == n
+        ref = np.array([[math.fsum(z[inv == c, 0]), math.fsum(z[inv == c, 1])]
+                        for c in range(upre.size)])
+        np.testing.assert_allclose(sm, ref, rtol=4e-16 * 2, atol=0)
+        # each point lies inside its cell's boundary [b_min, b_max) (Eq. 6-7)
+        cx = np.zeros(n, np.int64); cy = np.zeros(n, np.int64)
+        for b in range(l):
+            cx |= ((cell.astype(np.int64) >> (2 * b)) & 1) << b
+            cy |= ((cell.astype(np.int64) >> (2 * b + 1)) & 1) << b
+        assert np.all((cx * w <= z[:, 0]) & (z[:, 0] < (cx + 1) * w) | (px[:, 0] == r - 1))
+        assert np.all((cy * w <= z[:, 1]) & (z[:, 1] < (cy + 1) * w) | (px[:, 1] == r - 1))
+        if prev is not None:                       # parent count = sum of children counts
+            ppre, pcnt = prev
+            par = np.searchsorted(ppre, (pre >> 2))
+            assert np.array_equal(np.bincount(par, weights=cnt, minlength=ppre.size), pcnt)
+        prev = (pre, cnt)
+
+
+# --------------------------------------------------------------------------
+# Barnes-Hut traversal against a pure-Python brute force (tiny inputs)
+# --------------------------------------------------------------------------
+def _bh_python(z, r, beta, theta, mode):
+    L = int(round(math.log2(r)))
+    n = len(z)
+    px = np.clip(np.floor(z), 0, r - 1).astype(int)
+    b1, b2 = beta
+    R = np.zeros((n, 2)); Zi = np.zeros(n); vis = np.zeros(n, int)
+
+    def visit(i, level, x0, y0):
+        w = 2 ** (L - level)
+        mem = [j for j in range(n) if x0 <= px[j, 0] < x0 + w and y0 <= px[j, 1] < y0 + w]
+        if not mem:
+            return
+        vis[i] += 1
+        if level == L:
+            use = [j for j in mem if j != i]
+            if not use:
+                return
+            m = len(use)
+            c = (np.array([x0 + 0.5, y0 + 0.5]) if mode == 1
+                 else np.array([math.fsum(z[use, 0]), math.fsum(z[use, 1])]) / m)
+        else:
+            m = len(mem)
+            c = (np.array([x0 + w / 2, y0 + w / 2]) if mode == 1
+                 else np.array([math.fsum(z[mem, 0]), math.fsum(z[mem, 1])]) / m)
+            dz = z[i] - c
+            d2 = b1 * dz[0] ** 2 + b2 * dz[1] ** 2
+            if not (w * w * (b1 + b2) < theta * theta * d2):
+                h = w // 2
+                for q in range(4):                   # child 2*ybit + xbit
+                    visit(i, level + 1, x0 + (q & 1) * h, y0 + (q >> 1) * h)
+                return
+        dz = z[i] - c
+        q = 1.0 / (1.0 + b1 * dz[0] ** 2 + b2 * dz[1] ** 2)
+        Zi[i] += m * q
+        R[i] += m * q * q * dz
+
+    for i in range(n):
+        visit(i, 0, 0, 0)
+    return R, Zi, vis
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.9])
+def test_bh_traversal_bruteforce(orc, mode, theta):
+    r, n = 32, 120
+    z = datagen.clustered_pixels(n, r, seed=21, n_clusters=3, spread=0.06)
+    beta = np.array([0.37, 0.22])
+    R, Zi, vis = orc.Tree(z, r).repulsion(beta, theta, com_mode=mode)
+    Rp, Zp, vp = _bh_python(z, r, beta, theta, mode)
+    assert np.array_equal(vis, vp)
+    np.testing.assert_allclose(Zi, Zp, rtol=1e-13)
+    np.testing.assert_allclose(R, Rp, rtol=1e-11, atol=1e-13 * np.abs(Rp).max())
+
+
+def test_bh_error_small_and_monotone(orc):
+    """theta > 0 approximates the theta = 0 result (sanity only: the absolute
+    error level is not fixed by the paper -- parity unpinned)."""
+    r, n = 512, 2000
+    z = datagen.clustered_pixels(n, r, seed=31, n_clusters=6, spread=0.05)
+    beta = np.array([0.02, 0.02]) ** 2
+    tree = orc.Tree(z, r)
+    R0, Z0, v0 = tree.repulsion(beta, 0.0)
+    errs = []
+    for th in (0.2, 0.5, 0.8):
+        R, Z, v = tree.repulsion(beta, th)
+        errs.append(np.linalg.norm(R - R0) / np.linalg.norm(R0))
+        assert v.mean() < v0.mean()
+    assert errs[0] < errs[1] < errs[2] < 0.05
+
+
+# --------------------------------------------------------------------------
+# V6: scale compensation (Eq. 12-13) with anisotropic scales
+# --------------------------------------------------------------------------
+def test_scale_compensation(orc):
+    n, r = 40, 1024
+    P = _dense_P(orc, n, 6, 8.0, seed=9)
+    z = _distinct_pixel_positions(n, r, seed=10)
+    s = np.array([0.0071, 0.0123])
+    g = orc.gradient(z, r, s, P, theta=0.0, alpha=3.0)
+    Pd = ex.dense_from_csr(P, n)
+    ref = ex.gradient(z * s, Pd, alpha=3.0) / 4.0
+    np.testing.assert_allclose(g["B"] * s, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
+# V7: the pixel-frame optimiser tracks exact t-SNE in the y frame
+# --------------------------------------------------------------------------
+def test_pixel_frame_optimiser_tracks_exact_tsne(orc):
+    # Rounding differences grow about 3.5x per iteration under early
+    # exaggeration (unstable regime), so the exaggeration phase is kept short.
+    n, r, T = 30, 2 ** 15, 60
+    X, _ = datagen.small_mixture(n=n, D=8, K=3, seed=13)
+    P = orc.build_P(X, 5.0, k=15)
+    Pd = ex.dense_from_csr(P, n)
+    y0 = datagen.initial_embedding(n, seed=14)
+    st = orc.State(y0, r)
+    p = orc.params(r, theta=0.0, exag_iters=8, mom_switch=8)
+    orc.iterate(st, p, P, T)
+    # the oracle's initial frame maps y0 onto the screen; exact t-SNE starts from s*z0
+    z0, g0, _ = orc.normalize(y0, r)
+    Ye = ex.run(z0 * (g0 / r), Pd, T, exag_iters=8, mom_switch=8)
+    Yo = st.y()
+    Yo = Yo - Yo.mean(0)
+    Ye = Ye - Ye.mean(0)
+    assert len({tuple(p) for p in np.floor(st.z).astype(int)}) == n
+    assert np.max(np.abs(Yo - Ye)) <= 1e-9 * np.abs(Ye).max()
+
+
+# --------------------------------------------------------------------------
+# V8: screen-driven scaling keeps 0 <= z < r with min 0 and max pixel r-1
+# --------------------------------------------------------------------------
+def test_normalisation_range(orc):
+    X, _ = datagen.small_mixture(n=500, D=10, seed=15)
+    P = orc.build_P(X, 10.0)
+    st = orc.State(datagen.initial_embedding(500, seed=16), 512)
+    p = orc.params(512)
+    for _ in range(5):
+        orc.iterate(st, p, P, 3)
+        assert np.all(st.z.min(0) == 0.0)
+        assert np.all(st.z < 512)
+        assert np.all(np.floor(st.z.max(0)) == 511)
+
+
+# --------------------------------------------------------------------------
+# V9: brute-force kNN against NumPy sorting
+# --------------------------------------------------------------------------
+def test_knn_against_numpy(orc):
+    rng = np.random.default_rng(17)
+    X = rng.integers(0, 4, (300, 6)).astype(np.float64)     # many exact ties
+    k = 20
+    idx, d2 = orc.knn(X, k)
+    D = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    for i in range(300):
+        d = D[i].copy(); d[i] = np.inf
+        order = np.lexsort((np.arange(300), d))[:k]
+        assert np.array_equal(idx[i], order)
+        assert np.array_equal(d2[i], d[order])
+    rows = np.array([5, 0, 299])
+    idx2, d22 = orc.knn(X, k, rows=rows)
+    assert np.array_equal(idx2, idx[rows]) and np.array_equal(d22, d2[rows])
+
+
+def test_perplexity_against_root_finder(orc):
+    from scipy.optimize import brentq
+    from scipy.special import entr
+    X, _ = datagen.small_mixture(n=200, D=10, seed=18)
+    idx, d2 = orc.knn(X, 60)
+    P, beta, it = orc.perplexity(d2, 20.0)
+    for i in range(0, 200, 23):
+        d = d2[i] - d2[i].min()
+
+        def H(b):
+            e = np.exp(-b * d)
+            p = e / e.sum()
+            return np.sum(entr(p)) - math.log(20.0)
+        b = brentq(H, 1e-8, 1e3, xtol=1e-14)
+        assert abs(beta[i] - b) <= 1e-3 * b
+        e = np.exp(-beta[i] * d)
+        np.testing.assert_allclose(P[i], e / e.sum(), rtol=1e-12)
+
+
+def test_symmetrize_against_dense(orc):
+    X, _ = datagen.small_mixture(n=150, D=8, seed=19)
+    idx, d2 = orc.knn(X, 12)
+    Pc, _, _ = orc.perplexity(d2, 4.0)
+    P = orc.symmetrize(idx, Pc, 150)
+    C = np.zeros((150, 150))
+    for i in range(150):
+        C[i, idx[i]] = Pc[i]
+    ref = (C + C.T) / 300.0
+    assert np.array_equal(ex.dense_from_csr(P, 150), ref)
+
+
+def test_kl_against_numpy(orc):
+    X, _ = datagen.small_mixture(n=120, D=8, seed=20)
+    P = orc.build_P(X, 6.0)
+    z = datagen.uniform_pixels(120, 256, seed=22)
+    s = np.array([0.03, 0.05])
+    ref = ex.kl(z * s, ex.dense_from_csr(P, 120))
+    assert abs(orc.kl(z, s, P) - ref) <= 1e-12 * abs(ref)
