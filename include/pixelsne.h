@@ -1,0 +1,224 @@
+/*
+ * pixelsne.h -- C ABI of the MI355X (gfx950) PixelSNE library.
+ *
+ * PixelSNE (Kim et al., arXiv:1611.02568) is Barnes-Hut t-SNE whose quadtree
+ * is aligned to the pixels of the output screen (Section 3.1): positions are
+ * kept in the pixel frame z with 0 <= z < r (Eq. 1-2), the tree has a fixed
+ * depth L = log2 r with unit-pixel leaves, and after every gradient step the
+ * positions are rescaled to fill the screen (Section 3.2) while a per-axis
+ * scale factor keeps q identical to the unscaled embedding (Eq. 12-13).
+ *
+ * Conventions for every function below
+ *   - Pointers documented as "device" must point to device memory of the
+ *     current HIP device (hipMalloc or a torch CUDA tensor); "host" pointers to
+ *     ordinary host memory.  All arrays are dense, row-major, C-contiguous.
+ *   - The library never retains caller pointers beyond the call.
+ *   - Work is enqueued on the context's stream (params.stream, or the null
+ *     stream).  Functions that return values on the host synchronise that
+ *     stream; the others are asynchronous unless stated.
+ *   - Functions return a psne_status (0 = success) and never abort.  The
+ *     init functions return NULL on failure.  pixelsne_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - Arguments are validated on the host before any device work.
+ *   - A context must be used from one host thread at a time.
+ *
+ * Precision paths (params.precision)
+ *   PSNE_FP32: positions, velocities, gains, P values and the force
+ *              arithmetic are FP32; the Z normaliser, the centre-of-mass sums
+ *              and the Barnes-Hut opening test are FP64.
+ *   PSNE_FP64: everything FP64 (the paper keeps z in double, Section 3.1).
+ */
+#ifndef PIXELSNE_H
+#define PIXELSNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pixelsne_ctx pixelsne_ctx;
+
+typedef enum {
+    PSNE_OK = 0,
+    PSNE_E_INVAL = -1,        /* bad argument (nothing was enqueued) */
+    PSNE_E_NOMEM = -2,        /* device allocation failed */
+    PSNE_E_DEVICE = -3,       /* HIP runtime error; the context is unusable */
+    PSNE_E_NUMERIC = -4,      /* a non-finite value appeared */
+    PSNE_E_STATE = -5,        /* context unusable after an earlier device error */
+    PSNE_E_UNSUPPORTED = -6   /* valid request outside what this build supports */
+} psne_status;
+
+enum { PSNE_FP32 = 0, PSNE_FP64 = 1 };
+/* Representative point of a cell: centre of mass of its members (Eq. 8), or
+ * the geometric centre of the cell (Section 3.1, iteration-independent). */
+enum { PSNE_COM_MASS = 0, PSNE_COM_CELL_CENTER = 1 };
+/* Element type of the input matrix X. */
+enum { PSNE_X_F32 = 0, PSNE_X_F64 = 1, PSNE_X_U8 = 2 };
+/* Output frames of pixelsne_get_Y. */
+enum {
+    PSNE_FRAME_PIXEL = 0,   /* z, 0 <= z < r, float64 [n][2]            (Eq. 1-2) */
+    PSNE_FRAME_SCREEN = 1,  /* clamp(floor(z), 0, r-1), int32 [n][2]     (Eq. 1)   */
+    PSNE_FRAME_Y = 2        /* y = s * z per axis, float64 [n][2]        (Eq. 12)  */
+};
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(pixelsne_params); set by pixelsne_default_params */
+    int32_t k;                /* neighbours per row; 0 => floor(3 * perplexity) */
+    double theta;             /* opening threshold of Eq. 11, 0 <= theta <= 0.99 [0.5] */
+    int32_t exag_iters;       /* iterations with exaggerated P [250] */
+    double exaggeration;      /* factor on P during those iterations [12] */
+    double eta;               /* step size [200] */
+    double mom0, mom1;        /* momentum before / after mom_switch [0.5, 0.8] */
+    int32_t mom_switch;       /* [250] */
+    double min_gain;          /* gain floor [0.01] */
+    double eps;               /* screen-scaling epsilon of Section 3.2 [1e-6] */
+    double init_sigma;        /* std of the generated initial embedding [1e-4] */
+    uint64_t seed;            /* seed of the generated initial embedding [0] */
+    int32_t precision;        /* PSNE_FP32 | PSNE_FP64 [PSNE_FP32] */
+    int32_t com_mode;         /* PSNE_COM_MASS | PSNE_COM_CELL_CENTER [MASS] */
+    int32_t x_dtype;          /* element type of X for pixelsne_init_ex [F32] */
+    const double* Y_init;     /* optional device float64 [n][2] initial embedding
+                                 (y frame); NULL => N(0, init_sigma^2) from seed */
+    void* stream;             /* hipStream_t for all work; NULL => null stream */
+} pixelsne_params;
+
+/* Fill *p with the defaults shown in brackets above. */
+void pixelsne_default_params(pixelsne_params* p);
+
+/*
+ * Create a context: brute-force kNN of the rows of X (k = floor(3u) nearest by
+ * squared Euclidean distance, self excluded, ties to the smaller index),
+ * per-row Gaussian calibration to perplexity u (Section 2.2), the symmetric
+ * sparse P = (P_cond + P_cond^T) / 2n in CSR (Section 2.3), an initial
+ * embedding and its first screen scaling (Section 3.2).
+ *   X          device, [n][D], float32 (pixelsne_init) or params.x_dtype
+ *   n          number of points, 2 <= n < 2^31, k <= n - 1
+ *   D          input dimension >= 1
+ *   perplexity u > 0
+ *   screen_w/h square power of two, 2 <= r <= 65536 (else PSNE_E_UNSUPPORTED)
+ * X is read during the call only.  Returns NULL on failure.
+ */
+pixelsne_ctx* pixelsne_init(const float* X, int64_t n, int32_t D, double perplexity,
+                            int32_t screen_w, int32_t screen_h);
+pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
+                               int32_t screen_w, int32_t screen_h, const pixelsne_params* p);
+
+/*
+ * Create a context from a caller-built P instead of X (Section 2.3 CSR):
+ *   row_ptr device int64 [n+1], col device int32 [nnz] (each row ascending,
+ *   no diagonal), val device float64 [nnz] (sums to 1).  Copied into the
+ *   context.  The initial embedding comes from params as for pixelsne_init_ex.
+ */
+pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                   const int32_t* col, const double* val, int32_t screen_w,
+                                   int32_t screen_h, const pixelsne_params* p);
+
+/*
+ * Run n_iter >= 0 optimisation iterations.  Each iteration: snap to pixels and
+ * Morton keys (Eq. 1-2), sort, build the P-Quadtree (Section 3.1), Barnes-Hut
+ * repulsion and Z (Eq. 5, 11, 12), sparse attraction (Eq. 5), gains/momentum
+ * step, screen-driven scaling (Section 3.2).  Enqueues the work and then
+ * synchronises once to check for non-finite values (PSNE_E_NUMERIC).
+ */
+psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter);
+
+/* Enqueue the iterations without the final check (returns after enqueueing). */
+psne_status pixelsne_step_async(pixelsne_ctx* c, int32_t n_iter);
+
+/* Write the current embedding to device memory `out` in the given frame
+ * (types per PSNE_FRAME_*; [n][2], caller-owned).  Asynchronous. */
+psne_status pixelsne_get_Y(const pixelsne_ctx* c, void* out, int32_t frame);
+
+void pixelsne_destroy(pixelsne_ctx* c);
+const char* pixelsne_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Introspection, state and parity hooks                                   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t n, nnz, n_nodes;  /* points, nonzeros of P, occupied cells (last tree) */
+    int32_t r, L, k;          /* screen side, tree depth, neighbours per row */
+    int32_t precision, com_mode;
+    int32_t iteration;        /* iterations done */
+    double s[2];              /* y units per pixel, per axis (beta_d = s_d^2, Eq. 13) */
+    double Z;                 /* last Barnes-Hut normaliser */
+    int64_t level_size[17];   /* occupied cells per level 0..L of the last tree */
+} pixelsne_stats;
+
+/* Synchronises the stream. */
+psne_status pixelsne_get_stats(const pixelsne_ctx* c, pixelsne_stats* out);
+
+/*
+ * Replace the optimiser state.  z, u, g: device [n][2] of the state type
+ * (float32 for PSNE_FP32, float64 for PSNE_FP64), z in the pixel frame
+ * (0 <= z < r), u the velocity in that frame, g the gains; u or g NULL =>
+ * zeros / ones.  s: host double[2].  Asynchronous copies.
+ */
+psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g,
+                               const double* s, int32_t iteration);
+/* Read the state in the same layout (pending screen scaling applied). */
+psne_status pixelsne_get_state(const pixelsne_ctx* c, void* z, void* u, void* g, double* s,
+                               int32_t* iteration);
+
+/*
+ * Evaluate the pixel-frame gradient at the current state without stepping:
+ *   B = alpha * A - R / Z  with A_i = sum_j p_ij w_ij (z_i - z_j),
+ *   R_i = Barnes-Hut sum of m w^2 (z_i - c), Z = sum_i Z_i   (Eq. 5, 11, 12),
+ * so that dC/dy_i,d = 4 s_d B_i,d.  Outputs are device arrays of the state type
+ * ([n][2] for B, A, R) and may be NULL; Zi device float64 [n]; visits device
+ * uint32 [n] (cells reached by each point's traversal); Z host double.
+ * Also leaves the tree of the current state for pixelsne_export_tree.
+ * Synchronises the stream.
+ */
+psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, void* R,
+                              double* Zi, uint32_t* visits, double* Z);
+
+/*
+ * Export the tree built by the last pixelsne_gradient / iteration.
+ *   level_size host int64 [L+1] (always written)
+ *   keys   device uint32 [n]   Morton keys in sorted order
+ *   perm   device uint32 [n]   point index at each sorted position
+ *   prefix device uint32 [n_nodes], count device uint32 [n_nodes],
+ *   sum    device float64 [n_nodes][2]: cells of level 0, then 1, ..., L, each
+ *          level ascending by Morton prefix (key >> 2(L - level)).
+ * Pass NULL device pointers to query level_size only.  Synchronises.
+ */
+psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uint32_t* keys,
+                                 uint32_t* perm, uint32_t* prefix, uint32_t* count,
+                                 double* sum);
+
+/* Export P: *nnz (host) always; row_ptr int64 [n+1], col int32 [nnz],
+ * val float64 [nnz] device pointers may be NULL.  Synchronises. */
+psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_ptr,
+                              int32_t* col, double* val);
+
+/* ---------------------------------------------------------------------- */
+/* Setup stages as standalone calls (all device pointers, stream-ordered)  */
+/* ---------------------------------------------------------------------- */
+/*
+ * Brute-force k nearest neighbours of every row of X among all rows
+ * (squared Euclidean, self excluded, ties to the smaller index).
+ *   X device [n][D] of x_dtype; idx device int32 [n][k], d2 device float64
+ *   [n][k] ascending (exact distances recomputed in FP64).  Requires
+ *   1 <= k <= min(n - 1, 256).  Synchronises (returns after completion).
+ */
+psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
+                         int32_t* idx, double* d2, void* stream);
+
+/*
+ * Per-row Gaussian calibration (Section 2.2): for each row find b_i with
+ * entropy of p_{j|i} = exp(-b_i (d2_ij - min_j d2_ij)) / sum equal to ln(u)
+ * (|H - ln u| < 1e-5, at most 200 evaluations, start b = 1, double/halve
+ * until bracketed, then bisect).
+ *   d2 device float64 [n][k]; P device float64 [n][k]; beta device float64 [n]
+ *   (may be NULL).  Asynchronous.
+ */
+psne_status pixelsne_perplexity(const double* d2, int64_t n, int32_t k, double perplexity,
+                                double* P, double* beta, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIXELSNE_H */

@@ -63,6 +63,10 @@ def _load():
     lib.orc_tree_level.argtypes = [vp, C.c_int32, _u32p, _i64p, _dp]
     lib.orc_sorted_order.argtypes = [_dp, C.c_int64, C.c_int32, _u32p, _i64p]
     lib.orc_repulsion.argtypes = [vp, _dp, _dp, C.c_double, C.c_int32, _dp, _dp, _i64p]
+    lib.orc_repulsion_rows.argtypes = [vp, _dp, _dp, C.c_double, C.c_int32, vp, C.c_int64,
+                                       _dp, _dp, _i64p]
+    lib.orc_attraction_rows.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp, vp, C.c_int64,
+                                        _dp]
     lib.orc_sum.restype = C.c_double
     lib.orc_sum.argtypes = [_dp, C.c_int64]
     lib.orc_attraction.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp, _dp]
@@ -212,14 +216,18 @@ class Tree:
         _check(self._lib.orc_tree_level(self.h, l, pre, cnt, sm), "tree level")
         return pre, cnt, sm
 
-    def repulsion(self, beta, theta: float, com_mode: int = 0):
-        """(R [n,2], Z_i [n], visits [n]) for every point."""
-        n = self.z.shape[0]
-        R = np.empty((n, 2), np.float64)
-        Zi = np.empty(n, np.float64)
-        vis = np.empty(n, np.int64)
-        _check(self._lib.orc_repulsion(self.h, self.z, _f64(beta), float(theta), int(com_mode),
-                                       R, Zi, vis), "repulsion")
+    def repulsion(self, beta, theta: float, com_mode: int = 0, rows=None):
+        """(R, Z_i, visits) for every point, or for the points in rows."""
+        if rows is None:
+            m, rp = self.z.shape[0], None
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            m, rp = rows.size, rows.ctypes.data
+        R = np.empty((m, 2), np.float64)
+        Zi = np.empty(m, np.float64)
+        vis = np.empty(m, np.int64)
+        _check(self._lib.orc_repulsion_rows(self.h, self.z, _f64(beta), float(theta),
+                                            int(com_mode), rp, m, R, Zi, vis), "repulsion")
         return R, Zi, vis
 
 
@@ -236,11 +244,18 @@ def _csr(P):
     return (np.ascontiguousarray(rp, np.int64), np.ascontiguousarray(col, np.int32), _f64(val))
 
 
-def attraction(z, beta, P):
+def attraction(z, beta, P, rows=None):
+    """A_i for every point, or for the points in rows."""
     z = _f64(z)
     rp, col, val = _csr(P)
-    A = np.empty_like(z)
-    _check(_load().orc_attraction(z, z.shape[0], _f64(beta), rp, col, val, A), "attraction")
+    if rows is None:
+        m, rptr = z.shape[0], None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        m, rptr = rows.size, rows.ctypes.data
+    A = np.empty((m, 2), np.float64)
+    _check(_load().orc_attraction_rows(z, z.shape[0], _f64(beta), rp, col, val, rptr, m, A),
+           "attraction")
     return A
 
 

@@ -438,15 +438,20 @@ int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted
 /* (Section 3.1 "simply approximate the center of mass").               */
 /* visits counts every cell reached by the traversal.                    */
 /* ------------------------------------------------------------------ */
-int orc_repulsion(const void* h, const double* z, const double* beta, double theta,
-                  int32_t com_mode, double* R, double* Zi, int64_t* visits) {
+/* rows == NULL: every point, outputs indexed by point; otherwise outputs are
+ * indexed by position in rows[0..nrows). */
+int orc_repulsion_rows(const void* h, const double* z, const double* beta, double theta,
+                       int32_t com_mode, const int64_t* rows, int64_t nrows, double* R,
+                       double* Zi, int64_t* visits) {
     const otree* t = (const otree*)h;
     if (!t || !z || !beta || !(theta >= 0.0) || theta >= 1.0) return ORC_EINVAL;
     const int L = t->L;
     const double b1 = beta[0], b2 = beta[1], th2 = theta * theta;
-    int64_t i;
+    if (!rows) nrows = t->n;
+    int64_t q;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (i = 0; i < t->n; i++) {
+    for (q = 0; q < nrows; q++) {
+        const int64_t i = rows ? rows[q] : q;
         const double zx = z[2 * i], zy = z[2 * i + 1];
         const int32_t own = t->leaf_of[i];
         double rx = 0.0, ry = 0.0, zsum = 0.0;
@@ -501,11 +506,16 @@ int orc_repulsion(const void* h, const double* z, const double* beta, double the
                     if (nd->child[ch] >= 0) stack[sp++] = nd->child[ch];
             }
         }
-        R[2 * i] = rx; R[2 * i + 1] = ry;
-        Zi[i] = zsum;
-        if (visits) visits[i] = nv;
+        R[2 * q] = rx; R[2 * q + 1] = ry;
+        Zi[q] = zsum;
+        if (visits) visits[q] = nv;
     }
     return ORC_OK;
+}
+
+int orc_repulsion(const void* h, const double* z, const double* beta, double theta,
+                  int32_t com_mode, double* R, double* Zi, int64_t* visits) {
+    return orc_repulsion_rows(h, z, beta, theta, com_mode, NULL, 0, R, Zi, visits);
 }
 
 /* Z = sum_i Z_i, compensated, in index order */
@@ -519,13 +529,16 @@ double orc_sum(const double* v, int64_t n) {
 /* Attraction (Eq. 5 first term over the sparse P of Section 2.3):      */
 /* A_i = sum_{j in row i} p_ij w_ij (z_i - z_j), w from Eq. 12.         */
 /* ------------------------------------------------------------------ */
-int orc_attraction(const double* z, int64_t n, const double* beta, const int64_t* row_ptr,
-                   const int32_t* col, const double* val, double* A) {
+int orc_attraction_rows(const double* z, int64_t n, const double* beta, const int64_t* row_ptr,
+                        const int32_t* col, const double* val, const int64_t* rows,
+                        int64_t nrows, double* A) {
     if (!z || !beta || !row_ptr || !col || !val || !A) return ORC_EINVAL;
     const double b1 = beta[0], b2 = beta[1];
-    int64_t i;
+    if (!rows) nrows = n;
+    int64_t q;
 #pragma omp parallel for schedule(static)
-    for (i = 0; i < n; i++) {
+    for (q = 0; q < nrows; q++) {
+        const int64_t i = rows ? rows[q] : q;
         double ax = 0.0, ay = 0.0;
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
             int32_t j = col[e];
@@ -534,9 +547,14 @@ int orc_attraction(const double* z, int64_t n, const double* beta, const int64_t
             ax += val[e] * q * dx;
             ay += val[e] * q * dy;
         }
-        A[2 * i] = ax; A[2 * i + 1] = ay;
+        A[2 * q] = ax; A[2 * q + 1] = ay;
     }
     return ORC_OK;
+}
+
+int orc_attraction(const double* z, int64_t n, const double* beta, const int64_t* row_ptr,
+                   const int32_t* col, const double* val, double* A) {
+    return orc_attraction_rows(z, n, beta, row_ptr, col, val, NULL, 0, A);
 }
 
 /* ------------------------------------------------------------------ */

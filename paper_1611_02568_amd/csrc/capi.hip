@@ -1,0 +1,482 @@
+// C ABI of the gfx950 PixelSNE library (declared in include/pixelsne.h).
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+namespace psne {
+
+int64_t attract_block_count(int64_t n);
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+psne_status device_error(pixelsne_ctx* c, hipError_t e, const char* where) {
+    if (c) c->poisoned = true;
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? PSNE_E_NOMEM : PSNE_E_DEVICE;
+}
+
+namespace {
+
+psne_status invalid(const std::string& m) {
+    set_error(m);
+    return PSNE_E_INVAL;
+}
+
+int log2_pow2(int32_t r) {
+    if (r < 2 || (r & (r - 1))) return -1;
+    int L = 0;
+    while ((1 << L) < r) L++;
+    return L;
+}
+
+psne_status check_params(const pixelsne_params* p) {
+    if (p->struct_size != sizeof(pixelsne_params))
+        return invalid("pixelsne_params.struct_size does not match this library");
+    if (!(p->theta >= 0.0 && p->theta <= 0.99)) return invalid("theta must be in [0, 0.99]");
+    if (!(p->eta > 0.0) || !(p->exaggeration > 0.0)) return invalid("eta and exaggeration must be > 0");
+    if (!(p->min_gain >= 0.0) || !(p->eps > 0.0)) return invalid("min_gain >= 0 and eps > 0 required");
+    if (p->precision != PSNE_FP32 && p->precision != PSNE_FP64) return invalid("unknown precision");
+    if (p->com_mode != PSNE_COM_MASS && p->com_mode != PSNE_COM_CELL_CENTER)
+        return invalid("unknown com_mode");
+    if (p->x_dtype != PSNE_X_F32 && p->x_dtype != PSNE_X_F64 && p->x_dtype != PSNE_X_U8)
+        return invalid("unknown x_dtype");
+    if (p->exag_iters < 0 || p->mom_switch < 0) return invalid("negative schedule length");
+    return PSNE_OK;
+}
+
+psne_status check_screen(int32_t w, int32_t h, int* L) {
+    if (w < 2 || h < 2 || w > 65536 || h > 65536) return invalid("screen size must be in [2, 65536]");
+    if (w != h) {
+        set_error("only square screens are supported");
+        return PSNE_E_UNSUPPORTED;
+    }
+    *L = log2_pow2(w);
+    if (*L < 0) {
+        set_error("screen size must be a power of two");
+        return PSNE_E_UNSUPPORTED;
+    }
+    return PSNE_OK;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+template <typename P>
+hipError_t dalloc(pixelsne_ctx* c, P** out, size_t bytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+    if (e != hipSuccess) return e;
+    c->allocs.push_back(p);
+    *out = (P*)p;
+    return hipSuccess;
+}
+
+size_t state_bytes(const pixelsne_ctx* c) { return c->prm.precision == PSNE_FP64 ? 8 : 4; }
+
+hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
+    const int64_t n = c->n;
+    const size_t v2 = (size_t)n * 2 * state_bytes(c);
+    hipError_t e;
+    if ((e = dalloc(c, &c->zh, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->z, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->u, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->g, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->R, v2)) != hipSuccess) return e;
+    c->zpart_n = ceil_div(n, 256);
+    if ((e = dalloc(c, &c->zpart, sizeof(double) * c->zpart_n)) != hipSuccess) return e;
+    c->mm_n = attract_block_count(n);
+    if ((e = dalloc(c, &c->mm_part, sizeof(double) * 4 * c->mm_n)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->sc, sizeof(DevScalars))) != hipSuccess) return e;
+    TreeBufs& tb = c->tb;
+    int64_t mx = 0;
+    for (int l = 0; l <= c->L; l++) {
+        const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : n;
+        mx += cap < n ? cap : n;
+    }
+    tb.max_nodes = mx;
+    if (mx >= (int64_t)1 << 30) {
+        set_error("too many tree cells for this build");
+        return hipErrorNotSupported;
+    }
+    tb.sort_blocks = ceil_div(n, 2048);
+    tb.tree_blocks = ceil_div(n, 256);
+    for (int h = 0; h < 2; h++) {
+        if ((e = dalloc(c, &tb.key[h], 4 * (size_t)n)) != hipSuccess) return e;
+        if ((e = dalloc(c, &tb.idx[h], 4 * (size_t)n)) != hipSuccess) return e;
+    }
+    if ((e = dalloc(c, &tb.hist, 4 * 256 * (size_t)tb.sort_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.lvl_cnt, 4 * (size_t)(c->L + 1) * tb.tree_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.lvl_off, 4 * (size_t)(c->L + 1) * tb.tree_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.parent, 4 * (size_t)mx)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.first_child, 4 * (size_t)mx)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.arrive, 4 * (size_t)mx)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.nodes, sizeof(Node) * (size_t)mx)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.leaf_of, 4 * (size_t)n)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.zs, v2)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void free_ctx(pixelsne_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+}
+
+pixelsne_ctx* new_ctx(int64_t n, int L, int32_t r, const pixelsne_params* p) {
+    pixelsne_ctx* c = new pixelsne_ctx();
+    c->n = n;
+    c->L = L;
+    c->r = r;
+    c->prm = *p;
+    c->stream = (hipStream_t)p->stream;
+    (void)hipGetDevice(&c->device);
+    return c;
+}
+
+// state buffers + initial embedding; P must already be in the context
+psne_status finish_init(pixelsne_ctx* c) {
+    hipError_t e = alloc_iteration_buffers(c);
+    if (e == hipErrorNotSupported) return PSNE_E_UNSUPPORTED;
+    if (e != hipSuccess) return device_error(c, e, "allocation");
+    if (c->prm.Y_init && !is_device_ptr(c->prm.Y_init)) return invalid("Y_init must be a device pointer");
+    e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(c, e, "initial embedding");
+    return PSNE_OK;
+}
+
+}  // namespace
+}  // namespace psne
+
+using namespace psne;
+
+extern "C" {
+
+const char* pixelsne_last_error(void) { return g_err.c_str(); }
+
+void pixelsne_default_params(pixelsne_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(pixelsne_params);
+    p->k = 0;
+    p->theta = 0.5;
+    p->exag_iters = 250;
+    p->exaggeration = 12.0;
+    p->eta = 200.0;
+    p->mom0 = 0.5;
+    p->mom1 = 0.8;
+    p->mom_switch = 250;
+    p->min_gain = 0.01;
+    p->eps = 1e-6;
+    p->init_sigma = 1e-4;
+    p->seed = 0;
+    p->precision = PSNE_FP32;
+    p->com_mode = PSNE_COM_MASS;
+    p->x_dtype = PSNE_X_F32;
+    p->Y_init = nullptr;
+    p->stream = nullptr;
+}
+
+pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
+                               int32_t screen_w, int32_t screen_h, const pixelsne_params* pin) {
+    pixelsne_params p;
+    if (pin) p = *pin;
+    else pixelsne_default_params(&p);
+    if (check_params(&p) != PSNE_OK) return nullptr;
+    if (n < 2 || n >= ((int64_t)1 << 31)) { invalid("n must be in [2, 2^31)"); return nullptr; }
+    if (D < 1) { invalid("D must be >= 1"); return nullptr; }
+    if (!(perplexity > 0.0) || !isfinite(perplexity)) { invalid("perplexity must be > 0"); return nullptr; }
+    const int64_t k = p.k > 0 ? p.k : (int64_t)floor(3.0 * perplexity);
+    if (k < 1 || k > n - 1) { invalid("k = floor(3 * perplexity) must be in [1, n - 1]"); return nullptr; }
+    if (k > 256) { set_error("k > 256 is not supported"); return nullptr; }
+    int L;
+    if (check_screen(screen_w, screen_h, &L) != PSNE_OK) return nullptr;
+    if (!is_device_ptr(X)) { invalid("X must be a device pointer"); return nullptr; }
+
+    pixelsne_ctx* c = new_ctx(n, L, screen_w, &p);
+    c->k = (int32_t)k;
+    int32_t* idx = nullptr;
+    double *d2 = nullptr, *Pc = nullptr, *val64 = nullptr;
+    auto cleanup = [&]() { hipFree(idx); hipFree(d2); hipFree(Pc); hipFree(val64); };
+    hipError_t e = hipMalloc(&idx, sizeof(int32_t) * n * k);
+    if (e == hipSuccess) e = hipMalloc(&d2, sizeof(double) * n * k);
+    if (e == hipSuccess) e = hipMalloc(&Pc, sizeof(double) * n * k);
+    std::string err;
+    if (e == hipSuccess) e = psne::knn(X, n, D, p.x_dtype, (int32_t)k, idx, d2, c->stream, &err);
+    if (e == hipSuccess) e = psne::perplexity(d2, n, (int32_t)k, perplexity, Pc, nullptr, c->stream);
+    int64_t* rp = nullptr;
+    uint32_t* col = nullptr;
+    if (e == hipSuccess)
+        e = psne::symmetrize(idx, Pc, n, (int32_t)k, &rp, &col, &val64, &c->nnz, c->stream);
+    if (e != hipSuccess) {
+        if (e == hipErrorNotSupported) set_error("a row of P has more than 4096 entries");
+        else if (!err.empty()) set_error(err);
+        else device_error(c, e, "building P");
+        cleanup();
+        free_ctx(c);
+        return nullptr;
+    }
+    c->allocs.push_back(rp);
+    c->allocs.push_back(col);
+    c->row_ptr = rp;
+    c->col = col;
+    e = dalloc(c, &c->val, (size_t)c->nnz * state_bytes(c));
+    if (e == hipSuccess) e = run_convert_val(c, val64);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) { device_error(c, e, "storing P"); free_ctx(c); return nullptr; }
+    if (finish_init(c) != PSNE_OK) { free_ctx(c); return nullptr; }
+    return c;
+}
+
+pixelsne_ctx* pixelsne_init(const float* X, int64_t n, int32_t D, double perplexity,
+                            int32_t screen_w, int32_t screen_h) {
+    pixelsne_params p;
+    pixelsne_default_params(&p);
+    return pixelsne_init_ex(X, n, D, perplexity, screen_w, screen_h, &p);
+}
+
+pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                   const int32_t* col, const double* val, int32_t screen_w,
+                                   int32_t screen_h, const pixelsne_params* pin) {
+    pixelsne_params p;
+    if (pin) p = *pin;
+    else pixelsne_default_params(&p);
+    if (check_params(&p) != PSNE_OK) return nullptr;
+    if (n < 2 || n >= ((int64_t)1 << 31)) { invalid("n must be in [2, 2^31)"); return nullptr; }
+    if (nnz < 1) { invalid("nnz must be >= 1"); return nullptr; }
+    int L;
+    if (check_screen(screen_w, screen_h, &L) != PSNE_OK) return nullptr;
+    if (!is_device_ptr(row_ptr) || !is_device_ptr(col) || !is_device_ptr(val)) {
+        invalid("row_ptr, col and val must be device pointers");
+        return nullptr;
+    }
+    pixelsne_ctx* c = new_ctx(n, L, screen_w, &p);
+    c->nnz = nnz;
+    hipError_t e = dalloc(c, &c->row_ptr, 8 * (size_t)(n + 1));
+    if (e == hipSuccess) e = dalloc(c, &c->col, 4 * (size_t)nnz);
+    if (e == hipSuccess) e = dalloc(c, &c->val, state_bytes(c) * (size_t)nnz);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->row_ptr, row_ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->col, col, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = run_convert_val(c, val);
+    if (e != hipSuccess) { device_error(c, e, "copying P"); free_ctx(c); return nullptr; }
+    if (finish_init(c) != PSNE_OK) { free_ctx(c); return nullptr; }
+    return c;
+}
+
+psne_status pixelsne_step_async(pixelsne_ctx* c, int32_t n_iter) {
+    if (!c) return invalid("null context");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (n_iter < 0) return invalid("n_iter must be >= 0");
+    for (int32_t it = 0; it < n_iter; it++) {
+        hipError_t e = run_iteration(c);
+        if (e != hipSuccess) return device_error(c, e, "iteration");
+    }
+    return PSNE_OK;
+}
+
+psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter) {
+    psne_status st = pixelsne_step_async(c, n_iter);
+    if (st != PSNE_OK) return st;
+    int32_t bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, &c->sc->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(c, e, "step");
+    if (bad) {
+        set_error("non-finite positions");
+        return PSNE_E_NUMERIC;
+    }
+    return PSNE_OK;
+}
+
+psne_status pixelsne_get_Y(const pixelsne_ctx* c, void* out, int32_t frame) {
+    if (!c) return invalid("null context");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (frame != PSNE_FRAME_PIXEL && frame != PSNE_FRAME_SCREEN && frame != PSNE_FRAME_Y)
+        return invalid("unknown frame");
+    if (!is_device_ptr(out)) return invalid("out must be a device pointer");
+    hipError_t e = run_get_y(c, out, frame);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "get_Y");
+    return PSNE_OK;
+}
+
+void pixelsne_destroy(pixelsne_ctx* c) { free_ctx(c); }
+
+psne_status pixelsne_get_stats(const pixelsne_ctx* c, pixelsne_stats* out) {
+    if (!c || !out) return invalid("null argument");
+    DevScalars h;
+    hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "get_stats");
+    memset(out, 0, sizeof(*out));
+    out->n = c->n;
+    out->nnz = c->nnz;
+    out->n_nodes = h.n_nodes;
+    out->r = c->r;
+    out->L = c->L;
+    out->k = c->k;
+    out->precision = c->prm.precision;
+    out->com_mode = c->prm.com_mode;
+    out->iteration = h.t;
+    out->s[0] = h.s[0];
+    out->s[1] = h.s[1];
+    out->Z = h.Z;
+    for (int l = 0; l <= c->L && l < 17; l++) out->level_size[l] = h.level_size[l];
+    return PSNE_OK;
+}
+
+psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g,
+                               const double* s, int32_t iteration) {
+    if (!c) return invalid("null context");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (!is_device_ptr(z) || (u && !is_device_ptr(u)) || (g && !is_device_ptr(g)))
+        return invalid("z, u, g must be device pointers");
+    if (!s || !(s[0] > 0.0) || !(s[1] > 0.0)) return invalid("s must hold two positive scales");
+    if (iteration < 0) return invalid("iteration must be >= 0");
+    DevScalars h;
+    hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(c, e, "set_state");
+    h.s[0] = s[0];
+    h.s[1] = s[1];
+    h.zmin[0] = h.zmin[1] = 0.0;
+    h.scale[0] = h.scale[1] = 1.0;
+    h.uscale[0] = h.uscale[1] = 1.0;
+    h.t = iteration;
+    h.nonfinite = 0;
+    e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = run_set_state(c, z, u, g);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(c, e, "set_state");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_get_state(const pixelsne_ctx* c, void* z, void* u, void* g, double* s,
+                               int32_t* iteration) {
+    if (!c) return invalid("null context");
+    if ((z && !is_device_ptr(z)) || (u && !is_device_ptr(u)) || (g && !is_device_ptr(g)))
+        return invalid("z, u, g must be device pointers");
+    hipError_t e = run_get_state(c, z, u, g);
+    DevScalars h;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "get_state");
+    if (s) { s[0] = h.s[0]; s[1] = h.s[1]; }
+    if (iteration) *iteration = h.t;
+    return PSNE_OK;
+}
+
+psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, void* R,
+                              double* Zi, uint32_t* visits, double* Z) {
+    if (!c) return invalid("null context");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    const void* ptrs[5] = {B, A, R, Zi, visits};
+    for (const void* p : ptrs)
+        if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
+    if (!isfinite(alpha)) return invalid("alpha must be finite");
+    hipError_t e = run_snap(c);
+    if (e == hipSuccess) e = run_sort(c);
+    if (e == hipSuccess) e = run_tree(c);
+    if (e == hipSuccess) e = run_traverse(c, visits, Zi);
+    if (e == hipSuccess) e = run_zsum(c);
+    if (e == hipSuccess) e = run_attract(c, 1, alpha, A, B);
+    if (e == hipSuccess && R)
+        e = hipMemcpyAsync(R, c->R, (size_t)c->n * 2 * state_bytes(c), hipMemcpyDeviceToDevice,
+                           c->stream);
+    double hz = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hz, &c->sc->Z, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(c, e, "gradient");
+    if (Z) *Z = hz;
+    return PSNE_OK;
+}
+
+psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uint32_t* keys,
+                                 uint32_t* perm, uint32_t* prefix, uint32_t* count, double* sum) {
+    if (!c || !level_size) return invalid("null argument");
+    const void* ptrs[5] = {keys, perm, prefix, count, sum};
+    for (const void* p : ptrs)
+        if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
+    DevScalars h;
+    hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_tree");
+    for (int l = 0; l <= c->L; l++) level_size[l] = h.level_size[l];
+    e = run_export_tree(c, keys, perm, prefix, count, sum);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_tree");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_ptr, int32_t* col,
+                              double* val) {
+    if (!c || !nnz) return invalid("null argument");
+    *nnz = c->nnz;
+    const void* ptrs[3] = {row_ptr, col, val};
+    for (const void* p : ptrs)
+        if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
+    hipError_t e = hipSuccess;
+    if (row_ptr)
+        e = hipMemcpyAsync(row_ptr, c->row_ptr, 8 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess && col)
+        e = hipMemcpyAsync(col, c->col, 4 * (size_t)c->nnz, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && val) e = run_export_val(c, val);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_P");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
+                         int32_t* idx, double* d2, void* stream) {
+    if (n < 2 || n >= ((int64_t)1 << 31)) return invalid("n must be in [2, 2^31)");
+    if (D < 1) return invalid("D must be >= 1");
+    if (k < 1 || k > n - 1 || k > 256) return invalid("k must be in [1, min(n - 1, 256)]");
+    if (x_dtype != PSNE_X_F32 && x_dtype != PSNE_X_F64 && x_dtype != PSNE_X_U8)
+        return invalid("unknown x_dtype");
+    if (!is_device_ptr(X) || !is_device_ptr(idx) || !is_device_ptr(d2))
+        return invalid("X, idx, d2 must be device pointers");
+    std::string err;
+    hipError_t e = psne::knn(X, n, D, x_dtype, k, idx, d2, (hipStream_t)stream, &err);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess && !err.empty()) {
+        set_error(err);
+        return PSNE_E_NUMERIC;
+    }
+    if (e != hipSuccess) return device_error(nullptr, e, "knn");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_perplexity(const double* d2, int64_t n, int32_t k, double perplexity,
+                                double* P, double* beta, void* stream) {
+    if (n < 1 || k < 1) return invalid("n and k must be >= 1");
+    if (!(perplexity > 0.0)) return invalid("perplexity must be > 0");
+    if (!is_device_ptr(d2) || !is_device_ptr(P) || (beta && !is_device_ptr(beta)))
+        return invalid("d2, P, beta must be device pointers");
+    hipError_t e = psne::perplexity(d2, n, k, perplexity, P, beta, (hipStream_t)stream);
+    if (e != hipSuccess) return device_error(nullptr, e, "perplexity");
+    return PSNE_OK;
+}
+
+}  // extern "C"

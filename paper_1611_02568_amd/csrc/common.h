@@ -1,0 +1,103 @@
+// Shared device-side definitions of the gfx950 PixelSNE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pixelsne.h"
+
+namespace psne {
+
+constexpr int kWave = 64;
+constexpr int kMaxLevels = 17;          // L <= 16 (r <= 65536): levels 0..16
+
+// Scalars that live on the device so that an iteration needs no host round
+// trip.  All FP64.
+struct DevScalars {
+    double s[2];        // y units per pixel of the current (normalised) frame
+    double zmin[2];     // pending screen scaling: z = (zh - zmin) * scale
+    double scale[2];    // r / gamma of the pending scaling
+    double uscale[2];   // factor applied to the stored velocity before its next use
+    double Z;           // Barnes-Hut normaliser of the last gradient
+    int32_t t;          // iterations done
+    int32_t nonfinite;  // set when a non-finite position appears
+    int64_t n_nodes;    // occupied cells of the last tree
+    uint32_t level_size[kMaxLevels];
+    uint32_t level_base[kMaxLevels + 1];
+};
+
+// One quadtree cell as the traversal reads it (32 bytes, one scalar load).
+// child: index of the first child cell | (number of children - 1) << 30.
+struct alignas(32) Node {
+    double cx, cy;      // representative point: centre of mass or cell centre
+    uint32_t count;     // points in the cell
+    uint32_t child;
+    uint32_t start;     // first sorted position of the cell
+    uint32_t level;
+};
+
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+template <typename T> using v2_t = typename V2<T>::type;
+
+__device__ __forceinline__ uint32_t spread_bits16(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t gather_bits16(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, kWave); v = w < v ? w : v; }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, kWave); v = w > v ? w : v; }
+    return v;
+}
+
+// Relaxed agent-scope loads that bypass the per-CU cache, for data written by
+// other workgroups of the same kernel after a release fence.
+__device__ __forceinline__ double load_agent(const double* p) {
+    uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace psne

@@ -1,0 +1,100 @@
+// Host-side context of the gfx950 PixelSNE library and the launchers that the
+// C ABI (capi.hip) drives.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace psne {
+
+// Device buffers of the per-iteration tree (sized once for n points).
+struct TreeBufs {
+    int64_t max_nodes = 0;
+    uint32_t* key[2] = {nullptr, nullptr};   // radix-sort ping-pong: Morton keys
+    uint32_t* idx[2] = {nullptr, nullptr};   // ... and point indices
+    int sorted = 0;                          // which half holds the sorted result
+    uint32_t* hist = nullptr;                // [256][sort blocks]
+    int64_t sort_blocks = 0;
+    uint32_t* lvl_cnt = nullptr;             // [levels][tree blocks]
+    uint32_t* lvl_off = nullptr;
+    int64_t tree_blocks = 0;
+    uint32_t* parent = nullptr;              // [max_nodes]
+    uint32_t* first_child = nullptr;         // [max_nodes]
+    uint32_t* arrive = nullptr;              // [max_nodes]
+    Node* nodes = nullptr;                   // [max_nodes]
+    double2* nsum = nullptr;                 // [max_nodes] coordinate sums (FP64)
+    uint32_t* leaf_of = nullptr;             // [n] leaf cell of each sorted position
+    void* zs = nullptr;                      // [n][2] positions in sorted order (state type)
+};
+
+}  // namespace psne
+
+struct pixelsne_ctx {
+    int64_t n = 0;
+    int32_t r = 0, L = 0, k = 0;
+    pixelsne_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool poisoned = false;
+
+    // P in CSR
+    int64_t nnz = 0;
+    int64_t* row_ptr = nullptr;
+    uint32_t* col = nullptr;
+    void* val = nullptr;                     // state type
+
+    // optimiser state (state type, [n][2])
+    void* zh = nullptr;                      // positions before the pending screen scaling
+    void* z = nullptr;                       // normalised positions (written by the snap pass)
+    void* u = nullptr;
+    void* g = nullptr;
+    void* R = nullptr;                       // Barnes-Hut repulsion, original order
+    double* Zi = nullptr;                    // per-point normaliser terms (debug output)
+    double* zpart = nullptr;
+    int64_t zpart_n = 0;
+    double* mm_part = nullptr;               // per-block min/max of zh
+    int64_t mm_n = 0;
+    psne::DevScalars* sc = nullptr;
+    psne::TreeBufs tb;
+
+    std::vector<void*> allocs;
+};
+
+namespace psne {
+
+void set_error(const std::string& msg);
+psne_status device_error(pixelsne_ctx* c, hipError_t e, const char* where);
+
+// iteration passes (iter.hip); each enqueues on c->stream
+hipError_t run_snap(pixelsne_ctx* c);
+hipError_t run_sort(pixelsne_ctx* c);
+hipError_t run_tree(pixelsne_ctx* c);
+hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, double* Zi);
+hipError_t run_zsum(pixelsne_ctx* c);
+// mode 0: gradient step; mode 1: write A and B only (no update)
+hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B);
+hipError_t run_finalize(pixelsne_ctx* c, int advance);
+hipError_t run_iteration(pixelsne_ctx* c);
+hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma);
+hipError_t run_get_y(const pixelsne_ctx* c, void* out, int frame);
+hipError_t run_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g);
+hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g);
+hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm,
+                           uint32_t* prefix, uint32_t* count, double* sum);
+hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
+hipError_t run_export_val(const pixelsne_ctx* c, double* out);
+
+// setup passes (setup.hip)
+hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,
+               double* d2, hipStream_t s, std::string* err);
+hipError_t perplexity(const double* d2, int64_t n, int32_t k, double u, double* P,
+                      double* beta, hipStream_t s);
+// Symmetric CSR from kNN + conditional P.  Allocates row_ptr/col/val64 with
+// hipMalloc (caller frees); synchronises once to read nnz.
+hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k,
+                      int64_t** row_ptr, uint32_t** col, double** val64, int64_t* nnz,
+                      hipStream_t s);
+
+}  // namespace psne

@@ -1,0 +1,1017 @@
+// Per-iteration passes of PixelSNE on gfx950 (wave64).
+//
+//   snap        pending screen scaling (Section 3.2) + pixel (Eq. 1-2) + Morton key
+//   sort        stable LSD radix sort of (key, index), 8-bit digits, LDS ranking
+//   tree        P-Quadtree (Section 3.1) as a linear tree: one node per occupied
+//               (level, Morton prefix); counts and FP64 coordinate sums (Eq. 8)
+//               reduced bottom-up in one pass
+//   traverse    Barnes-Hut repulsion (Eq. 5, 11, 12): one wavefront walks the
+//               union of the interaction lists of 64 Morton-consecutive points,
+//               each stack entry carrying the mask of lanes still descending
+//   zsum        Z = sum_i Z_i in FP64, fixed order
+//   attract     sparse attraction over CSR P (Eq. 5) fused with the
+//               gains/momentum step and per-block min/max of the new positions
+//   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
+#include <math.h>
+
+#include "ctx.h"
+
+namespace psne {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kBlock * kRsItems;
+constexpr int kAttractBlocksMax = 8192;
+
+template <typename T> __device__ __forceinline__ T top_below(int r);
+template <> __device__ __forceinline__ float top_below<float>(int r) {
+    return __int_as_float(__float_as_int((float)r) - 1);
+}
+template <> __device__ __forceinline__ double top_below<double>(int r) {
+    return __longlong_as_double(__double_as_longlong((double)r) - 1);
+}
+
+// ---------------------------------------------------------------------------
+// snap: z = clamp((zh - zmin) * scale, 0, r^-), key = Morton(floor(z))
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_snap(const T* __restrict__ zh, T* __restrict__ z,
+                                                 uint32_t* __restrict__ key,
+                                                 uint32_t* __restrict__ idx,
+                                                 const DevScalars* __restrict__ sc, int64_t n,
+                                                 int r) {
+    using V = v2_t<T>;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const T top = top_below<T>(r);
+    const V p = reinterpret_cast<const V*>(zh)[i];
+    T zx = (p.x - (T)sc->zmin[0]) * (T)sc->scale[0];
+    T zy = (p.y - (T)sc->zmin[1]) * (T)sc->scale[1];
+    zx = zx < T(0) ? T(0) : (zx > top ? top : zx);
+    zy = zy < T(0) ? T(0) : (zy > top ? top : zy);
+    reinterpret_cast<V*>(z)[i] = V{zx, zy};
+    const uint32_t px = (uint32_t)zx, py = (uint32_t)zy;
+    key[i] = spread_bits16(px) | (spread_bits16(py) << 1);
+    idx[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// radix sort (stable, LSD, 8-bit digits)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int shift, uint32_t* __restrict__ hist,
+                                                    int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int j = 0; j < kRsItems; j++) {
+        const int64_t p = base + j * kBlock + threadIdx.x;
+        if (p < n) atomicAdd(&h[(keys[p] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of m uint32 values in place, one block
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t m) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < m ? b + per : m;
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; i++) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t ? part[t - 1] : 0u;
+    for (int64_t i = b; i < e; i++) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                       const uint32_t* __restrict__ vin,
+                                                       uint32_t* __restrict__ kout,
+                                                       uint32_t* __restrict__ vout, int64_t n,
+                                                       int shift,
+                                                       const uint32_t* __restrict__ hist,
+                                                       int64_t nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int t = threadIdx.x, w = t >> 6;
+    run[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int j = 0; j < kRsItems; j++) {
+        const int64_t p = base + j * kBlock + t;
+        const bool valid = p < n;
+        const uint32_t key = valid ? kin[p] : 0u;
+        const uint32_t val = valid ? (vin ? vin[p] : (uint32_t)p) : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
+        __syncthreads();
+        uint64_t peers = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = ballot64(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d] + rank;
+            for (int q = 0; q < w; q++) off += wcnt[q][d];
+            kout[off] = key;
+            vout[off] = val;
+        }
+        __syncthreads();
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tree: first level at which sorted position s starts a new cell
+// (s = 0 starts a cell at every level; equal keys start none: L + 1)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int first_new_level(const uint32_t* __restrict__ keys, int64_t s,
+                                               int L) {
+    if (s == 0) return 0;
+    const uint32_t x = keys[s] ^ keys[s - 1];
+    if (x == 0) return L + 1;
+    const int hb = 31 - __clz(x);
+    return L - (hb >> 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tree_count(const uint32_t* __restrict__ keys,
+                                                       int64_t n, int L,
+                                                       uint32_t* __restrict__ cnt, int64_t nb) {
+    __shared__ uint32_t wc[4][kMaxLevels];
+    const int t = threadIdx.x, w = t >> 6;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + t;
+    const int l0 = s < n ? first_new_level(keys, s, L) : L + 1;
+    for (int l = 0; l <= L; l++) {
+        const uint64_t b = ballot64(l0 <= l);
+        if (lane_id() == 0) wc[w][l] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (t <= L) cnt[(int64_t)t * nb + blockIdx.x] = wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+}
+
+__global__ __launch_bounds__(1024) void k_tree_scan(const uint32_t* __restrict__ cnt,
+                                                    uint32_t* __restrict__ off, int64_t nb,
+                                                    int L, DevScalars* __restrict__ sc) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t base = 0;
+    for (int l = 0; l <= L; l++) {
+        const uint32_t* a = cnt + (int64_t)l * nb;
+        uint32_t* o = off + (int64_t)l * nb;
+        const int64_t per = (nb + 1023) / 1024;
+        const int64_t b = t * per, e = b + per < nb ? b + per : nb;
+        uint32_t s = 0;
+        for (int64_t i = b; i < e; i++) s += a[i];
+        part[t] = s;
+        __syncthreads();
+        for (int q = 1; q < 1024; q <<= 1) {
+            uint32_t v = t >= q ? part[t - q] : 0u;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        uint32_t run = t ? part[t - 1] : 0u;
+        for (int64_t i = b; i < e; i++) {
+            o[i] = run;
+            run += a[i];
+        }
+        const uint32_t tot = part[1023];
+        if (t == 0) {
+            sc->level_size[l] = tot;
+            sc->level_base[l] = base;
+        }
+        base += tot;
+        __syncthreads();
+    }
+    if (t == 0) {
+        sc->level_base[L + 1] = base;
+        sc->n_nodes = base;
+    }
+}
+
+// Number each cell: for every level, the rank of the cell holding sorted
+// position s.  Positions that open a cell write its start, parent and first
+// child (children of a cell are consecutive in the next level).
+__global__ __launch_bounds__(kBlock) void k_tree_nodes(
+    const uint32_t* __restrict__ keys, int64_t n, int L, const uint32_t* __restrict__ off,
+    int64_t nb, const DevScalars* __restrict__ sc, uint32_t* __restrict__ parent,
+    uint32_t* __restrict__ first_child, uint32_t* __restrict__ arrive, Node* __restrict__ nodes,
+    uint32_t* __restrict__ leaf_of) {
+    __shared__ uint32_t wc[4][kMaxLevels];
+    const int t = threadIdx.x, w = t >> 6;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + t;
+    const bool valid = s < n;
+    const int l0 = valid ? first_new_level(keys, s, L) : L + 1;
+    for (int l = 0; l <= L; l++) {
+        const uint64_t b = ballot64(l0 <= l);
+        if (lane_id() == 0) wc[w][l] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    const uint64_t le = lanemask_lt() | (1ull << lane_id());
+    uint32_t rank[kMaxLevels];
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; l++) {
+        if (l <= L) {
+            const uint64_t b = ballot64(l0 <= l);
+            uint32_t r = off[(int64_t)l * nb + blockIdx.x] + (uint32_t)__popcll(b & le);
+            for (int q = 0; q < w; q++) r += wc[q][l];
+            rank[l] = r - 1;
+        } else {
+            rank[l] = 0;
+        }
+    }
+    if (!valid) return;
+    leaf_of[s] = sc->level_base[L] + rank[L];
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; l++) {
+        if (l <= L && l0 <= l) {
+            const uint32_t gid = sc->level_base[l] + rank[l];
+            nodes[gid].start = (uint32_t)s;
+            nodes[gid].level = (uint32_t)l;
+            arrive[gid] = 0;
+            parent[gid] = l > 0 ? sc->level_base[l > 0 ? l - 1 : 0] + rank[l > 0 ? l - 1 : 0]
+                                : 0xFFFFFFFFu;
+            first_child[gid] = l < L ? sc->level_base[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L]
+                                     : 0u;
+        }
+    }
+}
+
+__device__ __forceinline__ void write_node(Node* __restrict__ nodes, double2* __restrict__ nsum,
+                                           uint32_t g, int level, int L, double sx, double sy,
+                                           uint32_t count, uint32_t child, uint32_t key0,
+                                           int com_mode) {
+    double cx, cy;
+    if (com_mode == PSNE_COM_CELL_CENTER) {
+        const int sh = L - level;
+        const uint32_t pre = sh >= 16 ? 0u : (key0 >> (2 * sh));
+        const double w = (double)(1u << sh);
+        cx = (double)gather_bits16(pre) * w + 0.5 * w;
+        cy = (double)gather_bits16(pre >> 1) * w + 0.5 * w;
+    } else {
+        cx = sx / (double)count;
+        cy = sy / (double)count;
+    }
+    nodes[g].cx = cx;
+    nodes[g].cy = cy;
+    nodes[g].count = count;
+    nodes[g].child = child;
+    nsum[g] = double2{sx, sy};
+}
+
+// Leaves sum their points (sorted order); the last child to finish a parent
+// sums the parent's children in child order and continues upwards.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tree_sums(
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys, const T* __restrict__ z,
+    int64_t n, int L, int com_mode, const DevScalars* __restrict__ sc,
+    const uint32_t* __restrict__ parent, const uint32_t* __restrict__ first_child,
+    uint32_t* __restrict__ arrive, Node* __restrict__ nodes, double2* __restrict__ nsum,
+    T* __restrict__ zs) {
+    using V = v2_t<T>;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t nleaf = sc->level_size[L];
+    if (t >= nleaf) return;
+    const uint32_t gid = sc->level_base[L] + (uint32_t)t;
+    const uint32_t start = nodes[gid].start;
+    const uint32_t end = (t + 1 < nleaf) ? nodes[gid + 1].start : (uint32_t)n;
+    double sx = 0.0, sy = 0.0;
+    for (uint32_t s = start; s < end; s++) {
+        const V p = reinterpret_cast<const V*>(z)[perm[s]];
+        reinterpret_cast<V*>(zs)[s] = p;
+        sx += (double)p.x;
+        sy += (double)p.y;
+    }
+    write_node(nodes, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
+    int l = L;
+    uint32_t g = gid;
+    while (l > 0) {
+        const uint32_t p = parent[g];
+        const uint32_t fc = first_child[p];
+        const uint32_t pend = sc->level_base[l - 1] + sc->level_size[l - 1];
+        const uint32_t lc = (p + 1 < pend) ? first_child[p + 1] : sc->level_base[l] + sc->level_size[l];
+        const uint32_t nch = lc - fc;
+        __threadfence();
+        const uint32_t old = atomicAdd(&arrive[p], 1u);
+        if (old != nch - 1) break;
+        __threadfence();
+        double ax = 0.0, ay = 0.0;
+        uint32_t c = 0;
+        for (uint32_t q = fc; q < lc; q++) {
+            ax += load_agent(&nsum[q].x);
+            ay += load_agent(&nsum[q].y);
+            c += load_agent(&nodes[q].count);
+        }
+        l -= 1;
+        g = p;
+        write_node(nodes, nsum, g, l, L, ax, ay, c, fc | ((nch - 1) << 30),
+                   keys[nodes[g].start], com_mode);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Barnes-Hut traversal
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void bh_term(double d2, double dx, double dy, double m, double& zacc,
+                                        T& rx, T& ry);
+
+template <>
+__device__ __forceinline__ void bh_term<float>(double d2, double dx, double dy, double m,
+                                               double& zacc, float& rx, float& ry) {
+    const float q = __builtin_amdgcn_rcpf((float)(1.0 + d2));
+    const float mq = (float)m * q;
+    zacc += (double)mq;
+    const float f = mq * q;
+    rx += f * (float)dx;
+    ry += f * (float)dy;
+}
+
+template <>
+__device__ __forceinline__ void bh_term<double>(double d2, double dx, double dy, double m,
+                                                double& zacc, double& rx, double& ry) {
+    const double q = 1.0 / (1.0 + d2);
+    const double mq = m * q;
+    zacc += mq;
+    rx += mq * q * dx;
+    ry += mq * q * dy;
+}
+
+// beta-weighted squared distance, evaluated exactly as ((b1*dx)*dx) + ((b2*dy)*dy)
+// with every operation rounded separately (no fused multiply-add), so that the
+// opening decision is the one the FP64 definition takes
+__device__ __forceinline__ double dist2(double b1, double b2, double dx, double dy) {
+#pragma clang fp contract(off)
+    const double a = (b1 * dx) * dx;
+    const double b = (b2 * dy) * dy;
+    return a + b;
+}
+__device__ __forceinline__ double mul_nc(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double add_nc(double a, double b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+
+// replace lane `sel` of a per-lane register (sel is wave-uniform)
+__device__ __forceinline__ int put_lane(int v, int sel, int old) {
+    return lane_id() == sel ? v : old;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_traverse(
+    const Node* __restrict__ nodes, const double2* __restrict__ nsum, const T* __restrict__ zs,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
+    const DevScalars* __restrict__ sc, int64_t n, int L, double th2, int com_mode,
+    T* __restrict__ R, double* __restrict__ zpart, double* __restrict__ Zi_out,
+    uint32_t* __restrict__ visits_out) {
+    using V = v2_t<T>;
+    __shared__ double wz[4];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = s < n;
+    const V zp = valid ? reinterpret_cast<const V*>(zs)[s] : V{T(0), T(0)};
+    const double zx = (double)zp.x, zy = (double)zp.y;
+    const uint32_t own = valid ? leaf_of[s] : 0xFFFFFFFFu;
+    const double s0 = sc->s[0], s1 = sc->s[1];
+    const double b1 = mul_nc(s0, s0), b2 = mul_nc(s1, s1), bsum = add_nc(b1, b2);
+
+    double zacc = 0.0;
+    T rx = T(0), ry = T(0);
+    uint32_t nvis = 0;
+
+    // Stack entry k lives in lane k of these registers: first cell of a
+    // sibling group, (group size | level << 8), lane mask (lo, hi).
+    int st_first = 0, st_info = 0, st_mlo = 0, st_mhi = 0;
+    int sp = 0;
+    const uint64_t m0 = ballot64(valid);
+    if (m0) {
+        st_info = put_lane(1, 0, st_info);
+        st_mlo = put_lane((int)(uint32_t)m0, 0, st_mlo);
+        st_mhi = put_lane((int)(uint32_t)(m0 >> 32), 0, st_mhi);
+        sp = 1;
+    }
+    while (sp > 0) {
+        sp--;
+        const uint32_t first = (uint32_t)__builtin_amdgcn_readlane(st_first, sp);
+        const uint32_t info = (uint32_t)__builtin_amdgcn_readlane(st_info, sp);
+        const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(st_mhi, sp) << 32) |
+                              (uint64_t)(uint32_t)__builtin_amdgcn_readlane(st_mlo, sp);
+        const uint32_t nsib = info & 0xFFu;
+        const int level = (int)(info >> 8);
+        const bool act = (mask >> lane) & 1ull;
+        const double diag2 = ldexp(bsum, 2 * (L - level));
+        for (uint32_t q = 0; q < nsib; q++) {
+            const uint32_t c = first + q;
+            const Node nd = nodes[c];
+            bool open = false;
+            if (act) {
+                nvis++;
+                double cx = nd.cx, cy = nd.cy, m = (double)nd.count;
+                bool use;
+                if (level == L) {
+                    if (c == own) {
+                        m -= 1.0;
+                        if (m > 0.0 && com_mode != PSNE_COM_CELL_CENTER) {
+                            const double2 sm = nsum[c];
+                            cx = (sm.x - zx) / m;
+                            cy = (sm.y - zy) / m;
+                        }
+                    }
+                    use = m > 0.0;
+                } else {
+                    const double dx = zx - cx, dy = zy - cy;
+                    use = diag2 < mul_nc(th2, dist2(b1, b2, dx, dy));
+                    open = !use;
+                }
+                if (use) {
+                    const double dx = zx - cx, dy = zy - cy;
+                    bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, m, zacc, rx, ry);
+                }
+            }
+            const uint64_t om = ballot64(open);
+            if (om) {
+                st_first = put_lane((int)(nd.child & 0x3FFFFFFFu), sp, st_first);
+                st_info = put_lane((int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
+                                                     sp, st_info);
+                st_mlo = put_lane((int)(uint32_t)om, sp, st_mlo);
+                st_mhi = put_lane((int)(uint32_t)(om >> 32), sp, st_mhi);
+                sp++;
+            }
+        }
+    }
+    if (valid) {
+        const uint32_t i = perm[s];
+        reinterpret_cast<V*>(R)[i] = V{rx, ry};
+        if (Zi_out) Zi_out[i] = zacc;
+        if (visits_out) visits_out[i] = nvis;
+    }
+    const double zw = wave_sum(zacc);
+    if (lane == 0) wz[w] = zw;
+    __syncthreads();
+    if (threadIdx.x == 0) zpart[blockIdx.x] = ((wz[0] + wz[1]) + wz[2]) + wz[3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zsum(const double* __restrict__ zpart, int64_t m,
+                                                 DevScalars* __restrict__ sc) {
+    __shared__ double red[kBlock];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kBlock) a += zpart[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->Z = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// attraction + update
+// ---------------------------------------------------------------------------
+struct StepParams {
+    double exaggeration, eta, mom0, mom1, min_gain, alpha_override;
+    int32_t exag_iters, mom_switch;
+};
+
+template <typename T> __device__ __forceinline__ T rcp_fast(T x);
+template <> __device__ __forceinline__ float rcp_fast<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return 1.0 / x; }
+
+template <typename T> __device__ __forceinline__ T sgn(T x) {
+    return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_attract(
+    const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
+    const T* __restrict__ z, const T* __restrict__ R, T* __restrict__ u, T* __restrict__ g,
+    T* __restrict__ zh, DevScalars* __restrict__ sc, int64_t n, StepParams prm,
+    T* __restrict__ Aout, T* __restrict__ Bout, double* __restrict__ mm_part) {
+    using V = v2_t<T>;
+    __shared__ double red[4][4];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
+    const double s0 = sc->s[0], s1 = sc->s[1];
+    const T b1 = (T)(s0 * s0), b2 = (T)(s1 * s1);
+    const double Z = sc->Z;
+    const int t = sc->t;
+    const double alpha = MODE == 1 ? prm.alpha_override
+                                   : (t < prm.exag_iters ? prm.exaggeration : 1.0);
+    const T mu = (T)(t < prm.mom_switch ? prm.mom0 : prm.mom1);
+    const T us0 = (T)sc->uscale[0], us1 = (T)sc->uscale[1];
+    const T eta = (T)prm.eta, gmin = (T)prm.min_gain;
+    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    bool bad = false;
+    for (int64_t i = wave; i < n; i += nwaves) {
+        const int64_t e0 = rp[i], e1 = rp[i + 1];
+        const V zi = reinterpret_cast<const V*>(z)[i];
+        T ax = T(0), ay = T(0);
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const uint32_t j = col[e];
+            const T p = val[e];
+            const V zj = reinterpret_cast<const V*>(z)[j];
+            const T dx = zi.x - zj.x, dy = zi.y - zj.y;
+            const T q = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
+            const T pq = p * q;
+            ax += pq * dx;
+            ay += pq * dy;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if (lane == 0) {
+            const V Ri = reinterpret_cast<const V*>(R)[i];
+            const T bx = (T)(alpha * (double)ax - (double)Ri.x / Z);
+            const T by = (T)(alpha * (double)ay - (double)Ri.y / Z);
+            if (MODE == 1) {
+                if (Aout) reinterpret_cast<V*>(Aout)[i] = V{ax, ay};
+                if (Bout) reinterpret_cast<V*>(Bout)[i] = V{bx, by};
+            } else {
+                V ui = reinterpret_cast<V*>(u)[i];
+                V gi = reinterpret_cast<V*>(g)[i];
+                ui.x *= us0;
+                ui.y *= us1;
+                T gx = sgn(bx) != sgn(ui.x) ? gi.x + T(0.2) : gi.x * T(0.8);
+                T gy = sgn(by) != sgn(ui.y) ? gi.y + T(0.2) : gi.y * T(0.8);
+                gx = gx < gmin ? gmin : gx;
+                gy = gy < gmin ? gmin : gy;
+                ui.x = mu * ui.x - eta * gx * bx;
+                ui.y = mu * ui.y - eta * gy * by;
+                const T hx = zi.x + ui.x, hy = zi.y + ui.y;
+                reinterpret_cast<V*>(u)[i] = ui;
+                reinterpret_cast<V*>(g)[i] = V{gx, gy};
+                reinterpret_cast<V*>(zh)[i] = V{hx, hy};
+                if (!isfinite(hx) || !isfinite(hy)) bad = true;
+                mnx = fmin(mnx, (double)hx);
+                mny = fmin(mny, (double)hy);
+                mxx = fmax(mxx, (double)hx);
+                mxy = fmax(mxy, (double)hy);
+            }
+        }
+    }
+    if (MODE == 1) return;
+    if (bad) atomicOr(&sc->nonfinite, 1);
+    if (lane == 0) {
+        red[w][0] = mnx; red[w][1] = mny; red[w][2] = mxx; red[w][3] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int q = 1; q < 4; q++) v = k < 2 ? fmin(v, red[q][k]) : fmax(v, red[q][k]);
+        mm_part[(int64_t)blockIdx.x * 4 + k] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_minmax(const T* __restrict__ zh, int64_t n,
+                                                   double* __restrict__ mm_part) {
+    using V = v2_t<T>;
+    __shared__ double red[4][4];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const V p = reinterpret_cast<const V*>(zh)[i];
+        mnx = fmin(mnx, (double)p.x); mny = fmin(mny, (double)p.y);
+        mxx = fmax(mxx, (double)p.x); mxy = fmax(mxy, (double)p.y);
+    }
+    mnx = wave_min(mnx); mny = wave_min(mny); mxx = wave_max(mxx); mxy = wave_max(mxy);
+    if (lane == 0) { red[w][0] = mnx; red[w][1] = mny; red[w][2] = mxx; red[w][3] = mxy; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int q = 1; q < 4; q++) v = k < 2 ? fmin(v, red[q][k]) : fmax(v, red[q][k]);
+        mm_part[(int64_t)blockIdx.x * 4 + k] = v;
+    }
+}
+
+// screen-driven scaling: gamma = max - min + eps per axis (Section 3.2)
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ mm_part,
+                                                     int64_t m, DevScalars* __restrict__ sc,
+                                                     int r, double eps, int advance) {
+    __shared__ double red[4][kBlock];
+    double mn0 = INFINITY, mn1 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY;
+    for (int64_t i = threadIdx.x; i < m; i += kBlock) {
+        mn0 = fmin(mn0, mm_part[4 * i + 0]);
+        mn1 = fmin(mn1, mm_part[4 * i + 1]);
+        mx0 = fmax(mx0, mm_part[4 * i + 2]);
+        mx1 = fmax(mx1, mm_part[4 * i + 3]);
+    }
+    red[0][threadIdx.x] = mn0; red[1][threadIdx.x] = mn1;
+    red[2][threadIdx.x] = mx0; red[3][threadIdx.x] = mx1;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const int a = threadIdx.x, b = threadIdx.x + o;
+            red[0][a] = fmin(red[0][a], red[0][b]);
+            red[1][a] = fmin(red[1][a], red[1][b]);
+            red[2][a] = fmax(red[2][a], red[2][b]);
+            red[3][a] = fmax(red[3][a], red[3][b]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 2; d++) {
+            const double lo = red[d][0], hi = red[2 + d][0];
+            const double gamma = hi - lo + eps;
+            sc->zmin[d] = lo;
+            sc->scale[d] = (double)r / gamma;
+            sc->uscale[d] = (double)r / gamma;
+            sc->s[d] = sc->s[d] * (gamma / (double)r);
+        }
+        if (advance) sc->t += 1;
+    }
+}
+
+// counter-based initial embedding: SplitMix64 (Steele, Lea & Flood 2014)
+// uniforms through the Box-Muller transform
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_state(const double* __restrict__ Y, T* __restrict__ zh,
+                                                       T* __restrict__ u, T* __restrict__ g,
+                                                       int64_t n, uint64_t seed, double sigma) {
+    using V = v2_t<T>;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double y0, y1;
+    if (Y) {
+        y0 = Y[2 * i];
+        y1 = Y[2 * i + 1];
+    } else {
+        const uint64_t a = splitmix64(seed ^ (2ull * (uint64_t)i));
+        const uint64_t b = splitmix64(seed ^ (2ull * (uint64_t)i + 1ull));
+        const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
+        const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+        const double rad = sqrt(-2.0 * log(u1));
+        y0 = sigma * rad * cos(2.0 * M_PI * u2);
+        y1 = sigma * rad * sin(2.0 * M_PI * u2);
+    }
+    reinterpret_cast<V*>(zh)[i] = V{(T)y0, (T)y1};
+    reinterpret_cast<V*>(u)[i] = V{T(0), T(0)};
+    reinterpret_cast<V*>(g)[i] = V{T(1), T(1)};
+}
+
+// normalised position of point i (same arithmetic as k_snap)
+template <typename T>
+__device__ __forceinline__ v2_t<T> norm_pos(const T* __restrict__ zh,
+                                            const DevScalars* __restrict__ sc, int64_t i, int r) {
+    using V = v2_t<T>;
+    const T top = top_below<T>(r);
+    const V p = reinterpret_cast<const V*>(zh)[i];
+    T zx = (p.x - (T)sc->zmin[0]) * (T)sc->scale[0];
+    T zy = (p.y - (T)sc->zmin[1]) * (T)sc->scale[1];
+    zx = zx < T(0) ? T(0) : (zx > top ? top : zx);
+    zy = zy < T(0) ? T(0) : (zy > top ? top : zy);
+    return V{zx, zy};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_get_y(const T* __restrict__ zh,
+                                                  const DevScalars* __restrict__ sc, int64_t n,
+                                                  int r, int frame, void* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const v2_t<T> p = norm_pos<T>(zh, sc, i, r);
+    if (frame == PSNE_FRAME_SCREEN) {
+        int px = (int)p.x, py = (int)p.y;
+        px = px > r - 1 ? r - 1 : px;
+        py = py > r - 1 ? r - 1 : py;
+        reinterpret_cast<int2*>(out)[i] = int2{px, py};
+    } else if (frame == PSNE_FRAME_Y) {
+        reinterpret_cast<double2*>(out)[i] = double2{(double)p.x * sc->s[0], (double)p.y * sc->s[1]};
+    } else {
+        reinterpret_cast<double2*>(out)[i] = double2{(double)p.x, (double)p.y};
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_get_state(const T* __restrict__ zh, const T* __restrict__ u,
+                                                      const T* __restrict__ g,
+                                                      const DevScalars* __restrict__ sc, int64_t n,
+                                                      int r, T* __restrict__ zo, T* __restrict__ uo,
+                                                      T* __restrict__ go) {
+    using V = v2_t<T>;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (zo) reinterpret_cast<V*>(zo)[i] = norm_pos<T>(zh, sc, i, r);
+    if (uo) {
+        V v = reinterpret_cast<const V*>(u)[i];
+        v.x *= (T)sc->uscale[0];
+        v.y *= (T)sc->uscale[1];
+        reinterpret_cast<V*>(uo)[i] = v;
+    }
+    if (go) reinterpret_cast<V*>(go)[i] = reinterpret_cast<const V*>(g)[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_state(T* __restrict__ u, T* __restrict__ g, int64_t n,
+                                                       int fill_u, int fill_g) {
+    using V = v2_t<T>;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (fill_u) reinterpret_cast<V*>(u)[i] = V{T(0), T(0)};
+    if (fill_g) reinterpret_cast<V*>(g)[i] = V{T(1), T(1)};
+}
+
+__global__ __launch_bounds__(kBlock) void k_export_tree(const Node* __restrict__ nodes,
+                                                        const double2* __restrict__ nsum,
+                                                        const uint32_t* __restrict__ keys,
+                                                        const DevScalars* __restrict__ sc, int L,
+                                                        uint32_t* __restrict__ prefix,
+                                                        uint32_t* __restrict__ count,
+                                                        double* __restrict__ sum) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= sc->n_nodes) return;
+    const Node nd = nodes[g];
+    const int sh = L - (int)nd.level;
+    if (prefix) prefix[g] = sh >= 16 ? 0u : (keys[nd.start] >> (2 * sh));
+    if (count) count[g] = nd.count;
+    if (sum) {
+        sum[2 * g] = nsum[g].x;
+        sum[2 * g + 1] = nsum[g].y;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cast_val(const double* __restrict__ a, T* __restrict__ b,
+                                                     int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) b[i] = (T)a[i];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_uncast_val(const T* __restrict__ a, double* __restrict__ b,
+                                                       int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) b[i] = (double)a[i];
+}
+
+inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
+
+inline int64_t attract_blocks(int64_t n) {
+    int64_t b = ceil_div(n, 4);
+    return b < kAttractBlocksMax ? b : kAttractBlocksMax;
+}
+
+inline bool fp64(const pixelsne_ctx* c) { return c->prm.precision == PSNE_FP64; }
+
+StepParams step_params(const pixelsne_ctx* c, double alpha) {
+    StepParams p;
+    p.exaggeration = c->prm.exaggeration;
+    p.eta = c->prm.eta;
+    p.mom0 = c->prm.mom0;
+    p.mom1 = c->prm.mom1;
+    p.min_gain = c->prm.min_gain;
+    p.alpha_override = alpha;
+    p.exag_iters = c->prm.exag_iters;
+    p.mom_switch = c->prm.mom_switch;
+    return p;
+}
+
+}  // namespace
+
+int64_t attract_block_count(int64_t n) { return attract_blocks(n); }
+
+hipError_t run_snap(pixelsne_ctx* c) {
+    if (fp64(c))
+        k_snap<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const double*)c->zh, (double*)c->z, c->tb.key[0], c->tb.idx[0], c->sc, c->n, c->r);
+    else
+        k_snap<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const float*)c->zh, (float*)c->z, c->tb.key[0], c->tb.idx[0], c->sc, c->n, c->r);
+    return hipGetLastError();
+}
+
+hipError_t run_sort(pixelsne_ctx* c) {
+    TreeBufs& tb = c->tb;
+    const int bits = 2 * c->L;
+    const int passes = (bits + 7) / 8;
+    int cur = 0;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        k_rs_hist<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
+            tb.key[cur], c->n, shift, tb.hist, tb.sort_blocks);
+        k_scan_u32<<<1, 1024, 0, c->stream>>>(tb.hist, 256 * tb.sort_blocks);
+        // the first pass generates the identity permutation itself
+        k_rs_scatter<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
+            tb.key[cur], p == 0 ? nullptr : tb.idx[cur], tb.key[cur ^ 1], tb.idx[cur ^ 1], c->n,
+            shift, tb.hist, tb.sort_blocks);
+        cur ^= 1;
+    }
+    tb.sorted = cur;
+    return hipGetLastError();
+}
+
+hipError_t run_tree(pixelsne_ctx* c) {
+    TreeBufs& tb = c->tb;
+    const uint32_t* keys = tb.key[tb.sorted];
+    const uint32_t* perm = tb.idx[tb.sorted];
+    k_tree_count<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
+        keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks);
+    k_tree_scan<<<1, 1024, 0, c->stream>>>(tb.lvl_cnt, tb.lvl_off, tb.tree_blocks, c->L, c->sc);
+    k_tree_nodes<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
+        keys, c->n, c->L, tb.lvl_off, tb.tree_blocks, c->sc, tb.parent, tb.first_child,
+        tb.arrive, tb.nodes, tb.leaf_of);
+    // one thread per leaf; at most min(n, 4^L) leaves
+    const int64_t max_leaves = c->n;
+    if (fp64(c))
+        k_tree_sums<double><<<grid_for(max_leaves), kBlock, 0, c->stream>>>(
+            perm, keys, (const double*)c->z, c->n, c->L, c->prm.com_mode, c->sc, tb.parent,
+            tb.first_child, tb.arrive, tb.nodes, tb.nsum, (double*)tb.zs);
+    else
+        k_tree_sums<float><<<grid_for(max_leaves), kBlock, 0, c->stream>>>(
+            perm, keys, (const float*)c->z, c->n, c->L, c->prm.com_mode, c->sc, tb.parent,
+            tb.first_child, tb.arrive, tb.nodes, tb.nsum, (float*)tb.zs);
+    return hipGetLastError();
+}
+
+hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, double* Zi) {
+    TreeBufs& tb = c->tb;
+    const double th2 = c->prm.theta * c->prm.theta;
+    const uint32_t* perm = tb.idx[tb.sorted];
+    if (fp64(c))
+        k_traverse<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            tb.nodes, tb.nsum, (const double*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
+            c->prm.com_mode, (double*)c->R, c->zpart, Zi, visits);
+    else
+        k_traverse<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            tb.nodes, tb.nsum, (const float*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
+            c->prm.com_mode, (float*)c->R, c->zpart, Zi, visits);
+    return hipGetLastError();
+}
+
+hipError_t run_zsum(pixelsne_ctx* c) {
+    k_zsum<<<1, kBlock, 0, c->stream>>>(c->zpart, ceil_div(c->n, kBlock), c->sc);
+    return hipGetLastError();
+}
+
+hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B) {
+    const StepParams p = step_params(c, alpha);
+    const dim3 grid((unsigned)attract_blocks(c->n));
+    if (fp64(c)) {
+        using T = double;
+        if (mode == 0)
+            k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
+                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, nullptr, nullptr, c->mm_part);
+        else
+            k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
+                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, (T*)A, (T*)B, c->mm_part);
+    } else {
+        using T = float;
+        if (mode == 0)
+            k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
+                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, nullptr, nullptr, c->mm_part);
+        else
+            k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
+                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, (T*)A, (T*)B, c->mm_part);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_finalize(pixelsne_ctx* c, int advance) {
+    k_finalize<<<1, kBlock, 0, c->stream>>>(c->mm_part, attract_blocks(c->n), c->sc, c->r,
+                                            c->prm.eps, advance);
+    return hipGetLastError();
+}
+
+hipError_t run_iteration(pixelsne_ctx* c) {
+    hipError_t e;
+    if ((e = run_snap(c)) != hipSuccess) return e;
+    if ((e = run_sort(c)) != hipSuccess) return e;
+    if ((e = run_tree(c)) != hipSuccess) return e;
+    if ((e = run_traverse(c, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = run_zsum(c)) != hipSuccess) return e;
+    if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
+    return run_finalize(c, 1);
+}
+
+hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma) {
+    DevScalars h{};
+    h.s[0] = h.s[1] = 1.0;            // the initial frame is y itself
+    h.scale[0] = h.scale[1] = 1.0;
+    h.uscale[0] = h.uscale[1] = 1.0;
+    hipError_t e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    const int64_t nb = attract_blocks(c->n);
+    if (fp64(c)) {
+        k_init_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            Y, (double*)c->zh, (double*)c->u, (double*)c->g, c->n, seed, sigma);
+        k_minmax<double><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>((const double*)c->zh, c->n,
+                                                                         c->mm_part);
+    } else {
+        k_init_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            Y, (float*)c->zh, (float*)c->u, (float*)c->g, c->n, seed, sigma);
+        k_minmax<float><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>((const float*)c->zh, c->n,
+                                                                        c->mm_part);
+    }
+    return run_finalize(c, 0);
+}
+
+hipError_t run_get_y(const pixelsne_ctx* c, void* out, int frame) {
+    if (fp64(c))
+        k_get_y<double><<<grid_for(c->n), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
+                                                                   c->n, c->r, frame, out);
+    else
+        k_get_y<float><<<grid_for(c->n), kBlock, 0, c->stream>>>((const float*)c->zh, c->sc, c->n,
+                                                                  c->r, frame, out);
+    return hipGetLastError();
+}
+
+hipError_t run_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g) {
+    const size_t bytes = (size_t)c->n * 2 * (fp64(c) ? 8 : 4);
+    hipError_t e = hipMemcpyAsync(c->zh, z, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(c->u, u, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && g) e = hipMemcpyAsync(c->g, g, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    if (!u || !g) {
+        if (fp64(c))
+            k_fill_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+                (double*)c->u, (double*)c->g, c->n, !u, !g);
+        else
+            k_fill_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+                (float*)c->u, (float*)c->g, c->n, !u, !g);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g) {
+    if (fp64(c))
+        k_get_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const double*)c->zh, (const double*)c->u, (const double*)c->g, c->sc, c->n, c->r,
+            (double*)z, (double*)u, (double*)g);
+    else
+        k_get_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const float*)c->zh, (const float*)c->u, (const float*)c->g, c->sc, c->n, c->r,
+            (float*)z, (float*)u, (float*)g);
+    return hipGetLastError();
+}
+
+hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm, uint32_t* prefix,
+                           uint32_t* count, double* sum) {
+    const TreeBufs& tb = c->tb;
+    hipError_t e = hipSuccess;
+    if (keys)
+        e = hipMemcpyAsync(keys, tb.key[tb.sorted], (size_t)c->n * 4, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess && perm)
+        e = hipMemcpyAsync(perm, tb.idx[tb.sorted], (size_t)c->n * 4, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e != hipSuccess) return e;
+    if (prefix || count || sum)
+        k_export_tree<<<grid_for(tb.max_nodes), kBlock, 0, c->stream>>>(
+            tb.nodes, tb.nsum, tb.key[tb.sorted], c->sc, c->L, prefix, count, sum);
+    return hipGetLastError();
+}
+
+hipError_t run_convert_val(pixelsne_ctx* c, const double* val64) {
+    if (fp64(c))
+        return hipMemcpyAsync(c->val, val64, (size_t)c->nnz * 8, hipMemcpyDeviceToDevice,
+                              c->stream);
+    k_cast_val<float><<<grid_for(c->nnz), kBlock, 0, c->stream>>>(val64, (float*)c->val, c->nnz);
+    return hipGetLastError();
+}
+
+hipError_t run_export_val(const pixelsne_ctx* c, double* out) {
+    if (fp64(c))
+        return hipMemcpyAsync(out, c->val, (size_t)c->nnz * 8, hipMemcpyDeviceToDevice, c->stream);
+    k_uncast_val<float><<<grid_for(c->nnz), kBlock, 0, c->stream>>>((const float*)c->val, out,
+                                                                     c->nnz);
+    return hipGetLastError();
+}
+
+}  // namespace psne

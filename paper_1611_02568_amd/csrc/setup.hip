@@ -1,0 +1,638 @@
+// One-time setup on gfx950: the sparse affinity matrix P (paper Section 2.2-2.3).
+//
+//   knn          brute-force k nearest neighbours.  Distance tiles come from
+//                FP32 MFMA (v_mfma_f32_16x16x4f32): d = |x|^2 + |y|^2 - 2 x.y;
+//                each row keeps a candidate list (global memory, per-row
+//                threshold in LDS) that is compacted to the K' = k + 32 best
+//                by a block-wide bitonic sort whenever it fills up.  The K'
+//                survivors are re-ranked with exact FP64 distances and ties go
+//                to the smaller index.
+//   perplexity   per-row bisection on the Gaussian precision (FP64)
+//   symmetrize   p_ij = (p_{j|i} + p_{i|j}) / 2n on the union pattern -> CSR
+#include <math.h>
+
+#include <string>
+
+#include "ctx.h"
+
+namespace psne {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kQB = 64;        // query rows per block
+constexpr int kCB = 64;        // candidate columns per tile
+constexpr int kKC = 32;        // reduction chunk staged in LDS
+constexpr int kCap = 512;      // candidate list capacity per row
+constexpr int kMargin = 32;    // extra candidates kept for the exact re-rank
+
+template <typename X> __device__ __forceinline__ float to_f32(X v) { return (float)v; }
+
+template <typename X>
+__device__ __forceinline__ double to_f64(X v) { return (double)v; }
+
+template <typename X>
+__global__ __launch_bounds__(256) void k_row_norms(const X* __restrict__ Xm, int64_t n, int D,
+                                                   float* __restrict__ nrm) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (i >= n) return;
+    double a = 0.0;
+    for (int d = lane; d < D; d += 64) {
+        const float v = to_f32(Xm[i * D + d]);
+        a += (double)v * (double)v;
+    }
+    a = wave_sum(a);
+    if (lane == 0) nrm[i] = (float)a;
+}
+
+// block-wide bitonic sort of 512 uint64 keys in LDS (256 threads)
+__device__ void bitonic512(uint64_t* s) {
+    const int t = threadIdx.x;
+    for (int k = 2; k <= 512; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            // thread t handles the pair whose lower index has bit j clear
+            const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+            const int l = i | j;
+            const uint64_t a = s[i], b = s[l];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) {
+                s[i] = b;
+                s[l] = a;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t cand_key(float d, uint32_t j) {
+    const float c = d > 0.0f ? d : 0.0f;
+    return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)j;
+}
+
+// Compact the candidate list of local row q to its kp best (sorted).
+__device__ void compact_row(int q, int64_t grow, uint32_t* cnt, float* thr, uint64_t* cand,
+                            uint64_t* sbuf, int kp) {
+    const int t = threadIdx.x;
+    const int m = (int)cnt[q];
+    uint64_t* lst = cand + grow * kCap;
+    for (int e = t; e < 512; e += 256) sbuf[e] = e < m ? lst[e] : ~0ull;
+    __syncthreads();
+    bitonic512(sbuf);
+    const int keep = m < kp ? m : kp;
+    for (int e = t; e < keep; e += 256) lst[e] = sbuf[e];
+    __syncthreads();
+    if (t == 0) {
+        cnt[q] = (uint32_t)keep;
+        thr[q] = keep == kp ? __uint_as_float((uint32_t)(sbuf[kp - 1] >> 32)) : INFINITY;
+    }
+    __syncthreads();
+}
+
+// Candidate generation: one block per 64 query rows, all candidate tiles.
+template <typename X>
+__global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm, int64_t n,
+                                                        int D, const float* __restrict__ nrm,
+                                                        int kp, uint64_t* __restrict__ cand,
+                                                        uint32_t* __restrict__ cand_cnt,
+                                                        float* __restrict__ cand_thr) {
+    __shared__ float As[kQB][kKC + 1];
+    __shared__ float Bs[kCB][kKC + 1];
+    __shared__ uint32_t cnt[kQB];
+    __shared__ float thr[kQB];
+    __shared__ float nq[kQB];
+    __shared__ float nc[kCB];
+    __shared__ uint64_t sbuf[512];
+    __shared__ int need;
+
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const int64_t q0 = (int64_t)blockIdx.x * kQB;
+    if (t < kQB) {
+        cnt[t] = 0;
+        thr[t] = INFINITY;
+        nq[t] = q0 + t < n ? nrm[q0 + t] : 0.0f;
+    }
+    const int lr = t >> 2, lc = (t & 3) * 8;   // loader: row lr, 8 columns from lc
+
+    for (int64_t c0 = 0; c0 < n; c0 += kCB) {
+        v4f acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (t < kCB) nc[t] = c0 + t < n ? nrm[c0 + t] : 0.0f;
+        for (int k0 = 0; k0 < D; k0 += kKC) {
+            __syncthreads();
+            {
+                const int64_t ra = q0 + lr, rb = c0 + lr;
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int d = k0 + lc + e;
+                    As[lr][lc + e] = (ra < n && d < D) ? to_f32(Xm[ra * D + d]) : 0.0f;
+                    Bs[lr][lc + e] = (rb < n && d < D) ? to_f32(Xm[rb * D + d]) : 0.0f;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < kKC; kk += 4) {
+                const float a = As[16 * w + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const float b = Bs[16 * j + (lane & 15)][kk + (lane >> 4)];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+                }
+            }
+        }
+        // filter: output row 16w + 4(lane/16) + i, column 16j + lane%16
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int rl = 16 * w + 4 * (lane >> 4) + i;
+                const int cl = 16 * j + (lane & 15);
+                const int64_t gr = q0 + rl, gc = c0 + cl;
+                const float d = nq[rl] + nc[cl] - 2.0f * acc[j][i];
+                if (gr < n && gc < n && gc != gr && d <= thr[rl]) {
+                    const uint32_t pos = atomicAdd(&cnt[rl], 1u);
+                    cand[gr * kCap + pos] = cand_key(d, (uint32_t)gc);
+                }
+            }
+        }
+        __syncthreads();
+        // compact the rows that could overflow during the next tile
+        for (int q = 0; q < kQB; q++) {
+            if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
+        }
+        (void)need;
+    }
+    for (int q = 0; q < kQB; q++) {
+        if (q0 + q < n) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
+    }
+    if (t < kQB && q0 + t < n) {
+        cand_cnt[q0 + t] = cnt[t];
+        cand_thr[q0 + t] = thr[t];
+    }
+}
+
+// Exact re-rank: FP64 distances of the candidates, sorted by (d, j); emits
+// the first k.  flag[i] = 1 when the error bound of the FP32 pre-selection
+// does not prove that the k best are among the candidates.
+template <typename X>
+__global__ __launch_bounds__(256) void k_knn_rerank(const X* __restrict__ Xm, int64_t n, int D,
+                                                    int k, const uint64_t* __restrict__ cand,
+                                                    const uint32_t* __restrict__ cand_cnt,
+                                                    const float* __restrict__ cand_thr,
+                                                    const float* __restrict__ nrm, float nrm_max,
+                                                    int32_t* __restrict__ idx,
+                                                    double* __restrict__ d2,
+                                                    uint32_t* __restrict__ flag) {
+    __shared__ double dv[512];
+    __shared__ uint32_t jv[512];
+    const int64_t i = blockIdx.x;
+    const int t = threadIdx.x;
+    const int m = (int)cand_cnt[i];
+    const uint64_t* lst = cand + i * kCap;
+    for (int e = t; e < 512; e += 256) {
+        if (e < m) {
+            const uint32_t j = (uint32_t)(lst[e] & 0xFFFFFFFFu);
+            double a = 0.0;
+            for (int d = 0; d < D; d++) {
+                const double v = to_f64(Xm[i * D + d]) - to_f64(Xm[(int64_t)j * D + d]);
+                a += v * v;
+            }
+            dv[e] = a;
+            jv[e] = j;
+        } else {
+            dv[e] = INFINITY;
+            jv[e] = 0xFFFFFFFFu;
+        }
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= 512; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+            const int b = a | j;
+            const double da = dv[a], db = dv[b];
+            const uint32_t ja = jv[a], jb = jv[b];
+            const bool gt = da > db || (da == db && ja > jb);
+            const bool up = (a & kk) == 0;
+            if (gt == up) {
+                dv[a] = db; dv[b] = da;
+                jv[a] = jb; jv[b] = ja;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = t; e < k; e += 256) {
+        idx[i * k + e] = (int32_t)jv[e];
+        d2[i * k + e] = dv[e];
+    }
+    if (t == 0) {
+        // |fp32(d) - d| <= (D + 4) 2^-24 (|x| + |y|)^2  (conservative)
+        const double tau = (double)cand_thr[i];
+        const double sx = sqrt((double)nrm[i]), sy = sqrt((double)nrm_max);
+        const double err = (double)(D + 4) * 0x1.0p-24 * (sx + sy) * (sx + sy) * 1.01;
+        flag[i] = (isfinite(tau) && !(dv[k - 1] < tau - err)) ? 1u : 0u;
+    }
+}
+
+// Exact fallback for rows the bound could not certify: block per row,
+// FP64 over all n, keeps a sorted top-k in LDS by repeated block passes.
+template <typename X>
+__global__ __launch_bounds__(256) void k_knn_exact_row(const X* __restrict__ Xm, int64_t n, int D,
+                                                       int k, const uint32_t* __restrict__ rows,
+                                                       int32_t* __restrict__ idx,
+                                                       double* __restrict__ d2) {
+    __shared__ double bd[256];
+    __shared__ uint32_t bj[256];
+    const int64_t i = rows[blockIdx.x];
+    const int t = threadIdx.x;
+    double last_d = -1.0;
+    uint32_t last_j = 0;
+    for (int r = 0; r < k; r++) {
+        // smallest (d, j) strictly greater than (last_d, last_j)
+        double bdv = INFINITY;
+        uint32_t bjv = 0xFFFFFFFFu;
+        for (int64_t j = t; j < n; j += 256) {
+            if (j == i) continue;
+            double a = 0.0;
+            for (int d = 0; d < D; d++) {
+                const double v = to_f64(Xm[i * D + d]) - to_f64(Xm[j * D + d]);
+                a += v * v;
+            }
+            const bool after = a > last_d || (a == last_d && (uint32_t)j > last_j);
+            const bool better = a < bdv || (a == bdv && (uint32_t)j < bjv);
+            if (after && better) { bdv = a; bjv = (uint32_t)j; }
+        }
+        bd[t] = bdv; bj[t] = bjv;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) {
+                const bool better = bd[t + o] < bd[t] || (bd[t + o] == bd[t] && bj[t + o] < bj[t]);
+                if (better) { bd[t] = bd[t + o]; bj[t] = bj[t + o]; }
+            }
+            __syncthreads();
+        }
+        last_d = bd[0];
+        last_j = bj[0];
+        if (t == 0) {
+            idx[i * k + r] = (int32_t)last_j;
+            d2[i * k + r] = last_d;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// perplexity calibration, one thread per row (FP64)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_perplexity(const double* __restrict__ d2, int64_t n,
+                                                    int k, double target, double tol,
+                                                    int max_iter, double* __restrict__ P,
+                                                    double* __restrict__ beta_out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double* d = d2 + i * k;
+    double* p = P + i * k;
+    double dmin = d[0];
+    for (int j = 1; j < k; j++) dmin = fmin(dmin, d[j]);
+    double b = 1.0, lo = 0.0, hi = 0.0, S = 0.0;
+    bool have_lo = false, have_hi = false;
+    for (int it = 0; it < max_iter; it++) {
+        S = 0.0;
+        double SD = 0.0;
+        for (int j = 0; j < k; j++) {
+            const double dj = d[j] - dmin;
+            const double e = exp(-b * dj);
+            p[j] = e;
+            S += e;
+            SD += dj * e;
+        }
+        const double H = log(S) + b * SD / S;
+        if (fabs(H - target) < tol || it == max_iter - 1) break;
+        if (H > target) {
+            lo = b; have_lo = true;
+            b = have_hi ? 0.5 * (b + hi) : 2.0 * b;
+        } else {
+            hi = b; have_hi = true;
+            b = have_lo ? 0.5 * (b + lo) : 0.5 * b;
+        }
+    }
+    for (int j = 0; j < k; j++) p[j] /= S;
+    if (beta_out) beta_out[i] = b;
+}
+
+// ---------------------------------------------------------------------------
+// symmetrisation
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_indeg(const int32_t* __restrict__ idx, int64_t m,
+                                               uint32_t* __restrict__ indeg) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < m) atomicAdd(&indeg[idx[e]], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_row_caps(const uint32_t* __restrict__ indeg, int64_t n,
+                                                  int k, int64_t* __restrict__ cap) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) cap[i] = (int64_t)k + indeg[i];
+    if (i == n) cap[n] = 0;
+}
+
+// exclusive scan of int64, three phases (block size 1024 elements)
+__global__ __launch_bounds__(256) void k_scan64_reduce(const int64_t* __restrict__ a, int64_t m,
+                                                       int64_t* __restrict__ bsum) {
+    __shared__ int64_t red[256];
+    const int64_t base = (int64_t)blockIdx.x * 1024;
+    int64_t s = 0;
+    for (int e = threadIdx.x; e < 1024; e += 256)
+        if (base + e < m) s += a[base + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan64_top(int64_t* __restrict__ bsum, int64_t nb) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < nb ? b + per : nb;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; i++) s += bsum[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = t ? part[t - 1] : 0;
+    for (int64_t i = b; i < e; i++) {
+        int64_t v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan64_apply(const int64_t* __restrict__ a, int64_t m,
+                                                      const int64_t* __restrict__ bsum,
+                                                      int64_t* __restrict__ out) {
+    __shared__ int64_t s[1024];
+    const int64_t base = (int64_t)blockIdx.x * 1024;
+    for (int e = threadIdx.x; e < 1024; e += 256) s[e] = base + e < m ? a[base + e] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = bsum[blockIdx.x];
+        for (int e = 0; e < 1024; e++) {
+            const int64_t v = s[e];
+            s[e] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256)
+        if (base + e < m) out[base + e] = s[e];
+}
+
+__global__ __launch_bounds__(256) void k_sym_fill(const int32_t* __restrict__ idx,
+                                                  const double* __restrict__ Pc, int64_t n, int k,
+                                                  const int64_t* __restrict__ off,
+                                                  uint32_t* __restrict__ fill,
+                                                  uint32_t* __restrict__ tcol,
+                                                  double* __restrict__ tval) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * (int64_t)k) return;
+    const int64_t i = e / k;
+    const int t = (int)(e - i * k);
+    const int32_t j = idx[e];
+    const double v = Pc[e];
+    tcol[off[i] + t] = (uint32_t)j;
+    tval[off[i] + t] = v;
+    const uint32_t slot = atomicAdd(&fill[j], 1u);
+    tcol[off[j] + k + slot] = (uint32_t)i;
+    tval[off[j] + k + slot] = v;
+}
+
+constexpr int kRowMax = 4096;
+
+// Sort one row by column (rank by counting, ties by position), merge the
+// (at most two) summands of each column, write the unique entries at the
+// row start and their number.
+__global__ __launch_bounds__(256) void k_sym_row(const int64_t* __restrict__ off,
+                                                 uint32_t* __restrict__ tcol,
+                                                 double* __restrict__ tval,
+                                                 int64_t* __restrict__ ucnt,
+                                                 uint32_t* __restrict__ overflow) {
+    __shared__ uint32_t c_in[kRowMax];
+    __shared__ uint32_t c_s[kRowMax];
+    __shared__ double v_s[kRowMax];
+    __shared__ uint32_t flags[kRowMax];
+    __shared__ uint32_t wsum[4];
+    const int64_t i = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t b = off[i];
+    const int len = (int)(off[i + 1] - b);
+    if (len > kRowMax) {
+        if (t == 0) { atomicOr(overflow, 1u); ucnt[i] = 0; }
+        return;
+    }
+    for (int e = t; e < len; e += 256) c_in[e] = tcol[b + e];
+    __syncthreads();
+    for (int e = t; e < len; e += 256) {
+        const uint32_t ce = c_in[e];
+        int r = 0;
+        for (int f = 0; f < len; f++) {
+            const uint32_t cf = c_in[f];
+            r += (cf < ce || (cf == ce && f < e)) ? 1 : 0;
+        }
+        c_s[r] = ce;
+        v_s[r] = tval[b + e];
+    }
+    __syncthreads();
+    // unique flags and their exclusive prefix (block scan over chunks of 256)
+    uint32_t base = 0;
+    for (int c0 = 0; c0 < len; c0 += 256) {
+        const int e = c0 + t;
+        const bool u = e < len && (e == 0 || c_s[e] != c_s[e - 1]);
+        const uint64_t bal = ballot64(u);
+        if (lane_id() == 0) wsum[t >> 6] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t pre = base + (uint32_t)__popcll(bal & lanemask_lt());
+        for (int q = 0; q < (t >> 6); q++) pre += wsum[q];
+        if (u) flags[e] = pre;
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+        base += tot;
+    }
+    for (int e = t; e < len; e += 256) {
+        if (e == 0 || c_s[e] != c_s[e - 1]) {
+            double v = v_s[e];
+            if (e + 1 < len && c_s[e + 1] == c_s[e]) v = v + v_s[e + 1];
+            tcol[b + flags[e]] = c_s[e];
+            tval[b + flags[e]] = v;
+        }
+    }
+    if (t == 0) ucnt[i] = base;
+}
+
+__global__ __launch_bounds__(256) void k_sym_write(const int64_t* __restrict__ off,
+                                                   const int64_t* __restrict__ rp, int64_t n,
+                                                   const uint32_t* __restrict__ tcol,
+                                                   const double* __restrict__ tval,
+                                                   uint32_t* __restrict__ col,
+                                                   double* __restrict__ val, double inv2n) {
+    const int64_t i = blockIdx.x;
+    const int64_t b = off[i], o = rp[i], m = rp[i + 1] - rp[i];
+    for (int64_t e = threadIdx.x; e < m; e += 256) {
+        col[o + e] = tcol[b + e];
+        val[o + e] = tval[b + e] * inv2n;
+    }
+}
+
+hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
+    const int64_t nb = ceil_div(m, 1024);
+    k_scan64_reduce<<<dim3((unsigned)nb), 256, 0, s>>>(a, m, tmp);
+    k_scan64_top<<<1, 1024, 0, s>>>(tmp, nb);
+    k_scan64_apply<<<dim3((unsigned)nb), 256, 0, s>>>(a, m, tmp, out);
+    return hipGetLastError();
+}
+
+template <typename X>
+hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx, double* d2,
+                     hipStream_t s, std::string* err) {
+    const int kp = (int)((int64_t)(k + kMargin) < n - 1 ? (k + kMargin) : (n - 1));
+    float* nrm = nullptr;
+    uint64_t* cand = nullptr;
+    uint32_t *ccnt = nullptr, *flag = nullptr;
+    float* cthr = nullptr;
+    hipError_t e = hipSuccess;
+    auto fail = [&](hipError_t x) {
+        hipFree(nrm); hipFree(cand); hipFree(ccnt); hipFree(flag); hipFree(cthr);
+        return x;
+    };
+    if ((e = hipMalloc(&nrm, sizeof(float) * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&cand, sizeof(uint64_t) * kCap * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&ccnt, sizeof(uint32_t) * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&cthr, sizeof(float) * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&flag, sizeof(uint32_t) * n)) != hipSuccess) return fail(e);
+    k_row_norms<X><<<dim3((unsigned)ceil_div(n, 4)), 256, 0, s>>>(Xm, n, D, nrm);
+    std::vector<float> hn(n);
+    if ((e = hipMemcpyAsync(hn.data(), nrm, sizeof(float) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    float nmax = 0.0f;
+    for (float v : hn) {
+        if (!isfinite(v)) {
+            if (err) *err = "X contains non-finite values";
+            return fail(hipErrorInvalidValue);
+        }
+        nmax = v > nmax ? v : nmax;
+    }
+    k_knn_candidates<X><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(Xm, n, D, nrm, kp, cand,
+                                                                         ccnt, cthr);
+    k_knn_rerank<X><<<dim3((unsigned)n), 256, 0, s>>>(Xm, n, D, k, cand, ccnt, cthr, nrm, nmax,
+                                                      idx, d2, flag);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+    std::vector<uint32_t> hf(n);
+    if ((e = hipMemcpyAsync(hf.data(), flag, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    std::vector<uint32_t> rows;
+    for (int64_t i = 0; i < n; i++)
+        if (hf[i]) rows.push_back((uint32_t)i);
+    if (!rows.empty()) {
+        // exact FP64 fallback for rows the FP32 bound did not certify
+        if ((e = hipMemcpyAsync(flag, rows.data(), sizeof(uint32_t) * rows.size(),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return fail(e);
+        k_knn_exact_row<X><<<dim3((unsigned)rows.size()), 256, 0, s>>>(Xm, n, D, k, flag, idx, d2);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    }
+    (void)err;
+    return fail(hipSuccess);
+}
+
+}  // namespace
+
+hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,
+               double* d2, hipStream_t s, std::string* err) {
+    switch (x_dtype) {
+        case PSNE_X_F32: return knn_typed<float>((const float*)X, n, D, k, idx, d2, s, err);
+        case PSNE_X_F64: return knn_typed<double>((const double*)X, n, D, k, idx, d2, s, err);
+        case PSNE_X_U8: return knn_typed<uint8_t>((const uint8_t*)X, n, D, k, idx, d2, s, err);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t perplexity(const double* d2, int64_t n, int32_t k, double u, double* P, double* beta,
+                      hipStream_t s) {
+    k_perplexity<<<dim3((unsigned)ceil_div(n, 256)), 256, 0, s>>>(d2, n, k, log(u), 1e-5, 200, P,
+                                                                  beta);
+    return hipGetLastError();
+}
+
+hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k,
+                      int64_t** row_ptr_out, uint32_t** col_out, double** val_out, int64_t* nnz_out,
+                      hipStream_t s) {
+    const int64_t m = n * (int64_t)k;
+    uint32_t *indeg = nullptr, *fill = nullptr, *tcol = nullptr, *ovf = nullptr;
+    int64_t *cap = nullptr, *off = nullptr, *tmp = nullptr, *ucnt = nullptr, *rp = nullptr;
+    double* tval = nullptr;
+    uint32_t* col = nullptr;
+    double* val = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        hipFree(indeg); hipFree(fill); hipFree(tcol); hipFree(ovf); hipFree(cap);
+        hipFree(off); hipFree(tmp); hipFree(ucnt); hipFree(tval);
+    };
+    auto fail = [&](hipError_t x) {
+        cleanup();
+        hipFree(rp); hipFree(col); hipFree(val);
+        return x;
+    };
+    const int64_t nb = ceil_div(n + 1, 1024);
+    if ((e = hipMalloc(&indeg, 4 * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&fill, 4 * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&ovf, 4)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&cap, 8 * (n + 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&off, 8 * (n + 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&tmp, 8 * (nb + 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&ucnt, 8 * (n + 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&rp, 8 * (n + 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&tcol, 4 * 2 * m)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&tval, 8 * 2 * m)) != hipSuccess) return fail(e);
+    hipMemsetAsync(indeg, 0, 4 * n, s);
+    hipMemsetAsync(fill, 0, 4 * n, s);
+    hipMemsetAsync(ovf, 0, 4, s);
+    k_indeg<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, m, indeg);
+    k_row_caps<<<dim3((unsigned)ceil_div(n + 1, 256)), 256, 0, s>>>(indeg, n, k, cap);
+    if ((e = scan_i64(cap, n + 1, off, tmp, s)) != hipSuccess) return fail(e);
+    k_sym_fill<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, Pc, n, k, off, fill, tcol, tval);
+    k_sym_row<<<dim3((unsigned)n), 256, 0, s>>>(off, tcol, tval, ucnt, ovf);
+    hipMemsetAsync(ucnt + n, 0, 8, s);
+    if ((e = scan_i64(ucnt, n + 1, rp, tmp, s)) != hipSuccess) return fail(e);
+    int64_t nnz = 0;
+    uint32_t hovf = 0;
+    if ((e = hipMemcpyAsync(&nnz, rp + n, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
+    if ((e = hipMemcpyAsync(&hovf, ovf, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    if (hovf) return fail(hipErrorNotSupported);
+    if ((e = hipMalloc(&col, 4 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&val, 8 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
+    k_sym_write<<<dim3((unsigned)n), 256, 0, s>>>(off, rp, n, tcol, tval, col, val,
+                                                  1.0 / (2.0 * (double)n));
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    cleanup();
+    *row_ptr_out = rp;
+    *col_out = col;
+    *val_out = val;
+    *nnz_out = nnz;
+    return hipSuccess;
+}
+
+}  // namespace psne

@@ -1,0 +1,286 @@
+"""ctypes binding of libpixelsne.so (the gfx950 PixelSNE library).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and the stream.  Loading
+fails loudly when the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpixelsne.so")
+
+PSNE_OK, PSNE_E_INVAL, PSNE_E_NOMEM, PSNE_E_DEVICE = 0, -1, -2, -3
+PSNE_E_NUMERIC, PSNE_E_STATE, PSNE_E_UNSUPPORTED = -4, -5, -6
+FP32, FP64 = 0, 1
+COM_MASS, COM_CELL_CENTER = 0, 1
+X_F32, X_F64, X_U8 = 0, 1, 2
+FRAME_PIXEL, FRAME_SCREEN, FRAME_Y = 0, 1, 2
+
+_STATUS = {PSNE_E_INVAL: "invalid argument", PSNE_E_NOMEM: "out of device memory",
+           PSNE_E_DEVICE: "device error", PSNE_E_NUMERIC: "non-finite values",
+           PSNE_E_STATE: "context unusable", PSNE_E_UNSUPPORTED: "unsupported"}
+
+
+class PixelSNEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("k", C.c_int32), ("theta", C.c_double),
+        ("exag_iters", C.c_int32), ("exaggeration", C.c_double), ("eta", C.c_double),
+        ("mom0", C.c_double), ("mom1", C.c_double), ("mom_switch", C.c_int32),
+        ("min_gain", C.c_double), ("eps", C.c_double), ("init_sigma", C.c_double),
+        ("seed", C.c_uint64), ("precision", C.c_int32), ("com_mode", C.c_int32),
+        ("x_dtype", C.c_int32), ("Y_init", C.c_void_p), ("stream", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("nnz", C.c_int64), ("n_nodes", C.c_int64),
+        ("r", C.c_int32), ("L", C.c_int32), ("k", C.c_int32),
+        ("precision", C.c_int32), ("com_mode", C.c_int32), ("iteration", C.c_int32),
+        ("s", C.c_double * 2), ("Z", C.c_double), ("level_size", C.c_int64 * 17),
+    ]
+
+
+# exported symbol -> (restype, argtypes)
+_vp, _i64, _i32, _d, _u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64
+SIGNATURES = {
+    "pixelsne_default_params": (None, [C.POINTER(Params)]),
+    "pixelsne_init": (_vp, [_vp, _i64, _i32, _d, _i32, _i32]),
+    "pixelsne_init_ex": (_vp, [_vp, _i64, _i32, _d, _i32, _i32, C.POINTER(Params)]),
+    "pixelsne_init_with_P": (_vp, [_i64, _i64, _vp, _vp, _vp, _i32, _i32, C.POINTER(Params)]),
+    "pixelsne_step": (C.c_int, [_vp, _i32]),
+    "pixelsne_step_async": (C.c_int, [_vp, _i32]),
+    "pixelsne_get_Y": (C.c_int, [_vp, _vp, _i32]),
+    "pixelsne_destroy": (None, [_vp]),
+    "pixelsne_last_error": (C.c_char_p, []),
+    "pixelsne_get_stats": (C.c_int, [_vp, C.POINTER(Stats)]),
+    "pixelsne_set_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _i32]),
+    "pixelsne_get_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32)]),
+    "pixelsne_gradient": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "pixelsne_export_tree": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
+    "pixelsne_export_P": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp]),
+    "pixelsne_knn": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "pixelsne_perplexity": (C.c_int, [_vp, _i64, _i32, _d, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libpixelsne.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1611_02568_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _err():
+    return load().pixelsne_last_error().decode(errors="replace")
+
+
+def _check(rc):
+    if rc != PSNE_OK:
+        raise PixelSNEError(rc, _err())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().pixelsne_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+_X_TYPES = {torch.float32: X_F32, torch.float64: X_F64, torch.uint8: X_U8}
+
+
+class Context:
+    """A PixelSNE embedding on the current GPU (wraps pixelsne_ctx*)."""
+
+    def __init__(self, handle, n, params: Params, keep=()):
+        if not handle:
+            raise PixelSNEError(PSNE_E_INVAL, _err())
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self.params = params
+        self._keep = keep
+        self.state_dtype = torch.float64 if params.precision == FP64 else torch.float32
+
+    # --- construction -----------------------------------------------------
+    @classmethod
+    def from_data(cls, X: torch.Tensor, perplexity: float, screen: int, Y_init=None, **kw):
+        """pixelsne_init_ex on a device matrix X [n, D] (float32/float64/uint8)."""
+        n, D = X.shape
+        p = default_params(**kw)
+        p.x_dtype = _X_TYPES[X.dtype]
+        if Y_init is not None:
+            Y_init = Y_init.to(device=X.device, dtype=torch.float64).contiguous()
+            p.Y_init = Y_init.data_ptr()
+        p.stream = _stream().value
+        h = load().pixelsne_init_ex(_ptr(X.contiguous()), n, D, float(perplexity), screen, screen,
+                                    C.byref(p))
+        return cls(h, n, p, (Y_init,))
+
+    @classmethod
+    def from_P(cls, row_ptr, col, val, screen: int, Y_init=None, **kw):
+        """pixelsne_init_with_P on a device CSR P (int64 / int32 / float64)."""
+        dev = torch.device("cuda")
+        row_ptr = torch.as_tensor(row_ptr, dtype=torch.int64).to(dev).contiguous()
+        col = torch.as_tensor(col, dtype=torch.int32).to(dev).contiguous()
+        val = torch.as_tensor(val, dtype=torch.float64).to(dev).contiguous()
+        n = row_ptr.numel() - 1
+        p = default_params(**kw)
+        if Y_init is not None:
+            Y_init = torch.as_tensor(Y_init, dtype=torch.float64).to(dev).contiguous()
+            p.Y_init = Y_init.data_ptr()
+        p.stream = _stream().value
+        h = load().pixelsne_init_with_P(n, val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                        screen, screen, C.byref(p))
+        return cls(h, n, p, (Y_init,))
+
+    @classmethod
+    def from_data_plain(cls, X: torch.Tensor, perplexity: float, screen: int):
+        """pixelsne_init with its default parameters (float32 X)."""
+        n, D = X.shape
+        h = load().pixelsne_init(_ptr(X.contiguous()), n, D, float(perplexity), screen, screen)
+        return cls(h, n, default_params())
+
+    # --- iteration ---------------------------------------------------------
+    def step(self, n_iter: int = 1):
+        _check(load().pixelsne_step(self._h, int(n_iter)))
+
+    def step_async(self, n_iter: int = 1):
+        _check(load().pixelsne_step_async(self._h, int(n_iter)))
+
+    def get_Y(self, frame: int = FRAME_Y) -> torch.Tensor:
+        dt = torch.int32 if frame == FRAME_SCREEN else torch.float64
+        out = torch.empty((self.n, 2), dtype=dt, device="cuda")
+        _check(load().pixelsne_get_Y(self._h, _ptr(out), int(frame)))
+        return out
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(load().pixelsne_get_stats(self._h, C.byref(s)))
+        return s
+
+    def set_state(self, z, s, u=None, g=None, iteration: int = 0):
+        z = torch.as_tensor(z, dtype=self.state_dtype).cuda().contiguous()
+        u = None if u is None else torch.as_tensor(u, dtype=self.state_dtype).cuda().contiguous()
+        g = None if g is None else torch.as_tensor(g, dtype=self.state_dtype).cuda().contiguous()
+        sv = (C.c_double * 2)(float(s[0]), float(s[1]))
+        _check(load().pixelsne_set_state(self._h, _ptr(z), _ptr(u), _ptr(g), sv, int(iteration)))
+
+    def get_state(self):
+        z = torch.empty((self.n, 2), dtype=self.state_dtype, device="cuda")
+        u = torch.empty_like(z)
+        g = torch.empty_like(z)
+        sv = (C.c_double * 2)()
+        it = C.c_int32()
+        _check(load().pixelsne_get_state(self._h, _ptr(z), _ptr(u), _ptr(g), sv, C.byref(it)))
+        return {"z": z, "u": u, "g": g, "s": (sv[0], sv[1]), "iteration": it.value}
+
+    def gradient(self, alpha: float = 1.0):
+        """Pixel-frame bracket B = alpha*A - R/Z and its parts at the current state."""
+        B = torch.empty((self.n, 2), dtype=self.state_dtype, device="cuda")
+        A = torch.empty_like(B)
+        R = torch.empty_like(B)
+        Zi = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        vis = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        Z = C.c_double()
+        _check(load().pixelsne_gradient(self._h, float(alpha), _ptr(B), _ptr(A), _ptr(R),
+                                        _ptr(Zi), _ptr(vis), C.byref(Z)))
+        return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": Z.value}
+
+    def export_tree(self):
+        st = self.stats()
+        L = st.L
+        sizes = (C.c_int64 * (L + 1))()
+        _check(load().pixelsne_export_tree(self._h, sizes, None, None, None, None, None))
+        sizes = [sizes[i] for i in range(L + 1)]
+        m = sum(sizes)
+        keys = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        pre = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        cnt = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        sm = torch.empty((max(m, 1), 2), dtype=torch.float64, device="cuda")
+        s2 = (C.c_int64 * (L + 1))()
+        _check(load().pixelsne_export_tree(self._h, s2, _ptr(keys), _ptr(perm), _ptr(pre),
+                                           _ptr(cnt), _ptr(sm)))
+        return {"level_size": sizes, "keys": keys, "perm": perm, "prefix": pre[:m],
+                "count": cnt[:m], "sum": sm[:m]}
+
+    def export_P(self):
+        nnz = C.c_int64()
+        _check(load().pixelsne_export_P(self._h, C.byref(nnz), None, None, None))
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        _check(load().pixelsne_export_P(self._h, C.byref(nnz), _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col[:nnz.value], val[:nnz.value]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pixelsne_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def knn(X: torch.Tensor, k: int):
+    """Device kNN of the rows of X: (idx int32 [n,k], d2 float64 [n,k])."""
+    n, D = X.shape
+    X = X.contiguous()
+    idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, k), dtype=torch.float64, device=X.device)
+    _check(load().pixelsne_knn(_ptr(X), n, D, _X_TYPES[X.dtype], int(k), _ptr(idx), _ptr(d2),
+                               _stream()))
+    return idx, d2
+
+
+def perplexity(d2: torch.Tensor, u: float):
+    """Device perplexity calibration: (P_cond float64 [n,k], beta float64 [n])."""
+    n, k = d2.shape
+    d2 = d2.to(torch.float64).contiguous()
+    P = torch.empty_like(d2)
+    beta = torch.empty(n, dtype=torch.float64, device=d2.device)
+    _check(load().pixelsne_perplexity(_ptr(d2), n, k, float(u), _ptr(P), _ptr(beta), _stream()))
+    return P, beta

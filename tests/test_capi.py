@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads and exports every function
+that include/pixelsne.h declares, the ctypes layouts match, and argument
+validation rejects bad calls before any device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pixelsne.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pixelsne_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def psne():
+    from paper_1611_02568_amd import pixelsne
+    pixelsne.load()
+    return pixelsne
+
+
+def test_every_declared_symbol_is_exported(psne):
+    names = _declared()
+    assert len(names) >= 15
+    lib = C.CDLL(psne.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding declares a signature for exactly these functions
+    assert sorted(psne.SIGNATURES) == names
+
+
+def test_params_layout_matches(psne):
+    p = psne.default_params()
+    assert p.struct_size == C.sizeof(psne.Params)
+    assert (p.theta, p.eta, p.exaggeration, p.exag_iters, p.mom_switch) == (0.5, 200.0, 12.0, 250, 250)
+    assert (p.mom0, p.mom1, p.min_gain, p.eps, p.init_sigma) == (0.5, 0.8, 0.01, 1e-6, 1e-4)
+
+
+def _init(psne, X, n, D, u, w, h, **kw):
+    p = psne.default_params(**kw)
+    return psne.load().pixelsne_init_ex(X, n, D, u, w, h, C.byref(p))
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((10, 4, 3.0, 512, 512), "device pointer"),        # host pointer for X
+    ((1, 4, 3.0, 512, 512), "n must be"),
+    ((10, 0, 3.0, 512, 512), "D must be"),
+    ((10, 4, -1.0, 512, 512), "perplexity"),
+    ((10, 4, 5.0, 512, 512), "k = floor"),             # k = 15 > n - 1
+    ((10, 4, 3.0, 512, 256), "square"),
+    ((10, 4, 3.0, 500, 500), "power of two"),
+    ((10, 4, 3.0, 1, 1), "screen size"),
+])
+def test_init_validation(psne, args, frag):
+    X = np.zeros((10, 4), np.float32)
+    h = _init(psne, X.ctypes.data, *args)
+    assert not h
+    assert frag in psne.load().pixelsne_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,frag", [({"theta": 1.0}, "theta"), ({"precision": 7}, "precision"),
+                                     ({"com_mode": 3}, "com_mode"), ({"struct_size": 8}, "struct_size"),
+                                     ({"eta": 0.0}, "eta")])
+def test_params_validation(psne, kw, frag):
+    X = np.zeros((10, 4), np.float32)
+    assert not _init(psne, X.ctypes.data, 10, 4, 3.0, 512, 512, **kw)
+    assert frag in psne.load().pixelsne_last_error().decode()
+
+
+def test_null_context_calls(psne):
+    lib = psne.load()
+    assert lib.pixelsne_step(None, 1) == psne.PSNE_E_INVAL
+    assert lib.pixelsne_get_Y(None, None, 0) == psne.PSNE_E_INVAL
+    lib.pixelsne_destroy(None)
+    assert lib.pixelsne_knn(None, 10, 4, 0, 20, None, None, None) == psne.PSNE_E_INVAL
+    assert lib.pixelsne_perplexity(None, 10, 5, -2.0, None, None, None) == psne.PSNE_E_INVAL

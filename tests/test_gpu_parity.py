@@ -1,0 +1,238 @@
+"""GPU path against the CPU oracle, element by element, through the C ABI.
+
+Bars: tree keys, permutation, cell prefixes and counts bit-exact; cell sums
+rel <= 1e-12; per-point visit counts exact (the opening test is evaluated in
+FP64 on both sides); gradient norm-wise rel <= 1e-4 (FP32 path) / 1e-10
+(FP64 path); Z rel <= 1e-6 / 1e-12; final KL within 1% of the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1611_02568_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+TOL_B = {0: 1e-4, 1: 1e-10}
+TOL_Z = {0: 1e-6, 1: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def psne():
+    from paper_1611_02568_amd import pixelsne
+    pixelsne.load()
+    assert torch.cuda.is_available()
+    return pixelsne
+
+
+def _ring_P(n):
+    rp = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    col = np.stack([(np.arange(n) - 1) % n, (np.arange(n) + 1) % n], 1)
+    col = np.sort(col, 1).ravel().astype(np.int32)
+    val = np.full(2 * n, 1.0 / (2 * n))
+    return rp, col, val
+
+
+def _state_dtype(prec):
+    return np.float64 if prec == 1 else np.float32
+
+
+def _ctx(psne, P, r, prec, com_mode=0, theta=0.5, y0=None):
+    n = len(P[0]) - 1
+    if y0 is None:
+        y0 = datagen.initial_embedding(n, seed=1)
+    return psne.Context.from_P(*P, screen=r, Y_init=torch.as_tensor(y0), precision=prec,
+                               com_mode=com_mode, theta=theta)
+
+
+def _tree_check(ctx, z64, r):
+    tr = ctx.export_tree()
+    keys, perm = oracle.sorted_order(z64, r)
+    assert np.array_equal(tr["keys"].cpu().numpy().view(np.uint32), keys)
+    assert np.array_equal(tr["perm"].cpu().numpy().astype(np.int64), perm)
+    otree = oracle.Tree(z64, r)
+    sizes = otree.level_sizes()
+    assert tr["level_size"] == sizes.tolist()
+    off = 0
+    pre = tr["prefix"].cpu().numpy().view(np.uint32)
+    cnt = tr["count"].cpu().numpy().view(np.uint32)
+    sm = tr["sum"].cpu().numpy()
+    for l in range(otree.L + 1):
+        m = int(sizes[l])
+        op, oc, os_ = otree.level(l)
+        assert np.array_equal(pre[off:off + m], op), f"prefix level {l}"
+        assert np.array_equal(cnt[off:off + m].astype(np.int64), oc), f"count level {l}"
+        np.testing.assert_allclose(sm[off:off + m], os_, rtol=1e-12, atol=1e-300)
+        off += m
+
+
+# --------------------------------------------------------------------------
+# tree: bit-exact against the oracle
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gen,n,r", [("uniform", 20037, 512), ("clustered", 30011, 1024),
+                                     ("clustered", 777, 64), ("uniform", 2, 2)])
+def test_tree_bit_exact(psne, prec, gen, n, r):
+    dt = _state_dtype(prec)
+    z = (datagen.uniform_pixels(n, r, seed=n, dtype=dt) if gen == "uniform"
+         else datagen.clustered_pixels(n, r, seed=n, spread=0.01, dtype=dt))
+    ctx = _ctx(psne, _ring_P(n), r, prec)
+    s = np.array([0.01, 0.013])
+    ctx.set_state(z, s)
+    ctx.gradient(1.0)
+    _tree_check(ctx, z.astype(np.float64), r)
+
+
+# --------------------------------------------------------------------------
+# gradient parity on the same state
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_problem():
+    X, _ = datagen.small_mixture(n=2000)
+    P = oracle.build_P(X, 30.0)
+    st = oracle.State(datagen.initial_embedding(2000, seed=datagen.seed_for(0, 1)), 512)
+    oracle.iterate(st, oracle.params(512), P, 300)
+    return X, P, st
+
+
+def _grad_check(psne, P, z, s, r, prec, theta, alpha, com_mode=0):
+    dt = _state_dtype(prec)
+    zt = np.minimum(z.astype(dt), np.nextafter(dt(r), dt(0)))   # keep 0 <= z < r after rounding
+    ctx = _ctx(psne, P, r, prec, com_mode=com_mode, theta=theta)
+    ctx.set_state(zt, s)
+    g = ctx.gradient(alpha)
+    z64 = zt.astype(np.float64)
+    og = oracle.gradient(z64, r, s, P, theta=theta, com_mode=com_mode, alpha=alpha)
+    assert np.array_equal(g["visits"].cpu().numpy(), og["visits"])
+    assert abs(g["Z"] - og["Z"]) <= TOL_Z[prec] * og["Z"]
+    for key in ("A", "R"):
+        got = g[key].double().cpu().numpy()
+        ref = og[key]
+        assert np.linalg.norm(got - ref) <= TOL_B[prec] * np.linalg.norm(ref), key
+    B = g["B"].double().cpu().numpy()
+    err = np.linalg.norm(B - og["B"]) / np.linalg.norm(og["B"])
+    assert err <= TOL_B[prec], err
+    # per point, relative to the size of its two parts
+    scale = alpha * np.linalg.norm(og["A"], axis=1) + np.linalg.norm(og["R"], axis=1) / og["Z"]
+    per = np.linalg.norm(B - og["B"], axis=1) / scale
+    assert per.max() <= 10 * TOL_B[prec], per.max()
+    return err
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.8])
+def test_gradient_parity(psne, small_problem, prec, theta):
+    X, P, st = small_problem
+    _grad_check(psne, P, st.z, st.s, 512, prec, theta, alpha=1.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_parity_cell_centre(psne, small_problem, prec):
+    X, P, st = small_problem
+    _grad_check(psne, P, st.z, st.s, 512, prec, 0.5, alpha=12.0, com_mode=1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_parity_initial_state(psne, small_problem, prec):
+    """Right after the first screen scaling (points spread as a Gaussian)."""
+    X, P, _ = small_problem
+    st = oracle.State(datagen.initial_embedding(2000, seed=3), 512)
+    _grad_check(psne, P, st.z, st.s, 512, prec, 0.5, alpha=12.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_degenerate_single_pixel(psne, prec):
+    """Every point in one pixel except the two that span the screen."""
+    n, r = 500, 256
+    rng = np.random.default_rng(9)
+    z = 100.0 + rng.random((n, 2)) * 0.999
+    z[0] = (0.0, 0.0)
+    z[1] = (255.5, 255.5)
+    z[2:40] = z[2]                          # exact duplicates
+    X, _ = datagen.small_mixture(n=n, D=10, seed=10)
+    P = oracle.build_P(X, 10.0)
+    _grad_check(psne, P, z, np.array([0.02, 0.02]), r, prec, 0.5, alpha=1.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_two_points(psne, prec):
+    P = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([0.5, 0.5]))
+    z = np.array([[10.3, 200.7], [400.2, 31.9]])
+    ctx = _ctx(psne, P, 512, prec, y0=np.array([[0.0, 0.0], [1.0, 1.0]]))
+    ctx.set_state(z.astype(_state_dtype(prec)), np.array([0.01, 0.02]))
+    g = ctx.gradient(1.0)
+    B = g["B"].double().cpu().numpy()
+    A = g["A"].double().cpu().numpy()
+    assert np.max(np.abs(B)) <= (1e-6 if prec == 0 else 1e-15) * np.max(np.abs(A))
+
+
+# --------------------------------------------------------------------------
+# setup: kNN, perplexity, P
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32", "u8"])
+def test_knn_parity(psne, dtype):
+    if dtype == "u8":
+        X, _ = datagen.uint8_mixture(n=3001, D=100)
+        k = 40
+    else:
+        X, _ = datagen.small_mixture(n=2000, dtype=np.float64 if dtype == "f64" else np.float32)
+        k = 90
+    idx, d2 = psne.knn(torch.as_tensor(X).cuda(), k)
+    oi, od = oracle.knn(X.astype(np.float64), k)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+    np.testing.assert_allclose(d2.cpu().numpy(), od, rtol=1e-13, atol=0)
+
+
+def test_perplexity_parity(psne):
+    X, _ = datagen.small_mixture(n=2000)
+    _, od = oracle.knn(X, 90)
+    P, beta = psne.perplexity(torch.as_tensor(od).cuda(), 30.0)
+    oP, ob, _ = oracle.perplexity(od, 30.0)
+    np.testing.assert_allclose(P.cpu().numpy(), oP, rtol=1e-9, atol=1e-300)
+    np.testing.assert_allclose(beta.cpu().numpy(), ob, rtol=1e-9)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_P_parity(psne, prec):
+    X, _ = datagen.small_mixture(n=2000)
+    ctx = psne.Context.from_data(torch.as_tensor(X).cuda(), 30.0, 512, precision=prec,
+                                 Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=2)))
+    rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
+    orp, ocol, oval = oracle.build_P(X, 30.0)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    tol = 1e-9 if prec == 1 else 6e-8
+    np.testing.assert_allclose(val, oval, rtol=tol)
+    assert abs(val.sum() - 1.0) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# optimisation: screen scaling invariants and final KL
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_normalisation_after_steps(psne, small_problem, prec):
+    X, P, _ = small_problem
+    ctx = _ctx(psne, P, 512, prec)
+    for _ in range(3):
+        ctx.step(7)
+        Y = ctx.get_Y(psne.FRAME_PIXEL).cpu().numpy()
+        S = ctx.get_Y(psne.FRAME_SCREEN).cpu().numpy()
+        assert np.all(Y.min(0) == 0.0) and np.all(Y < 512)
+        assert np.all(S.max(0) == 511) and np.all(S.min(0) == 0)
+        assert np.array_equal(S, np.minimum(np.floor(Y), 511).astype(np.int32))
+    assert ctx.stats().iteration == 21
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_final_kl_matches_oracle(psne, small_problem, prec):
+    """1,000 iterations from the same initial embedding: KL within 1%."""
+    X, P, _ = small_problem
+    y0 = datagen.initial_embedding(2000, seed=datagen.seed_for(0, 1))
+    ctx = _ctx(psne, P, 512, prec, y0=y0)
+    ctx.step(1000)
+    st = ctx.get_state()
+    kl_gpu = oracle.kl(st["z"].double().cpu().numpy(), np.array(st["s"]), P)
+    ost = oracle.State(y0, 512)
+    oracle.iterate(ost, oracle.params(512), P, 1000)
+    kl_orc = oracle.kl(ost.z, ost.s, P)
+    assert abs(kl_gpu - kl_orc) <= 0.01 * kl_orc, (kl_gpu, kl_orc)
