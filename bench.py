@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the PixelSNE iteration on one MI355X: points x iterations / s.
+
+Workload: 1,000,000 x 128 float32 points from a 100-component Gaussian mixture
+with Zipf(1.1) component sizes and per-component variance U(0.5, 2),
+perplexity 50 (k = 150), 2048 x 2048 screen, theta = 0.5.  One step is one
+full iteration of the method (pixel snap + Morton keys, sort, P-Quadtree,
+Barnes-Hut repulsion, Z, sparse attraction + gains/momentum step, screen
+scaling) over all points; the one-time setup (kNN, perplexity, P) is timed
+separately.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  See the design doc for the byte / flop counts used by the
+roofline numbers.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "points×iters/sec at n=1M (fp32 vs fp64) + time-to-KL within 1%, MLP init vs plain"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the rate of FP64 and of
+# non-packed FP32 vector arithmetic (packed FP32 is disabled in this build)
+VALU_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tree_bytes(n, n_nodes, sb):
+    """Algorithmic HBM bytes of snap + sort + cell build for one iteration:
+    read zh and write z (2 sb each), write and read (key, index) once in and
+    once out of the sort (4 x 8 B), gather z in sorted order (2 sb) and write
+    each cell's count (4 B) and FP64 sums (16 B)."""
+    return n * (2 * 2 * sb + 4 * 8 + 2 * sb) + n_nodes * 20
+
+
+def attract_bytes(n, nnz, sb):
+    """Algorithmic HBM bytes of attraction + update for one iteration: CSR
+    column (4 B) and value (sb) per nonzero, row pointer (8 B), z_i once and
+    z_j compulsory once (2 x 2 sb), R (2 sb), u and g read and written
+    (4 x 2 sb), zh written (2 sb)."""
+    return nnz * (4 + sb) + n * (8 + 8 * 2 * sb)
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+
+    from paper_1611_02568_amd import datagen, pixelsne
+
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"[bench] generating {n} x 128 mixture")
+    X, _, _ = datagen.zipf_mixture_1m(n=n)
+    y0 = torch.as_tensor(datagen.initial_embedding(n, seed=datagen.seed_for(2, 1)))
+    Xd = torch.from_numpy(X).cuda()
+    torch.cuda.synchronize()
+
+    log("[bench] setup (kNN, perplexity, P) in FP64")
+    t0 = time.perf_counter()
+    ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    del Xd
+    rp, col, val = ctx64.export_P()
+    ctx32 = pixelsne.Context.from_P(rp, col, val, 2048, Y_init=y0, precision=pixelsne.FP32)
+    del rp, col, val
+    nnz = ctx32.stats().nnz
+    log(f"[bench] setup {setup_s:.2f} s, nnz {nnz} ({nnz / n:.1f} per row)")
+
+    out = {}
+    for name, ctx, sb in (("fp32", ctx32, 4), ("fp64", ctx64, 8)):
+        if name == "fp64" and args.no_fp64:
+            continue
+        ctx.step(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        ctx.step_async(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = ctx.stats()
+        log(f"[bench] {name}: {args.steps} iterations in {ms:.1f} ms")
+        # the same number of iterations again, with per-pass HIP events
+        pt = ctx.step_profiled(args.steps).as_dict()
+        g = ctx.gradient(1.0)
+        vis = g["visits"].double().mean().item()
+        used = g["used"].double().mean().item()
+        n_nodes = ctx.stats().n_nodes
+        K = args.steps
+        per = {k[:-3]: v / K for k, v in pt.items() if k.endswith("_ms")}
+        tree_ms = per["snap"] + per["sort"] + per["tree"]
+        att_ms = per["attract"]
+        tb = tree_bytes(n, n_nodes, sb)
+        ab = attract_bytes(n, nnz, sb)
+        flops = n * (8.0 * vis + 9.0 * used)
+        out[name] = {
+            "value": n * K / (ms / 1e3),
+            "ms_per_step": ms / K,
+            "pass_ms": per,
+            "iteration": st.iteration,
+            "mean_visits": vis,
+            "mean_used_cells": used,
+            "cells": n_nodes,
+            "tree_build": {"ms": tree_ms, "bytes": tb, "GBps": tb / (tree_ms * 1e6),
+                           "frac_hbm": tb / (tree_ms * 1e6) / HBM_PEAK_GBS},
+            "attract": {"ms": att_ms, "bytes": ab, "GBps": ab / (att_ms * 1e6),
+                        "frac_hbm": ab / (att_ms * 1e6) / HBM_PEAK_GBS},
+            "traverse": {"ms": per["traverse"], "flops": flops,
+                         "TFLOPs": flops / (per["traverse"] * 1e9)},
+        }
+        log(f"[bench] {name}: passes {json.dumps({k: round(v, 4) for k, v in per.items()})}")
+    return out, setup_s, nnz
+
+
+def cpu_baseline(sample_n: int, min_seconds: float):
+    """The oracle as it stands on this host's cores, on the first sample_n
+    points of the same mixture (rows are shuffled, so a random sample)."""
+    import numpy as np
+
+    import oracle
+    from paper_1611_02568_amd import datagen
+
+    X, _, _ = datagen.zipf_mixture_1m(n=1_000_000)
+    Xs = X[:sample_n].astype(np.float64)
+    del X
+    P = oracle.build_P(Xs, 50.0, k=150)
+    st = oracle.State(datagen.initial_embedding(sample_n, seed=7), 2048)
+    p = oracle.params(2048)
+    oracle.iterate(st, p, P, 2)
+    iters, t = 0, 0.0
+    while t < min_seconds and iters < 1000:
+        t0 = time.perf_counter()
+        oracle.iterate(st, p, P, 10)
+        t += time.perf_counter() - t0
+        iters += 10
+    return {"value": sample_n * iters / t, "unit": "points*iters/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{sample_n} points of the same 1M x 128 mixture (its own brute-force "
+                      f"P, perplexity 50, k 150), screen 2048, theta 0.5, {iters} iterations "
+                      f"after 2 warm-up iterations, FP64, OpenMP; setup not timed"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
+                                   "note only (DESIGN.md), so --gpus must be 1"}))
+        sys.exit(2)
+
+    res, setup_s, nnz = run_gpu(args)
+    main32 = res["fp32"]
+    # dominant kernel of the FP32 iteration
+    per = main32["pass_ms"]
+    dom = max(per, key=per.get)
+    if dom == "traverse":
+        ach = main32["traverse"]["TFLOPs"]
+        roof = {"bound": "alu", "kernel": "k_traverse<float>", "achieved": ach,
+                "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
+                "traffic": None}
+    elif dom == "attract":
+        ach = main32["attract"]["GBps"]
+        roof = {"bound": "hbm", "kernel": "k_attract<float,0>", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None}
+    else:
+        ach = main32["tree_build"]["GBps"]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(args.cpu_sample, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": main32["value"],
+        "unit": "points*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n:,} x 128 fp32 Zipf(1.1) 100-component Gaussian mixture, "
+                               "perplexity 50, k 150, screen 2048x2048, theta 0.5, FP32 path "
+                               "(FP64 Z, cell sums and opening test)",
+                   "n": args.n, "D": 128, "perplexity": 50, "k": 150, "screen": 2048,
+                   "theta": 0.5, "nnz": nnz},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64": res.get("fp64") and {"value": res["fp64"]["value"],
+                                     "ms_per_step": res["fp64"]["ms_per_step"]},
+        "setup_s": setup_s,
+        "passes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,10 @@ typedef struct {
     const double* Y_init;     /* optional device float64 [n][2] initial embedding
                                  (y frame); NULL => N(0, init_sigma^2) from seed */
     void* stream;             /* hipStream_t for all work; NULL => null stream */
+    int32_t reorder_every;    /* renumber points internally by their Morton order every
+                                 this many iterations (memory locality of the sparse
+                                 attraction); 0 = never [10].  Results are reported in the
+                                 caller's numbering either way. */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -127,6 +131,23 @@ psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter);
 /* Enqueue the iterations without the final check (returns after enqueueing). */
 psne_status pixelsne_step_async(pixelsne_ctx* c, int32_t n_iter);
 
+/* Time spent in each pass, summed over the iterations of one call (ms),
+ * measured with HIP events recorded on the context's stream between passes. */
+typedef struct {
+    double snap_ms;       /* pending screen scaling + pixel + Morton key */
+    double sort_ms;       /* radix sort of (key, index) */
+    double tree_ms;       /* cell numbering, counts and FP64 sums */
+    double traverse_ms;   /* Barnes-Hut repulsion */
+    double zsum_ms;       /* Z reduction */
+    double attract_ms;    /* attraction + gains/momentum step */
+    double finalize_ms;   /* screen scaling factors */
+    double reorder_ms;    /* internal renumbering (every params.reorder_every iterations) */
+    int32_t iterations;
+} pixelsne_pass_times;
+
+/* As pixelsne_step, also returning per-pass times.  Synchronises. */
+psne_status pixelsne_step_profiled(pixelsne_ctx* c, int32_t n_iter, pixelsne_pass_times* out);
+
 /* Write the current embedding to device memory `out` in the given frame
  * (types per PSNE_FRAME_*; [n][2], caller-owned).  Asynchronous. */
 psne_status pixelsne_get_Y(const pixelsne_ctx* c, void* out, int32_t frame);
@@ -168,12 +189,13 @@ psne_status pixelsne_get_state(const pixelsne_ctx* c, void* z, void* u, void* g,
  *   R_i = Barnes-Hut sum of m w^2 (z_i - c), Z = sum_i Z_i   (Eq. 5, 11, 12),
  * so that dC/dy_i,d = 4 s_d B_i,d.  Outputs are device arrays of the state type
  * ([n][2] for B, A, R) and may be NULL; Zi device float64 [n]; visits device
- * uint32 [n] (cells reached by each point's traversal); Z host double.
+ * uint32 [n] (cells reached by each point's traversal); used device uint32 [n]
+ * (cells that entered R_i and Z_i); Z host double.
  * Also leaves the tree of the current state for pixelsne_export_tree.
  * Synchronises the stream.
  */
 psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, void* R,
-                              double* Zi, uint32_t* visits, double* Z);
+                              double* Zi, uint32_t* visits, uint32_t* used, double* Z);
 
 /*
  * Export the tree built by the last pixelsne_gradient / iteration.

@@ -49,6 +49,7 @@ psne_status check_params(const pixelsne_params* p) {
     if (p->x_dtype != PSNE_X_F32 && p->x_dtype != PSNE_X_F64 && p->x_dtype != PSNE_X_U8)
         return invalid("unknown x_dtype");
     if (p->exag_iters < 0 || p->mom_switch < 0) return invalid("negative schedule length");
+    if (p->reorder_every < 0) return invalid("reorder_every must be >= 0");
     return PSNE_OK;
 }
 
@@ -120,8 +121,11 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
         if ((e = dalloc(c, &tb.idx[h], 4 * (size_t)n)) != hipSuccess) return e;
     }
     if ((e = dalloc(c, &tb.hist, 4 * 256 * (size_t)tb.sort_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.dtot, 4 * 256)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.lvl_cnt, 4 * (size_t)(c->L + 1) * tb.tree_blocks)) != hipSuccess) return e;
-    if ((e = dalloc(c, &tb.lvl_off, 4 * (size_t)(c->L + 1) * tb.tree_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.ltot, 4 * (size_t)(c->L + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.wfirst, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.wlast, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.parent, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.first_child, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.arrive, 4 * (size_t)mx)) != hipSuccess) return e;
@@ -129,6 +133,18 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.leaf_of, 4 * (size_t)n)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.zs, v2)) != hipSuccess) return e;
+    // renumbering: spare copies of P and of the state, index maps
+    if ((e = dalloc(c, &c->orig, 4 * (size_t)n)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->orig2, 4 * (size_t)n)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->inv, 4 * (size_t)n)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->row_ptr2, 8 * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->col2, 4 * (size_t)c->nnz)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->val2, state_bytes(c) * (size_t)c->nnz)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->zh2, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->u2, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->g2, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->len_tmp, 8 * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->scan_tmp, 8 * (size_t)scan_i64_tmp_len(n + 1))) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -157,7 +173,8 @@ psne_status finish_init(pixelsne_ctx* c) {
     if (e == hipErrorNotSupported) return PSNE_E_UNSUPPORTED;
     if (e != hipSuccess) return device_error(c, e, "allocation");
     if (c->prm.Y_init && !is_device_ptr(c->prm.Y_init)) return invalid("Y_init must be a device pointer");
-    e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
+    e = run_identity_order(c);
+    if (e == hipSuccess) e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_error(c, e, "initial embedding");
     return PSNE_OK;
@@ -193,6 +210,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->x_dtype = PSNE_X_F32;
     p->Y_init = nullptr;
     p->stream = nullptr;
+    p->reorder_every = 10;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -227,8 +245,7 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
     if (e == hipSuccess)
         e = psne::symmetrize(idx, Pc, n, (int32_t)k, &rp, &col, &val64, &c->nnz, c->stream);
     if (e != hipSuccess) {
-        if (e == hipErrorNotSupported) set_error("a row of P has more than 4096 entries");
-        else if (!err.empty()) set_error(err);
+        if (!err.empty()) set_error(err);
         else device_error(c, e, "building P");
         cleanup();
         free_ctx(c);
@@ -310,6 +327,36 @@ psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter) {
     return PSNE_OK;
 }
 
+psne_status pixelsne_step_profiled(pixelsne_ctx* c, int32_t n_iter, pixelsne_pass_times* out) {
+    if (!c || !out) return invalid("null argument");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (n_iter < 0) return invalid("n_iter must be >= 0");
+    memset(out, 0, sizeof(*out));
+    std::vector<hipEvent_t> ev((size_t)n_iter * 9);
+    hipError_t e = hipSuccess;
+    size_t made = 0;
+    for (; made < ev.size() && e == hipSuccess; made++) e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) made--;
+    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++) e = run_iteration_timed(c, &ev[9 * it]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double* acc[8] = {&out->snap_ms, &out->sort_ms, &out->tree_ms, &out->traverse_ms,
+                      &out->zsum_ms, &out->attract_ms, &out->finalize_ms, &out->reorder_ms};
+    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
+        for (int p = 0; p < 8 && e == hipSuccess; p++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[9 * it + p], ev[9 * it + p + 1]);
+            *acc[p] += ms;
+        }
+    for (size_t i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return device_error(c, e, "step_profiled");
+    out->iterations = n_iter;
+    int32_t bad = 0;
+    e = hipMemcpy(&bad, &c->sc->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_error(c, e, "step_profiled");
+    if (bad) { set_error("non-finite positions"); return PSNE_E_NUMERIC; }
+    return PSNE_OK;
+}
+
 psne_status pixelsne_get_Y(const pixelsne_ctx* c, void* out, int32_t frame) {
     if (!c) return invalid("null context");
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
@@ -388,22 +435,20 @@ psne_status pixelsne_get_state(const pixelsne_ctx* c, void* z, void* u, void* g,
 }
 
 psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, void* R,
-                              double* Zi, uint32_t* visits, double* Z) {
+                              double* Zi, uint32_t* visits, uint32_t* used, double* Z) {
     if (!c) return invalid("null context");
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
-    const void* ptrs[5] = {B, A, R, Zi, visits};
+    const void* ptrs[6] = {B, A, R, Zi, visits, used};
     for (const void* p : ptrs)
         if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
     if (!isfinite(alpha)) return invalid("alpha must be finite");
     hipError_t e = run_snap(c);
     if (e == hipSuccess) e = run_sort(c);
     if (e == hipSuccess) e = run_tree(c);
-    if (e == hipSuccess) e = run_traverse(c, visits, Zi);
+    if (e == hipSuccess) e = run_traverse(c, visits, used, Zi);
     if (e == hipSuccess) e = run_zsum(c);
     if (e == hipSuccess) e = run_attract(c, 1, alpha, A, B);
-    if (e == hipSuccess && R)
-        e = hipMemcpyAsync(R, c->R, (size_t)c->n * 2 * state_bytes(c), hipMemcpyDeviceToDevice,
-                           c->stream);
+    if (e == hipSuccess && R) e = run_to_user_v2(c, c->R, R);
     double hz = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hz, &c->sc->Z, 8, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -437,12 +482,7 @@ psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_
     for (const void* p : ptrs)
         if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
     hipError_t e = hipSuccess;
-    if (row_ptr)
-        e = hipMemcpyAsync(row_ptr, c->row_ptr, 8 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice,
-                           c->stream);
-    if (e == hipSuccess && col)
-        e = hipMemcpyAsync(col, c->col, 4 * (size_t)c->nnz, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess && val) e = run_export_val(c, val);
+    if (row_ptr || col || val) e = run_export_P(c, row_ptr, col, val);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_P");
     return PSNE_OK;

@@ -16,10 +16,13 @@ struct TreeBufs {
     uint32_t* idx[2] = {nullptr, nullptr};   // ... and point indices
     int sorted = 0;                          // which half holds the sorted result
     uint32_t* hist = nullptr;                // [256][sort blocks]
+    uint32_t* dtot = nullptr;                // [256] digit totals of one pass
     int64_t sort_blocks = 0;
-    uint32_t* lvl_cnt = nullptr;             // [levels][tree blocks]
-    uint32_t* lvl_off = nullptr;
+    uint32_t* lvl_cnt = nullptr;             // [levels][tree blocks], scanned in place
+    uint32_t* ltot = nullptr;                // [levels] cells per level
     int64_t tree_blocks = 0;
+    double2* wfirst = nullptr;               // [n / 64] per-wave partial leaf sums
+    double2* wlast = nullptr;
     uint32_t* parent = nullptr;              // [max_nodes]
     uint32_t* first_child = nullptr;         // [max_nodes]
     uint32_t* arrive = nullptr;              // [max_nodes]
@@ -59,6 +62,22 @@ struct pixelsne_ctx {
     psne::DevScalars* sc = nullptr;
     psne::TreeBufs tb;
 
+    // Internal order: points are renumbered by their Morton order every
+    // prm.reorder_every iterations so that the neighbours of a CSR row sit
+    // close in memory.  orig[i] is the caller's index of internal point i.
+    uint32_t* orig = nullptr;
+    uint32_t* orig2 = nullptr;
+    uint32_t* inv = nullptr;
+    int64_t* row_ptr2 = nullptr;
+    uint32_t* col2 = nullptr;
+    void* val2 = nullptr;
+    void* zh2 = nullptr;
+    void* u2 = nullptr;
+    void* g2 = nullptr;
+    int64_t* len_tmp = nullptr;              // [n + 1]
+    int64_t* scan_tmp = nullptr;
+    int32_t since_reorder = 0;
+
     std::vector<void*> allocs;
 };
 
@@ -71,12 +90,14 @@ psne_status device_error(pixelsne_ctx* c, hipError_t e, const char* where);
 hipError_t run_snap(pixelsne_ctx* c);
 hipError_t run_sort(pixelsne_ctx* c);
 hipError_t run_tree(pixelsne_ctx* c);
-hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, double* Zi);
+hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi);
 hipError_t run_zsum(pixelsne_ctx* c);
 // mode 0: gradient step; mode 1: write A and B only (no update)
 hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B);
 hipError_t run_finalize(pixelsne_ctx* c, int advance);
 hipError_t run_iteration(pixelsne_ctx* c);
+// one iteration with events recorded before each pass and after the last (9 events)
+hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev);
 hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma);
 hipError_t run_get_y(const pixelsne_ctx* c, void* out, int frame);
 hipError_t run_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g);
@@ -84,7 +105,16 @@ hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g);
 hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm,
                            uint32_t* prefix, uint32_t* count, double* sum);
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
-hipError_t run_export_val(const pixelsne_ctx* c, double* out);
+// renumbering (reorder.hip)
+hipError_t run_reorder(pixelsne_ctx* c);
+hipError_t run_identity_order(pixelsne_ctx* c);
+// P in the caller's numbering, columns ascending; row_ptr/col/val device, caller-owned
+hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, double* val);
+// scatter an internal-order [n][2] state-type array to caller order
+hipError_t run_to_user_v2(const pixelsne_ctx* c, const void* in, void* out);
+hipError_t run_map_perm(const pixelsne_ctx* c, const uint32_t* perm, uint32_t* out);
+hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s);
+int64_t scan_i64_tmp_len(int64_t m);
 
 // setup passes (setup.hip)
 hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,

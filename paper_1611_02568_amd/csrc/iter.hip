@@ -76,28 +76,32 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t* __restrict__
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of m uint32 values in place, one block
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t m) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t b = t * per, e = b + per < m ? b + per : m;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; i++) s += a[i];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = t >= o ? part[t - o] : 0u;
+// Exclusive scan of each row of a [rows][len] uint32 array in place (one block
+// per row, coalesced chunks of 256); the row totals go to tot[row].
+__global__ __launch_bounds__(kBlock) void k_rows_scan(uint32_t* __restrict__ a, int64_t len,
+                                                      uint32_t* __restrict__ tot) {
+    __shared__ uint32_t ws[4];
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    uint32_t* row = a + (int64_t)blockIdx.x * len;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < len; c0 += kBlock) {
+        const int64_t i = c0 + t;
+        const uint32_t v = i < len ? row[i] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) ws[w] = x;
         __syncthreads();
-        part[t] += v;
+        uint32_t pre = carry;
+        for (int q = 0; q < w; q++) pre += ws[q];
+        if (i < len) row[i] = pre + x - v;
+        carry += ws[0] + ws[1] + ws[2] + ws[3];
         __syncthreads();
     }
-    uint32_t run = t ? part[t - 1] : 0u;
-    for (int64_t i = b; i < e; i++) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
+    if (t == 0) tot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
@@ -106,11 +110,27 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
                                                        uint32_t* __restrict__ vout, int64_t n,
                                                        int shift,
                                                        const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ dtot,
                                                        int64_t nblocks) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
-    const int t = threadIdx.x, w = t >> 6;
-    run[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    {
+        // digit bases: exclusive scan of the 256 digit totals
+        const uint32_t v = dtot[t];
+        uint32_t x = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) wcnt[0][w] = x;
+        __syncthreads();
+        uint32_t pre = x - v;
+        for (int q = 0; q < w; q++) pre += wcnt[0][q];
+        run[t] = pre + hist[(int64_t)t * nblocks + blockIdx.x];
+        __syncthreads();
+    }
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int j = 0; j < kRsItems; j++) {
         const int64_t p = base + j * kBlock + t;
@@ -169,56 +189,33 @@ __global__ __launch_bounds__(kBlock) void k_tree_count(const uint32_t* __restric
     if (t <= L) cnt[(int64_t)t * nb + blockIdx.x] = wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
 }
 
-__global__ __launch_bounds__(1024) void k_tree_scan(const uint32_t* __restrict__ cnt,
-                                                    uint32_t* __restrict__ off, int64_t nb,
-                                                    int L, DevScalars* __restrict__ sc) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    uint32_t base = 0;
-    for (int l = 0; l <= L; l++) {
-        const uint32_t* a = cnt + (int64_t)l * nb;
-        uint32_t* o = off + (int64_t)l * nb;
-        const int64_t per = (nb + 1023) / 1024;
-        const int64_t b = t * per, e = b + per < nb ? b + per : nb;
-        uint32_t s = 0;
-        for (int64_t i = b; i < e; i++) s += a[i];
-        part[t] = s;
-        __syncthreads();
-        for (int q = 1; q < 1024; q <<= 1) {
-            uint32_t v = t >= q ? part[t - q] : 0u;
-            __syncthreads();
-            part[t] += v;
-            __syncthreads();
-        }
-        uint32_t run = t ? part[t - 1] : 0u;
-        for (int64_t i = b; i < e; i++) {
-            o[i] = run;
-            run += a[i];
-        }
-        const uint32_t tot = part[1023];
-        if (t == 0) {
-            sc->level_size[l] = tot;
-            sc->level_base[l] = base;
-        }
-        base += tot;
-        __syncthreads();
-    }
-    if (t == 0) {
-        sc->level_base[L + 1] = base;
-        sc->n_nodes = base;
-    }
-}
-
 // Number each cell: for every level, the rank of the cell holding sorted
 // position s.  Positions that open a cell write its start, parent and first
 // child (children of a cell are consecutive in the next level).
 __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     const uint32_t* __restrict__ keys, int64_t n, int L, const uint32_t* __restrict__ off,
-    int64_t nb, const DevScalars* __restrict__ sc, uint32_t* __restrict__ parent,
-    uint32_t* __restrict__ first_child, uint32_t* __restrict__ arrive, Node* __restrict__ nodes,
-    uint32_t* __restrict__ leaf_of) {
+    int64_t nb, const uint32_t* __restrict__ ltot, DevScalars* __restrict__ sc,
+    uint32_t* __restrict__ parent, uint32_t* __restrict__ first_child,
+    uint32_t* __restrict__ arrive, Node* __restrict__ nodes, uint32_t* __restrict__ leaf_of) {
     __shared__ uint32_t wc[4][kMaxLevels];
+    __shared__ uint32_t lbase[kMaxLevels + 1];
     const int t = threadIdx.x, w = t >> 6;
+    if (t == 0) {
+        uint32_t b = 0;
+        for (int l = 0; l <= L; l++) {
+            lbase[l] = b;
+            b += ltot[l];
+        }
+        lbase[L + 1] = b;
+        if (blockIdx.x == 0) {
+            for (int l = 0; l <= L; l++) {
+                sc->level_size[l] = ltot[l];
+                sc->level_base[l] = lbase[l];
+            }
+            sc->level_base[L + 1] = b;
+            sc->n_nodes = b;
+        }
+    }
     const int64_t s = (int64_t)blockIdx.x * kBlock + t;
     const bool valid = s < n;
     const int l0 = valid ? first_new_level(keys, s, L) : L + 1;
@@ -241,18 +238,16 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
         }
     }
     if (!valid) return;
-    leaf_of[s] = sc->level_base[L] + rank[L];
+    leaf_of[s] = lbase[L] + rank[L];
 #pragma unroll
     for (int l = 0; l < kMaxLevels; l++) {
         if (l <= L && l0 <= l) {
-            const uint32_t gid = sc->level_base[l] + rank[l];
+            const uint32_t gid = lbase[l] + rank[l];
             nodes[gid].start = (uint32_t)s;
             nodes[gid].level = (uint32_t)l;
             arrive[gid] = 0;
-            parent[gid] = l > 0 ? sc->level_base[l > 0 ? l - 1 : 0] + rank[l > 0 ? l - 1 : 0]
-                                : 0xFFFFFFFFu;
-            first_child[gid] = l < L ? sc->level_base[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L]
-                                     : 0u;
+            parent[gid] = l > 0 ? lbase[l > 0 ? l - 1 : 0] + rank[l > 0 ? l - 1 : 0] : 0xFFFFFFFFu;
+            first_child[gid] = l < L ? lbase[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L] : 0u;
         }
     }
 }
@@ -279,28 +274,85 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, double2* __
     nsum[g] = double2{sx, sy};
 }
 
-// Leaves sum their points (sorted order); the last child to finish a parent
-// sums the parent's children in child order and continues upwards.
+// Leaf sums, part 1 (one thread per sorted position): gather the position
+// into sorted order and run a segmented inclusive scan over each wave's 64
+// positions (segments = leaves, fixed shuffle pattern, FP64).  A leaf that
+// starts and ends inside the wave gets its sum here; otherwise the wave
+// records the piece of the segment that covers its first position (wfirst)
+// and the piece of the segment that covers its last position (wlast).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tree_sums(
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys, const T* __restrict__ z,
-    int64_t n, int L, int com_mode, const DevScalars* __restrict__ sc,
-    const uint32_t* __restrict__ parent, const uint32_t* __restrict__ first_child,
-    uint32_t* __restrict__ arrive, Node* __restrict__ nodes, double2* __restrict__ nsum,
-    T* __restrict__ zs) {
+__global__ __launch_bounds__(kBlock) void k_leaf_scan(
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
+    const T* __restrict__ z, int64_t n, double2* __restrict__ nsum, T* __restrict__ zs,
+    double2* __restrict__ wfirst, double2* __restrict__ wlast) {
     using V = v2_t<T>;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = lane_id();
+    const bool valid = s < n;
+    const uint32_t lf = valid ? leaf_of[s] : 0xFFFFFFFFu;
+    V p = V{T(0), T(0)};
+    if (valid) {
+        p = reinterpret_cast<const V*>(z)[perm[s]];
+        reinterpret_cast<V*>(zs)[s] = p;
+    }
+    const bool head = valid && (s == 0 || leaf_of[s - 1] != lf);
+    const bool tail = valid && (s == n - 1 || leaf_of[s + 1] != lf);
+    double vx = (double)p.x, vy = (double)p.y;
+    bool f = head;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double ax = __shfl_up(vx, o, kWave), ay = __shfl_up(vy, o, kWave);
+        const bool af = __shfl_up((int)f, o, kWave) != 0;
+        if (lane >= o) {
+            if (!f) {
+                vx = ax + vx;
+                vy = ay + vy;
+            }
+            f = f || af;
+        }
+    }
+    const int64_t wv = s / kWave;
+    if (tail) {
+        if (f) nsum[lf] = double2{vx, vy};
+        else wfirst[wv] = double2{vx, vy};
+    } else if (valid && lane == kWave - 1) {
+        wlast[wv] = double2{vx, vy};
+        if (!f) wfirst[wv] = double2{vx, vy};
+    }
+}
+
+// Leaf sums, part 2 (one thread per leaf) and the cells above: a leaf that
+// spans several waves adds its pieces in wave order; then the last child to
+// finish a parent sums the parent's children in child order and continues
+// upwards.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tree_up(
+    const uint32_t* __restrict__ keys, int64_t n, int L, int com_mode,
+    const DevScalars* __restrict__ sc, const uint32_t* __restrict__ parent,
+    const uint32_t* __restrict__ first_child, uint32_t* __restrict__ arrive,
+    Node* __restrict__ nodes, double2* __restrict__ nsum, const double2* __restrict__ wfirst,
+    const double2* __restrict__ wlast) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t nleaf = sc->level_size[L];
     if (t >= nleaf) return;
     const uint32_t gid = sc->level_base[L] + (uint32_t)t;
     const uint32_t start = nodes[gid].start;
     const uint32_t end = (t + 1 < nleaf) ? nodes[gid + 1].start : (uint32_t)n;
-    double sx = 0.0, sy = 0.0;
-    for (uint32_t s = start; s < end; s++) {
-        const V p = reinterpret_cast<const V*>(z)[perm[s]];
-        reinterpret_cast<V*>(zs)[s] = p;
-        sx += (double)p.x;
-        sy += (double)p.y;
+    const uint32_t wa = start / kWave, wb = (end - 1) / kWave;
+    double sx, sy;
+    if (wa == wb) {
+        const double2 v = nsum[gid];
+        sx = v.x;
+        sy = v.y;
+    } else {
+        sx = wlast[wa].x;
+        sy = wlast[wa].y;
+        for (uint32_t w = wa + 1; w < wb; w++) {
+            sx += wfirst[w].x;
+            sy += wfirst[w].y;
+        }
+        sx += wfirst[wb].x;
+        sy += wfirst[wb].y;
     }
     write_node(nodes, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
     int l = L;
@@ -385,8 +437,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     const Node* __restrict__ nodes, const double2* __restrict__ nsum, const T* __restrict__ zs,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
     const DevScalars* __restrict__ sc, int64_t n, int L, double th2, int com_mode,
-    T* __restrict__ R, double* __restrict__ zpart, double* __restrict__ Zi_out,
-    uint32_t* __restrict__ visits_out) {
+    T* __restrict__ R, double* __restrict__ zpart, const uint32_t* __restrict__ orig,
+    double* __restrict__ Zi_out, uint32_t* __restrict__ visits_out,
+    uint32_t* __restrict__ used_out) {
     using V = v2_t<T>;
     __shared__ double wz[4];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -400,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
 
     double zacc = 0.0;
     T rx = T(0), ry = T(0);
-    uint32_t nvis = 0;
+    uint32_t nvis = 0, nuse = 0;
 
     // Stack entry k lives in lane k of these registers: first cell of a
     // sibling group, (group size | level << 8), lane mask (lo, hi).
@@ -449,6 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 if (use) {
                     const double dx = zx - cx, dy = zy - cy;
                     bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, m, zacc, rx, ry);
+                    nuse++;
                 }
             }
             const uint64_t om = ballot64(open);
@@ -465,8 +519,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     if (valid) {
         const uint32_t i = perm[s];
         reinterpret_cast<V*>(R)[i] = V{rx, ry};
-        if (Zi_out) Zi_out[i] = zacc;
-        if (visits_out) visits_out[i] = nvis;
+        if (Zi_out) Zi_out[orig[i]] = zacc;
+        if (visits_out) visits_out[orig[i]] = nvis;
+        if (used_out) used_out[orig[i]] = nuse;
     }
     const double zw = wave_sum(zacc);
     if (lane == 0) wz[w] = zw;
@@ -511,7 +566,8 @@ __global__ __launch_bounds__(kBlock) void k_attract(
     const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
     const T* __restrict__ z, const T* __restrict__ R, T* __restrict__ u, T* __restrict__ g,
     T* __restrict__ zh, DevScalars* __restrict__ sc, int64_t n, StepParams prm,
-    T* __restrict__ Aout, T* __restrict__ Bout, double* __restrict__ mm_part) {
+    const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout,
+    double* __restrict__ mm_part) {
     using V = v2_t<T>;
     __shared__ double red[4][4];
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -548,8 +604,8 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             const T bx = (T)(alpha * (double)ax - (double)Ri.x / Z);
             const T by = (T)(alpha * (double)ay - (double)Ri.y / Z);
             if (MODE == 1) {
-                if (Aout) reinterpret_cast<V*>(Aout)[i] = V{ax, ay};
-                if (Bout) reinterpret_cast<V*>(Bout)[i] = V{bx, by};
+                if (Aout) reinterpret_cast<V*>(Aout)[orig[i]] = V{ax, ay};
+                if (Bout) reinterpret_cast<V*>(Bout)[orig[i]] = V{bx, by};
             } else {
                 V ui = reinterpret_cast<V*>(u)[i];
                 V gi = reinterpret_cast<V*>(g)[i];
@@ -699,11 +755,13 @@ __device__ __forceinline__ v2_t<T> norm_pos(const T* __restrict__ zh,
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_get_y(const T* __restrict__ zh,
-                                                  const DevScalars* __restrict__ sc, int64_t n,
+                                                  const DevScalars* __restrict__ sc,
+                                                  const uint32_t* __restrict__ orig, int64_t n,
                                                   int r, int frame, void* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const v2_t<T> p = norm_pos<T>(zh, sc, i, r);
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i0 >= n) return;
+    const v2_t<T> p = norm_pos<T>(zh, sc, i0, r);
+    const int64_t i = orig[i0];
     if (frame == PSNE_FRAME_SCREEN) {
         int px = (int)p.x, py = (int)p.y;
         px = px > r - 1 ? r - 1 : px;
@@ -719,30 +777,38 @@ __global__ __launch_bounds__(kBlock) void k_get_y(const T* __restrict__ zh,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_get_state(const T* __restrict__ zh, const T* __restrict__ u,
                                                       const T* __restrict__ g,
-                                                      const DevScalars* __restrict__ sc, int64_t n,
+                                                      const DevScalars* __restrict__ sc,
+                                                      const uint32_t* __restrict__ orig, int64_t n,
                                                       int r, T* __restrict__ zo, T* __restrict__ uo,
                                                       T* __restrict__ go) {
     using V = v2_t<T>;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    if (zo) reinterpret_cast<V*>(zo)[i] = norm_pos<T>(zh, sc, i, r);
+    const uint32_t o = orig[i];
+    if (zo) reinterpret_cast<V*>(zo)[o] = norm_pos<T>(zh, sc, i, r);
     if (uo) {
         V v = reinterpret_cast<const V*>(u)[i];
         v.x *= (T)sc->uscale[0];
         v.y *= (T)sc->uscale[1];
-        reinterpret_cast<V*>(uo)[i] = v;
+        reinterpret_cast<V*>(uo)[o] = v;
     }
-    if (go) reinterpret_cast<V*>(go)[i] = reinterpret_cast<const V*>(g)[i];
+    if (go) reinterpret_cast<V*>(go)[o] = reinterpret_cast<const V*>(g)[i];
 }
 
+// state from the caller's order (u, g NULL => zeros, ones)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fill_state(T* __restrict__ u, T* __restrict__ g, int64_t n,
-                                                       int fill_u, int fill_g) {
+__global__ __launch_bounds__(kBlock) void k_set_state(const T* __restrict__ zin, const T* __restrict__ uin,
+                                                      const T* __restrict__ gin,
+                                                      const uint32_t* __restrict__ orig, int64_t n,
+                                                      T* __restrict__ zh, T* __restrict__ u,
+                                                      T* __restrict__ g) {
     using V = v2_t<T>;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    if (fill_u) reinterpret_cast<V*>(u)[i] = V{T(0), T(0)};
-    if (fill_g) reinterpret_cast<V*>(g)[i] = V{T(1), T(1)};
+    const uint32_t o = orig[i];
+    reinterpret_cast<V*>(zh)[i] = reinterpret_cast<const V*>(zin)[o];
+    reinterpret_cast<V*>(u)[i] = uin ? reinterpret_cast<const V*>(uin)[o] : V{T(0), T(0)};
+    reinterpret_cast<V*>(g)[i] = gin ? reinterpret_cast<const V*>(gin)[o] : V{T(1), T(1)};
 }
 
 __global__ __launch_bounds__(kBlock) void k_export_tree(const Node* __restrict__ nodes,
@@ -770,13 +836,6 @@ __global__ __launch_bounds__(kBlock) void k_cast_val(const double* __restrict__ 
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < m) b[i] = (T)a[i];
 }
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_uncast_val(const T* __restrict__ a, double* __restrict__ b,
-                                                       int64_t m) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < m) b[i] = (double)a[i];
-}
-
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
 inline int64_t attract_blocks(int64_t n) {
@@ -822,11 +881,11 @@ hipError_t run_sort(pixelsne_ctx* c) {
         const int shift = 8 * p;
         k_rs_hist<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
             tb.key[cur], c->n, shift, tb.hist, tb.sort_blocks);
-        k_scan_u32<<<1, 1024, 0, c->stream>>>(tb.hist, 256 * tb.sort_blocks);
+        k_rows_scan<<<256, kBlock, 0, c->stream>>>(tb.hist, tb.sort_blocks, tb.dtot);
         // the first pass generates the identity permutation itself
         k_rs_scatter<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
             tb.key[cur], p == 0 ? nullptr : tb.idx[cur], tb.key[cur ^ 1], tb.idx[cur ^ 1], c->n,
-            shift, tb.hist, tb.sort_blocks);
+            shift, tb.hist, tb.dtot, tb.sort_blocks);
         cur ^= 1;
     }
     tb.sorted = cur;
@@ -839,35 +898,41 @@ hipError_t run_tree(pixelsne_ctx* c) {
     const uint32_t* perm = tb.idx[tb.sorted];
     k_tree_count<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
         keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks);
-    k_tree_scan<<<1, 1024, 0, c->stream>>>(tb.lvl_cnt, tb.lvl_off, tb.tree_blocks, c->L, c->sc);
+    k_rows_scan<<<dim3((unsigned)(c->L + 1)), kBlock, 0, c->stream>>>(tb.lvl_cnt, tb.tree_blocks,
+                                                                      tb.ltot);
     k_tree_nodes<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
-        keys, c->n, c->L, tb.lvl_off, tb.tree_blocks, c->sc, tb.parent, tb.first_child,
-        tb.arrive, tb.nodes, tb.leaf_of);
-    // one thread per leaf; at most min(n, 4^L) leaves
-    const int64_t max_leaves = c->n;
-    if (fp64(c))
-        k_tree_sums<double><<<grid_for(max_leaves), kBlock, 0, c->stream>>>(
-            perm, keys, (const double*)c->z, c->n, c->L, c->prm.com_mode, c->sc, tb.parent,
-            tb.first_child, tb.arrive, tb.nodes, tb.nsum, (double*)tb.zs);
-    else
-        k_tree_sums<float><<<grid_for(max_leaves), kBlock, 0, c->stream>>>(
-            perm, keys, (const float*)c->z, c->n, c->L, c->prm.com_mode, c->sc, tb.parent,
-            tb.first_child, tb.arrive, tb.nodes, tb.nsum, (float*)tb.zs);
+        keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.parent,
+        tb.first_child, tb.arrive, tb.nodes, tb.leaf_of);
+    if (fp64(c)) {
+        k_leaf_scan<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            perm, tb.leaf_of, (const double*)c->z, c->n, tb.nsum, (double*)tb.zs, tb.wfirst,
+            tb.wlast);
+        k_tree_up<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.parent, tb.first_child, tb.arrive,
+            tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+    } else {
+        k_leaf_scan<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            perm, tb.leaf_of, (const float*)c->z, c->n, tb.nsum, (float*)tb.zs, tb.wfirst,
+            tb.wlast);
+        k_tree_up<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.parent, tb.first_child, tb.arrive,
+            tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+    }
     return hipGetLastError();
 }
 
-hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, double* Zi) {
+hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi) {
     TreeBufs& tb = c->tb;
     const double th2 = c->prm.theta * c->prm.theta;
     const uint32_t* perm = tb.idx[tb.sorted];
     if (fp64(c))
         k_traverse<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             tb.nodes, tb.nsum, (const double*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
-            c->prm.com_mode, (double*)c->R, c->zpart, Zi, visits);
+            c->prm.com_mode, (double*)c->R, c->zpart, c->orig, Zi, visits, used);
     else
         k_traverse<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             tb.nodes, tb.nsum, (const float*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
-            c->prm.com_mode, (float*)c->R, c->zpart, Zi, visits);
+            c->prm.com_mode, (float*)c->R, c->zpart, c->orig, Zi, visits, used);
     return hipGetLastError();
 }
 
@@ -884,21 +949,21 @@ hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B
         if (mode == 0)
             k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
                 c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, nullptr, nullptr, c->mm_part);
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, nullptr, nullptr, c->mm_part);
         else
             k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
                 c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, (T*)A, (T*)B, c->mm_part);
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, (T*)A, (T*)B, c->mm_part);
     } else {
         using T = float;
         if (mode == 0)
             k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
                 c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, nullptr, nullptr, c->mm_part);
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, nullptr, nullptr, c->mm_part);
         else
             k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
                 c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, (T*)A, (T*)B, c->mm_part);
+                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, (T*)A, (T*)B, c->mm_part);
     }
     return hipGetLastError();
 }
@@ -914,10 +979,35 @@ hipError_t run_iteration(pixelsne_ctx* c) {
     if ((e = run_snap(c)) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
     if ((e = run_tree(c)) != hipSuccess) return e;
-    if ((e = run_traverse(c, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;
     if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
-    return run_finalize(c, 1);
+    if ((e = run_finalize(c, 1)) != hipSuccess) return e;
+    if (c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
+        return run_reorder(c);
+    return hipSuccess;
+}
+
+hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev) {
+    hipError_t e;
+    if ((e = hipEventRecord(ev[0], c->stream)) != hipSuccess) return e;
+    if ((e = run_snap(c)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[1], c->stream)) != hipSuccess) return e;
+    if ((e = run_sort(c)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[2], c->stream)) != hipSuccess) return e;
+    if ((e = run_tree(c)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[3], c->stream)) != hipSuccess) return e;
+    if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[4], c->stream)) != hipSuccess) return e;
+    if ((e = run_zsum(c)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[5], c->stream)) != hipSuccess) return e;
+    if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[6], c->stream)) != hipSuccess) return e;
+    if ((e = run_finalize(c, 1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[7], c->stream)) != hipSuccess) return e;
+    if (c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
+        if ((e = run_reorder(c)) != hipSuccess) return e;
+    return hipEventRecord(ev[8], c->stream);
 }
 
 hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma) {
@@ -945,39 +1035,34 @@ hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, doubl
 hipError_t run_get_y(const pixelsne_ctx* c, void* out, int frame) {
     if (fp64(c))
         k_get_y<double><<<grid_for(c->n), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
-                                                                   c->n, c->r, frame, out);
+                                                                   c->orig, c->n, c->r, frame, out);
     else
-        k_get_y<float><<<grid_for(c->n), kBlock, 0, c->stream>>>((const float*)c->zh, c->sc, c->n,
-                                                                  c->r, frame, out);
+        k_get_y<float><<<grid_for(c->n), kBlock, 0, c->stream>>>((const float*)c->zh, c->sc,
+                                                                  c->orig, c->n, c->r, frame, out);
     return hipGetLastError();
 }
 
 hipError_t run_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g) {
-    const size_t bytes = (size_t)c->n * 2 * (fp64(c) ? 8 : 4);
-    hipError_t e = hipMemcpyAsync(c->zh, z, bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess && u) e = hipMemcpyAsync(c->u, u, bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess && g) e = hipMemcpyAsync(c->g, g, bytes, hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return e;
-    if (!u || !g) {
-        if (fp64(c))
-            k_fill_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-                (double*)c->u, (double*)c->g, c->n, !u, !g);
-        else
-            k_fill_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-                (float*)c->u, (float*)c->g, c->n, !u, !g);
-    }
+    if (fp64(c))
+        k_set_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const double*)z, (const double*)u, (const double*)g, c->orig, c->n, (double*)c->zh,
+            (double*)c->u, (double*)c->g);
+    else
+        k_set_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            (const float*)z, (const float*)u, (const float*)g, c->orig, c->n, (float*)c->zh,
+            (float*)c->u, (float*)c->g);
     return hipGetLastError();
 }
 
 hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g) {
     if (fp64(c))
         k_get_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            (const double*)c->zh, (const double*)c->u, (const double*)c->g, c->sc, c->n, c->r,
-            (double*)z, (double*)u, (double*)g);
+            (const double*)c->zh, (const double*)c->u, (const double*)c->g, c->sc, c->orig, c->n,
+            c->r, (double*)z, (double*)u, (double*)g);
     else
         k_get_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            (const float*)c->zh, (const float*)c->u, (const float*)c->g, c->sc, c->n, c->r,
-            (float*)z, (float*)u, (float*)g);
+            (const float*)c->zh, (const float*)c->u, (const float*)c->g, c->sc, c->orig, c->n,
+            c->r, (float*)z, (float*)u, (float*)g);
     return hipGetLastError();
 }
 
@@ -988,9 +1073,7 @@ hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm
     if (keys)
         e = hipMemcpyAsync(keys, tb.key[tb.sorted], (size_t)c->n * 4, hipMemcpyDeviceToDevice,
                            c->stream);
-    if (e == hipSuccess && perm)
-        e = hipMemcpyAsync(perm, tb.idx[tb.sorted], (size_t)c->n * 4, hipMemcpyDeviceToDevice,
-                           c->stream);
+    if (e == hipSuccess && perm) e = run_map_perm(c, tb.idx[tb.sorted], perm);
     if (e != hipSuccess) return e;
     if (prefix || count || sum)
         k_export_tree<<<grid_for(tb.max_nodes), kBlock, 0, c->stream>>>(
@@ -1003,14 +1086,6 @@ hipError_t run_convert_val(pixelsne_ctx* c, const double* val64) {
         return hipMemcpyAsync(c->val, val64, (size_t)c->nnz * 8, hipMemcpyDeviceToDevice,
                               c->stream);
     k_cast_val<float><<<grid_for(c->nnz), kBlock, 0, c->stream>>>(val64, (float*)c->val, c->nnz);
-    return hipGetLastError();
-}
-
-hipError_t run_export_val(const pixelsne_ctx* c, double* out) {
-    if (fp64(c))
-        return hipMemcpyAsync(out, c->val, (size_t)c->nnz * 8, hipMemcpyDeviceToDevice, c->stream);
-    k_uncast_val<float><<<grid_for(c->nnz), kBlock, 0, c->stream>>>((const float*)c->val, out,
-                                                                     c->nnz);
     return hipGetLastError();
 }
 

@@ -418,62 +418,64 @@ __global__ __launch_bounds__(256) void k_sym_fill(const int32_t* __restrict__ id
 
 constexpr int kRowMax = 4096;
 
-// Sort one row by column (rank by counting, ties by position), merge the
-// (at most two) summands of each column, write the unique entries at the
-// row start and their number.
+// Sort one row by column (rank by counting, ties by position) into scol/sval
+// at the same offsets, merge the (at most two) summands of each column, write
+// the unique entries at the row start of tcol/tval and their number.  Rows
+// up to kRowMax entries are ranked from LDS, longer rows from global memory.
 __global__ __launch_bounds__(256) void k_sym_row(const int64_t* __restrict__ off,
                                                  uint32_t* __restrict__ tcol,
                                                  double* __restrict__ tval,
-                                                 int64_t* __restrict__ ucnt,
-                                                 uint32_t* __restrict__ overflow) {
+                                                 uint32_t* __restrict__ scol,
+                                                 double* __restrict__ sval,
+                                                 int64_t* __restrict__ ucnt) {
     __shared__ uint32_t c_in[kRowMax];
-    __shared__ uint32_t c_s[kRowMax];
-    __shared__ double v_s[kRowMax];
-    __shared__ uint32_t flags[kRowMax];
     __shared__ uint32_t wsum[4];
     const int64_t i = blockIdx.x;
     const int t = threadIdx.x;
     const int64_t b = off[i];
-    const int len = (int)(off[i + 1] - b);
-    if (len > kRowMax) {
-        if (t == 0) { atomicOr(overflow, 1u); ucnt[i] = 0; }
-        return;
-    }
-    for (int e = t; e < len; e += 256) c_in[e] = tcol[b + e];
+    const int64_t len = off[i + 1] - b;
+    const bool in_lds = len <= kRowMax;
+    if (in_lds)
+        for (int64_t e = t; e < len; e += 256) c_in[e] = tcol[b + e];
     __syncthreads();
-    for (int e = t; e < len; e += 256) {
-        const uint32_t ce = c_in[e];
-        int r = 0;
-        for (int f = 0; f < len; f++) {
-            const uint32_t cf = c_in[f];
-            r += (cf < ce || (cf == ce && f < e)) ? 1 : 0;
+    for (int64_t e = t; e < len; e += 256) {
+        const uint32_t ce = in_lds ? c_in[e] : tcol[b + e];
+        int64_t r = 0;
+        if (in_lds) {
+            for (int64_t f = 0; f < len; f++) {
+                const uint32_t cf = c_in[f];
+                r += (cf < ce || (cf == ce && f < e)) ? 1 : 0;
+            }
+        } else {
+            for (int64_t f = 0; f < len; f++) {
+                const uint32_t cf = tcol[b + f];
+                r += (cf < ce || (cf == ce && f < e)) ? 1 : 0;
+            }
         }
-        c_s[r] = ce;
-        v_s[r] = tval[b + e];
+        scol[b + r] = ce;
+        sval[b + r] = tval[b + e];
     }
+    __threadfence_block();
     __syncthreads();
-    // unique flags and their exclusive prefix (block scan over chunks of 256)
-    uint32_t base = 0;
-    for (int c0 = 0; c0 < len; c0 += 256) {
-        const int e = c0 + t;
-        const bool u = e < len && (e == 0 || c_s[e] != c_s[e - 1]);
+    // unique flags and their exclusive prefix, 256 entries at a time
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < len; c0 += 256) {
+        const int64_t e = c0 + t;
+        const bool u = e < len && (e == 0 || scol[b + e] != scol[b + e - 1]);
         const uint64_t bal = ballot64(u);
         if (lane_id() == 0) wsum[t >> 6] = (uint32_t)__popcll(bal);
         __syncthreads();
-        uint32_t pre = base + (uint32_t)__popcll(bal & lanemask_lt());
+        int64_t pre = base + (int64_t)__popcll(bal & lanemask_lt());
         for (int q = 0; q < (t >> 6); q++) pre += wsum[q];
-        if (u) flags[e] = pre;
-        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (u) {
+            double v = sval[b + e];
+            if (e + 1 < len && scol[b + e + 1] == scol[b + e]) v = v + sval[b + e + 1];
+            tcol[b + pre] = scol[b + e];
+            tval[b + pre] = v;
+        }
+        const int64_t tot = (int64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
         base += tot;
-    }
-    for (int e = t; e < len; e += 256) {
-        if (e == 0 || c_s[e] != c_s[e - 1]) {
-            double v = v_s[e];
-            if (e + 1 < len && c_s[e + 1] == c_s[e]) v = v + v_s[e + 1];
-            tcol[b + flags[e]] = c_s[e];
-            tval[b + flags[e]] = v;
-        }
     }
     if (t == 0) ucnt[i] = base;
 }
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(256) void k_sym_write(const int64_t* __restrict__ o
     }
 }
 
-hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
+hipError_t scan_i64_local(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
     const int64_t nb = ceil_div(m, 1024);
     k_scan64_reduce<<<dim3((unsigned)nb), 256, 0, s>>>(a, m, tmp);
     k_scan64_top<<<1, 1024, 0, s>>>(tmp, nb);
@@ -558,6 +560,12 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
 
 }  // namespace
 
+hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
+    return scan_i64_local(a, m, out, tmp, s);
+}
+
+int64_t scan_i64_tmp_len(int64_t m) { return ceil_div(m, 1024) + 1; }
+
 hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,
                double* d2, hipStream_t s, std::string* err) {
     switch (x_dtype) {
@@ -579,15 +587,15 @@ hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k
                       int64_t** row_ptr_out, uint32_t** col_out, double** val_out, int64_t* nnz_out,
                       hipStream_t s) {
     const int64_t m = n * (int64_t)k;
-    uint32_t *indeg = nullptr, *fill = nullptr, *tcol = nullptr, *ovf = nullptr;
+    uint32_t *indeg = nullptr, *fill = nullptr, *tcol = nullptr, *scol = nullptr;
     int64_t *cap = nullptr, *off = nullptr, *tmp = nullptr, *ucnt = nullptr, *rp = nullptr;
-    double* tval = nullptr;
+    double *tval = nullptr, *sval = nullptr;
     uint32_t* col = nullptr;
     double* val = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
-        hipFree(indeg); hipFree(fill); hipFree(tcol); hipFree(ovf); hipFree(cap);
-        hipFree(off); hipFree(tmp); hipFree(ucnt); hipFree(tval);
+        hipFree(indeg); hipFree(fill); hipFree(tcol); hipFree(scol); hipFree(cap);
+        hipFree(off); hipFree(tmp); hipFree(ucnt); hipFree(tval); hipFree(sval);
     };
     auto fail = [&](hipError_t x) {
         cleanup();
@@ -597,7 +605,6 @@ hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k
     const int64_t nb = ceil_div(n + 1, 1024);
     if ((e = hipMalloc(&indeg, 4 * n)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&fill, 4 * n)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc(&ovf, 4)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&cap, 8 * (n + 1))) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&off, 8 * (n + 1))) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&tmp, 8 * (nb + 1))) != hipSuccess) return fail(e);
@@ -605,22 +612,20 @@ hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k
     if ((e = hipMalloc(&rp, 8 * (n + 1))) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&tcol, 4 * 2 * m)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&tval, 8 * 2 * m)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&scol, 4 * 2 * m)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&sval, 8 * 2 * m)) != hipSuccess) return fail(e);
     hipMemsetAsync(indeg, 0, 4 * n, s);
     hipMemsetAsync(fill, 0, 4 * n, s);
-    hipMemsetAsync(ovf, 0, 4, s);
     k_indeg<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, m, indeg);
     k_row_caps<<<dim3((unsigned)ceil_div(n + 1, 256)), 256, 0, s>>>(indeg, n, k, cap);
-    if ((e = scan_i64(cap, n + 1, off, tmp, s)) != hipSuccess) return fail(e);
+    if ((e = scan_i64_local(cap, n + 1, off, tmp, s)) != hipSuccess) return fail(e);
     k_sym_fill<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, Pc, n, k, off, fill, tcol, tval);
-    k_sym_row<<<dim3((unsigned)n), 256, 0, s>>>(off, tcol, tval, ucnt, ovf);
+    k_sym_row<<<dim3((unsigned)n), 256, 0, s>>>(off, tcol, tval, scol, sval, ucnt);
     hipMemsetAsync(ucnt + n, 0, 8, s);
-    if ((e = scan_i64(ucnt, n + 1, rp, tmp, s)) != hipSuccess) return fail(e);
+    if ((e = scan_i64_local(ucnt, n + 1, rp, tmp, s)) != hipSuccess) return fail(e);
     int64_t nnz = 0;
-    uint32_t hovf = 0;
     if ((e = hipMemcpyAsync(&nnz, rp + n, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
-    if ((e = hipMemcpyAsync(&hovf, ovf, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
-    if (hovf) return fail(hipErrorNotSupported);
     if ((e = hipMalloc(&col, 4 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&val, 8 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
     k_sym_write<<<dim3((unsigned)n), 256, 0, s>>>(off, rp, n, tcol, tval, col, val,

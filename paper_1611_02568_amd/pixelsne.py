@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("min_gain", C.c_double), ("eps", C.c_double), ("init_sigma", C.c_double),
         ("seed", C.c_uint64), ("precision", C.c_int32), ("com_mode", C.c_int32),
         ("x_dtype", C.c_int32), ("Y_init", C.c_void_p), ("stream", C.c_void_p),
+        ("reorder_every", C.c_int32),
     ]
 
 
@@ -52,6 +53,16 @@ class Stats(C.Structure):
     ]
 
 
+class PassTimes(C.Structure):
+    _fields_ = [("snap_ms", C.c_double), ("sort_ms", C.c_double), ("tree_ms", C.c_double),
+                ("traverse_ms", C.c_double), ("zsum_ms", C.c_double),
+                ("attract_ms", C.c_double), ("finalize_ms", C.c_double),
+                ("reorder_ms", C.c_double), ("iterations", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # exported symbol -> (restype, argtypes)
 _vp, _i64, _i32, _d, _u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64
 SIGNATURES = {
@@ -61,6 +72,7 @@ SIGNATURES = {
     "pixelsne_init_with_P": (_vp, [_i64, _i64, _vp, _vp, _vp, _i32, _i32, C.POINTER(Params)]),
     "pixelsne_step": (C.c_int, [_vp, _i32]),
     "pixelsne_step_async": (C.c_int, [_vp, _i32]),
+    "pixelsne_step_profiled": (C.c_int, [_vp, _i32, C.POINTER(PassTimes)]),
     "pixelsne_get_Y": (C.c_int, [_vp, _vp, _i32]),
     "pixelsne_destroy": (None, [_vp]),
     "pixelsne_last_error": (C.c_char_p, []),
@@ -68,7 +80,8 @@ SIGNATURES = {
     "pixelsne_set_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _i32]),
     "pixelsne_get_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32)]),
-    "pixelsne_gradient": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "pixelsne_gradient": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    C.POINTER(C.c_double)]),
     "pixelsne_export_tree": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
     "pixelsne_export_P": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp]),
     "pixelsne_knn": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
@@ -187,6 +200,11 @@ class Context:
     def step_async(self, n_iter: int = 1):
         _check(load().pixelsne_step_async(self._h, int(n_iter)))
 
+    def step_profiled(self, n_iter: int = 1) -> PassTimes:
+        t = PassTimes()
+        _check(load().pixelsne_step_profiled(self._h, int(n_iter), C.byref(t)))
+        return t
+
     def get_Y(self, frame: int = FRAME_Y) -> torch.Tensor:
         dt = torch.int32 if frame == FRAME_SCREEN else torch.float64
         out = torch.empty((self.n, 2), dtype=dt, device="cuda")
@@ -221,10 +239,11 @@ class Context:
         R = torch.empty_like(B)
         Zi = torch.empty(self.n, dtype=torch.float64, device="cuda")
         vis = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        used = torch.empty(self.n, dtype=torch.int32, device="cuda")
         Z = C.c_double()
         _check(load().pixelsne_gradient(self._h, float(alpha), _ptr(B), _ptr(A), _ptr(R),
-                                        _ptr(Zi), _ptr(vis), C.byref(Z)))
-        return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": Z.value}
+                                        _ptr(Zi), _ptr(vis), _ptr(used), C.byref(Z)))
+        return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "used": used, "Z": Z.value}
 
     def export_tree(self):
         st = self.stats()

@@ -236,3 +236,45 @@ def test_final_kl_matches_oracle(psne, small_problem, prec):
     oracle.iterate(ost, oracle.params(512), P, 1000)
     kl_orc = oracle.kl(ost.z, ost.s, P)
     assert abs(kl_gpu - kl_orc) <= 0.01 * kl_orc, (kl_gpu, kl_orc)
+
+
+# --------------------------------------------------------------------------
+# internal renumbering: results stay in the caller's numbering
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reorder_keeps_caller_order(psne, small_problem, prec):
+    X, P, st = small_problem
+    dt = _state_dtype(prec)
+    ctx = psne.Context.from_P(*P, screen=512, Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=4)),
+                              precision=prec, reorder_every=3)
+    ctx.step(10)                                  # three renumberings
+    zt = np.minimum(st.z.astype(dt), np.nextafter(dt(512), dt(0)))
+    ctx.set_state(zt, st.s)
+    got = ctx.get_state()
+    assert np.array_equal(got["z"].cpu().numpy(), zt)
+    g = ctx.gradient(1.0)
+    og = oracle.gradient(zt.astype(np.float64), 512, st.s, P, theta=0.5)
+    assert np.array_equal(g["visits"].cpu().numpy(), og["visits"])
+    B = g["B"].double().cpu().numpy()
+    assert np.linalg.norm(B - og["B"]) <= TOL_B[prec] * np.linalg.norm(og["B"])
+    R = g["R"].double().cpu().numpy()
+    assert np.linalg.norm(R - og["R"]) <= TOL_B[prec] * np.linalg.norm(og["R"])
+    Zi = g["Zi"].cpu().numpy()
+    np.testing.assert_allclose(Zi, og["Zi"], rtol=1e-5 if prec == 0 else 1e-12)
+    _tree_check(ctx, zt.astype(np.float64), 512)
+    rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
+    assert np.array_equal(rp, P[0]) and np.array_equal(col, P[1])
+    np.testing.assert_allclose(val, P[2], rtol=6e-8 if prec == 0 else 0)
+
+
+def test_reorder_does_not_change_the_trajectory(psne, small_problem):
+    """FP64: 12 iterations renumbering every iteration vs never."""
+    X, P, _ = small_problem
+    y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=5))
+    a = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=1, reorder_every=1)
+    b = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=1, reorder_every=0)
+    a.step(12)
+    b.step(12)
+    ya = a.get_Y(psne.FRAME_Y).cpu().numpy()
+    yb = b.get_Y(psne.FRAME_Y).cpu().numpy()
+    assert np.max(np.abs(ya - yb)) <= 1e-8 * np.max(np.abs(yb))
