@@ -163,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed region, copy a buffer of this size once (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
@@ -170,6 +173,13 @@ def main():
         sys.exit(2)
 
     res, setup_s, nnz = run_gpu(args)
+    if args.calibrate_copy_mib:
+        import torch
+        a = torch.ones(args.calibrate_copy_mib * 2**18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     main32 = res["fp32"]
     # dominant kernel of the FP32 iteration
     per = main32["pass_ms"]

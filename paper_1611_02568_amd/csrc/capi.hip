@@ -126,9 +126,7 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &tb.ltot, 4 * (size_t)(c->L + 1))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.wfirst, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.wlast, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
-    if ((e = dalloc(c, &tb.parent, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.first_child, 4 * (size_t)mx)) != hipSuccess) return e;
-    if ((e = dalloc(c, &tb.arrive, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.nodes, sizeof(Node) * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.leaf_of, 4 * (size_t)n)) != hipSuccess) return e;

@@ -87,17 +87,6 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
-// Relaxed agent-scope loads that bypass the per-CU cache, for data written by
-// other workgroups of the same kernel after a release fence.
-__device__ __forceinline__ double load_agent(const double* p) {
-    uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)b);
-}
-__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace psne

@@ -23,9 +23,7 @@ struct TreeBufs {
     int64_t tree_blocks = 0;
     double2* wfirst = nullptr;               // [n / 64] per-wave partial leaf sums
     double2* wlast = nullptr;
-    uint32_t* parent = nullptr;              // [max_nodes]
     uint32_t* first_child = nullptr;         // [max_nodes]
-    uint32_t* arrive = nullptr;              // [max_nodes]
     Node* nodes = nullptr;                   // [max_nodes]
     double2* nsum = nullptr;                 // [max_nodes] coordinate sums (FP64)
     uint32_t* leaf_of = nullptr;             // [n] leaf cell of each sorted position

@@ -24,6 +24,8 @@ constexpr int kBlock = 256;
 constexpr int kRsItems = 8;
 constexpr int kRsTile = kBlock * kRsItems;
 constexpr int kAttractBlocksMax = 8192;
+constexpr int kUnroll = 2;        // nonzeros per lane and row in flight in the attraction
+constexpr int kRows = 4;          // rows per wavefront at a time in the attraction
 
 template <typename T> __device__ __forceinline__ T top_below(int r);
 template <> __device__ __forceinline__ float top_below<float>(int r) {
@@ -190,13 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_tree_count(const uint32_t* __restric
 }
 
 // Number each cell: for every level, the rank of the cell holding sorted
-// position s.  Positions that open a cell write its start, parent and first
+// position s.  Positions that open a cell write its start and first
 // child (children of a cell are consecutive in the next level).
 __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     const uint32_t* __restrict__ keys, int64_t n, int L, const uint32_t* __restrict__ off,
     int64_t nb, const uint32_t* __restrict__ ltot, DevScalars* __restrict__ sc,
-    uint32_t* __restrict__ parent, uint32_t* __restrict__ first_child,
-    uint32_t* __restrict__ arrive, Node* __restrict__ nodes, uint32_t* __restrict__ leaf_of) {
+    uint32_t* __restrict__ first_child, Node* __restrict__ nodes,
+    uint32_t* __restrict__ leaf_of) {
     __shared__ uint32_t wc[4][kMaxLevels];
     __shared__ uint32_t lbase[kMaxLevels + 1];
     const int t = threadIdx.x, w = t >> 6;
@@ -245,8 +247,6 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
             const uint32_t gid = lbase[l] + rank[l];
             nodes[gid].start = (uint32_t)s;
             nodes[gid].level = (uint32_t)l;
-            arrive[gid] = 0;
-            parent[gid] = l > 0 ? lbase[l > 0 ? l - 1 : 0] + rank[l > 0 ? l - 1 : 0] : 0xFFFFFFFFu;
             first_child[gid] = l < L ? lbase[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L] : 0u;
         }
     }
@@ -321,17 +321,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
     }
 }
 
-// Leaf sums, part 2 (one thread per leaf) and the cells above: a leaf that
-// spans several waves adds its pieces in wave order; then the last child to
-// finish a parent sums the parent's children in child order and continues
-// upwards.
+// Leaf sums, part 2 (one thread per leaf): a leaf that spans several waves
+// adds its pieces in wave order; every leaf writes its cell record.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tree_up(
+__global__ __launch_bounds__(kBlock) void k_tree_leaves(
     const uint32_t* __restrict__ keys, int64_t n, int L, int com_mode,
-    const DevScalars* __restrict__ sc, const uint32_t* __restrict__ parent,
-    const uint32_t* __restrict__ first_child, uint32_t* __restrict__ arrive,
-    Node* __restrict__ nodes, double2* __restrict__ nsum, const double2* __restrict__ wfirst,
-    const double2* __restrict__ wlast) {
+    const DevScalars* __restrict__ sc, Node* __restrict__ nodes, double2* __restrict__ nsum,
+    const double2* __restrict__ wfirst, const double2* __restrict__ wlast) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t nleaf = sc->level_size[L];
     if (t >= nleaf) return;
@@ -355,30 +351,32 @@ __global__ __launch_bounds__(kBlock) void k_tree_up(
         sy += wfirst[wb].y;
     }
     write_node(nodes, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
-    int l = L;
-    uint32_t g = gid;
-    while (l > 0) {
-        const uint32_t p = parent[g];
-        const uint32_t fc = first_child[p];
-        const uint32_t pend = sc->level_base[l - 1] + sc->level_size[l - 1];
-        const uint32_t lc = (p + 1 < pend) ? first_child[p + 1] : sc->level_base[l] + sc->level_size[l];
-        const uint32_t nch = lc - fc;
-        __threadfence();
-        const uint32_t old = atomicAdd(&arrive[p], 1u);
-        if (old != nch - 1) break;
-        __threadfence();
-        double ax = 0.0, ay = 0.0;
-        uint32_t c = 0;
-        for (uint32_t q = fc; q < lc; q++) {
-            ax += load_agent(&nsum[q].x);
-            ay += load_agent(&nsum[q].y);
-            c += load_agent(&nodes[q].count);
-        }
-        l -= 1;
-        g = p;
-        write_node(nodes, nsum, g, l, L, ax, ay, c, fc | ((nch - 1) << 30),
-                   keys[nodes[g].start], com_mode);
+}
+
+// One level of inner cells (one thread per cell): counts and sums of the
+// children (consecutive in the next level) added in child order.
+__global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restrict__ keys, int l,
+                                                       int L, int com_mode,
+                                                       const DevScalars* __restrict__ sc,
+                                                       const uint32_t* __restrict__ first_child,
+                                                       Node* __restrict__ nodes,
+                                                       double2* __restrict__ nsum) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t m = sc->level_size[l];
+    if (t >= m) return;
+    const uint32_t g = sc->level_base[l] + (uint32_t)t;
+    const uint32_t fc = first_child[g];
+    const uint32_t lc = (t + 1 < m) ? first_child[g + 1] : sc->level_base[l + 1] + sc->level_size[l + 1];
+    double ax = 0.0, ay = 0.0;
+    uint32_t c = 0;
+    for (uint32_t q = fc; q < lc; q++) {
+        const double2 v = nsum[q];
+        ax += v.x;
+        ay += v.y;
+        c += nodes[q].count;
     }
+    write_node(nodes, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30), keys[nodes[g].start],
+               com_mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,6 +559,10 @@ template <typename T> __device__ __forceinline__ T sgn(T x) {
     return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
 }
 
+// One wavefront works on kRows consecutive rows at a time: the loads of all
+// of them are issued together (kRows x kUnroll column/value loads and
+// gathers per lane in flight), the row sums are reduced across the wave, and
+// lanes 0..kRows-1 apply the step to their row in parallel.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_attract(
     const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
@@ -583,30 +585,66 @@ __global__ __launch_bounds__(kBlock) void k_attract(
     const T eta = (T)prm.eta, gmin = (T)prm.min_gain;
     double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
     bool bad = false;
-    for (int64_t i = wave; i < n; i += nwaves) {
-        const int64_t e0 = rp[i], e1 = rp[i + 1];
-        const V zi = reinterpret_cast<const V*>(z)[i];
-        T ax = T(0), ay = T(0);
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            const uint32_t j = col[e];
-            const T p = val[e];
-            const V zj = reinterpret_cast<const V*>(z)[j];
-            const T dx = zi.x - zj.x, dy = zi.y - zj.y;
-            const T q = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
-            const T pq = p * q;
-            ax += pq * dx;
-            ay += pq * dy;
+    for (int64_t i0 = wave * kRows; i0 < n; i0 += nwaves * kRows) {
+        int64_t e0[kRows], e1[kRows];
+        V zi[kRows];
+        int64_t len = 0;
+#pragma unroll
+        for (int r = 0; r < kRows; r++) {
+            const int64_t i = i0 + r < n ? i0 + r : n - 1;
+            e0[r] = rp[i];
+            e1[r] = i0 + r < n ? rp[i + 1] : e0[r];
+            zi[r] = reinterpret_cast<const V*>(z)[i];
+            len = e1[r] - e0[r] > len ? e1[r] - e0[r] : len;
         }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) {
+        T ax[kRows], ay[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; r++) { ax[r] = T(0); ay[r] = T(0); }
+        for (int64_t base = lane; base < len; base += kWave * kUnroll) {
+            uint32_t j[kRows][kUnroll];
+            T p[kRows][kUnroll];
+#pragma unroll
+            for (int r = 0; r < kRows; r++)
+#pragma unroll
+                for (int q = 0; q < kUnroll; q++) {
+                    const int64_t e = e0[r] + base + q * kWave;
+                    const bool ok = e < e1[r];
+                    // streamed once: keep the per-CU cache for the gathered z_j
+                    j[r][q] = ok ? __builtin_nontemporal_load(&col[e]) : 0u;
+                    p[r][q] = ok ? __builtin_nontemporal_load(&val[e]) : T(0);
+                }
+            V zj[kRows][kUnroll];
+#pragma unroll
+            for (int r = 0; r < kRows; r++)
+#pragma unroll
+                for (int q = 0; q < kUnroll; q++) zj[r][q] = reinterpret_cast<const V*>(z)[j[r][q]];
+#pragma unroll
+            for (int r = 0; r < kRows; r++)
+#pragma unroll
+                for (int q = 0; q < kUnroll; q++) {
+                    const T dx = zi[r].x - zj[r][q].x, dy = zi[r].y - zj[r][q].y;
+                    const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
+                    const T pw = p[r][q] * wq;
+                    ax[r] += pw * dx;
+                    ay[r] += pw * dy;
+                }
+        }
+        T mx = T(0), my = T(0);
+#pragma unroll
+        for (int r = 0; r < kRows; r++) {
+            const T sx = wave_sum(ax[r]), sy = wave_sum(ay[r]);
+            if (lane == r) { mx = sx; my = sy; }
+        }
+        const int64_t i = i0 + lane;
+        if (lane < kRows && i < n) {
             const V Ri = reinterpret_cast<const V*>(R)[i];
-            const T bx = (T)(alpha * (double)ax - (double)Ri.x / Z);
-            const T by = (T)(alpha * (double)ay - (double)Ri.y / Z);
+            const T bx = (T)(alpha * (double)mx - (double)Ri.x / Z);
+            const T by = (T)(alpha * (double)my - (double)Ri.y / Z);
             if (MODE == 1) {
-                if (Aout) reinterpret_cast<V*>(Aout)[orig[i]] = V{ax, ay};
+                if (Aout) reinterpret_cast<V*>(Aout)[orig[i]] = V{mx, my};
                 if (Bout) reinterpret_cast<V*>(Bout)[orig[i]] = V{bx, by};
             } else {
+                const V zii = reinterpret_cast<const V*>(z)[i];
                 V ui = reinterpret_cast<V*>(u)[i];
                 V gi = reinterpret_cast<V*>(g)[i];
                 ui.x *= us0;
@@ -617,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 gy = gy < gmin ? gmin : gy;
                 ui.x = mu * ui.x - eta * gx * bx;
                 ui.y = mu * ui.y - eta * gy * by;
-                const T hx = zi.x + ui.x, hy = zi.y + ui.y;
+                const T hx = zii.x + ui.x, hy = zii.y + ui.y;
                 reinterpret_cast<V*>(u)[i] = ui;
                 reinterpret_cast<V*>(g)[i] = V{gx, gy};
                 reinterpret_cast<V*>(zh)[i] = V{hx, hy};
@@ -630,7 +668,8 @@ __global__ __launch_bounds__(kBlock) void k_attract(
         }
     }
     if (MODE == 1) return;
-    if (bad) atomicOr(&sc->nonfinite, 1);
+    if (ballot64(bad) && lane == 0) atomicOr(&sc->nonfinite, 1);
+    mnx = wave_min(mnx); mny = wave_min(mny); mxx = wave_max(mxx); mxy = wave_max(mxy);
     if (lane == 0) {
         red[w][0] = mnx; red[w][1] = mny; red[w][2] = mxx; red[w][3] = mxy;
     }
@@ -839,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void k_cast_val(const double* __restrict__ 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
 inline int64_t attract_blocks(int64_t n) {
-    int64_t b = ceil_div(n, 4);
+    int64_t b = ceil_div(n, 4 * kRows);
     return b < kAttractBlocksMax ? b : kAttractBlocksMax;
 }
 
@@ -901,22 +940,25 @@ hipError_t run_tree(pixelsne_ctx* c) {
     k_rows_scan<<<dim3((unsigned)(c->L + 1)), kBlock, 0, c->stream>>>(tb.lvl_cnt, tb.tree_blocks,
                                                                       tb.ltot);
     k_tree_nodes<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
-        keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.parent,
-        tb.first_child, tb.arrive, tb.nodes, tb.leaf_of);
+        keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child, tb.nodes,
+        tb.leaf_of);
     if (fp64(c)) {
         k_leaf_scan<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             perm, tb.leaf_of, (const double*)c->z, c->n, tb.nsum, (double*)tb.zs, tb.wfirst,
             tb.wlast);
-        k_tree_up<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.parent, tb.first_child, tb.arrive,
-            tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+        k_tree_leaves<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
     } else {
         k_leaf_scan<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             perm, tb.leaf_of, (const float*)c->z, c->n, tb.nsum, (float*)tb.zs, tb.wfirst,
             tb.wlast);
-        k_tree_up<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.parent, tb.first_child, tb.arrive,
-            tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+        k_tree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+    }
+    for (int l = c->L - 1; l >= 0; l--) {
+        const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;
+        k_tree_level<<<grid_for(cap < c->n ? cap : c->n), kBlock, 0, c->stream>>>(
+            keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.nsum);
     }
     return hipGetLastError();
 }

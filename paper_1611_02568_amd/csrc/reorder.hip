@@ -36,23 +36,59 @@ __global__ __launch_bounds__(kBlock) void k_reorder_index(const uint32_t* __rest
     }
 }
 
-// one wavefront per new row: copy the old row with its columns renumbered
+constexpr int kSortMax = 512;   // rows up to this length get their columns sorted
+
+// One wavefront per new row: the old row's columns are renumbered and, for
+// rows of at most kSortMax entries, sorted ascending (bitonic sort of
+// (column, position) keys in LDS), so that the attraction's gathers walk
+// memory in order.  Longer rows are copied in their old order.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reorder_csr(
     const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv,
     const int64_t* __restrict__ rp2, uint32_t* __restrict__ col2, T* __restrict__ val2,
     int64_t n) {
-    const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    __shared__ uint64_t sk[kBlock / kWave][kSortMax];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint64_t* key = sk[w];
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + w;
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
     for (int64_t s = wave; s < n; s += nw) {
         const uint32_t i = perm[s];
         const int64_t b = rp[i], m = rp[i + 1] - b, o = rp2[s];
-        for (int64_t e = lane; e < m; e += kWave) {
-            col2[o + e] = inv[col[b + e]];
-            val2[o + e] = val[b + e];
+        if (m > kSortMax) {
+            for (int64_t e = lane; e < m; e += kWave) {
+                col2[o + e] = inv[col[b + e]];
+                val2[o + e] = val[b + e];
+            }
+            continue;
         }
+        int P = kWave;
+        while (P < m) P <<= 1;
+        for (int e = lane; e < P; e += kWave)
+            key[e] = e < m ? (((uint64_t)inv[col[b + e]] << 32) | (uint32_t)e) : ~0ull;
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < P / 2; t += kWave) {
+                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const int c = a | j;
+                    const uint64_t x = key[a], y = key[c];
+                    const bool up = (a & k) == 0;
+                    if ((x > y) == up) {
+                        key[a] = y;
+                        key[c] = x;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        for (int e = lane; e < m; e += kWave) {
+            const uint64_t kk = key[e];
+            col2[o + e] = (uint32_t)(kk >> 32);
+            val2[o + e] = val[b + (uint32_t)kk];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -154,7 +190,7 @@ hipError_t run_reorder(pixelsne_ctx* c) {
                                                                   c->inv, c->orig2, c->len_tmp);
     if ((e = scan_i64(c->len_tmp, c->n + 1, c->row_ptr2, c->scan_tmp, c->stream)) != hipSuccess)
         return e;
-    const int64_t waves = c->n < 65536 ? c->n : 65536;
+    const int64_t waves = c->n < 32768 ? c->n : 32768;
     const dim3 g((unsigned)ceil_div(waves, kBlock / kWave));
     if (fp64(c)) {
         k_reorder_csr<double><<<g, kBlock, 0, c->stream>>>(

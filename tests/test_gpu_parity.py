@@ -46,11 +46,18 @@ def _ctx(psne, P, r, prec, com_mode=0, theta=0.5, y0=None):
                                com_mode=com_mode, theta=theta)
 
 
-def _tree_check(ctx, z64, r):
+def _tree_check(ctx, z64, r, exact_ties=True):
+    """exact_ties: points sharing a pixel keep the caller's index order.  After
+    internal renumbering they follow the internal order instead, so only the
+    set of points of each pixel is unique."""
     tr = ctx.export_tree()
     keys, perm = oracle.sorted_order(z64, r)
     assert np.array_equal(tr["keys"].cpu().numpy().view(np.uint32), keys)
-    assert np.array_equal(tr["perm"].cpu().numpy().astype(np.int64), perm)
+    gperm = tr["perm"].cpu().numpy().astype(np.int64)
+    if not exact_ties:
+        run = np.concatenate([[0], np.cumsum(np.diff(keys.astype(np.int64)) != 0)])
+        gperm = gperm[np.lexsort((gperm, run))]
+    assert np.array_equal(gperm, perm)
     otree = oracle.Tree(z64, r)
     sizes = otree.level_sizes()
     assert tr["level_size"] == sizes.tolist()
@@ -261,7 +268,7 @@ def test_reorder_keeps_caller_order(psne, small_problem, prec):
     assert np.linalg.norm(R - og["R"]) <= TOL_B[prec] * np.linalg.norm(og["R"])
     Zi = g["Zi"].cpu().numpy()
     np.testing.assert_allclose(Zi, og["Zi"], rtol=1e-5 if prec == 0 else 1e-12)
-    _tree_check(ctx, zt.astype(np.float64), 512)
+    _tree_check(ctx, zt.astype(np.float64), 512, exact_ties=False)
     rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
     assert np.array_equal(rp, P[0]) and np.array_equal(col, P[1])
     np.testing.assert_allclose(val, P[2], rtol=6e-8 if prec == 0 else 0)
