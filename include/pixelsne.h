@@ -216,6 +216,14 @@ psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uin
 psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_ptr,
                               int32_t* col, double* val);
 
+/*
+ * KL(P || Q) of Eq. (4) for the current embedding with the exact normaliser
+ * Z = sum over ordered pairs i != j of w_ij (O(n^2) pairs on the GPU; pair
+ * terms in FP32 summed in FP64) and sum over the nonzeros of p (ln p - ln w_ij)
+ * in FP64; P as stored (un-exaggerated).  *kl host double.  Synchronises.
+ */
+psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl);
+
 /* ---------------------------------------------------------------------- */
 /* Setup stages as standalone calls (all device pointers, stream-ordered)  */
 /* ---------------------------------------------------------------------- */
@@ -239,6 +247,52 @@ psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, i
  */
 psne_status pixelsne_perplexity(const double* d2, int64_t n, int32_t k, double perplexity,
                                 double* P, double* beta, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned placement network                                               */
+/* ---------------------------------------------------------------------- */
+/*
+ * A small MLP maps a point x (dimension d_in) to its screen position z / r in
+ * [0,1)^2 of a converged embedding: Linear(d_in,h1) - GELU - Linear(h1,h2) -
+ * GELU - Linear(h2,2), GELU(x) = x Phi(x).  It places new points, or all
+ * points of a new run, before a few ordinary iterations refine them.  Matrix
+ * products take bfloat16 operands (inputs, weights and activations rounded to
+ * nearest even) on the MFMA units and accumulate in FP32; master weights and
+ * the Adam moments are FP32.  Inputs are standardised per feature first.
+ * Parameters and gradients are flat FP32 vectors laid out as
+ * W1 [d_in][h1], b1 [h1], W2 [h1][h2], b2 [h2], W3 [h2][2], b3 [2] (row-major).
+ * X device float32 [n][d_in]; Y01 device float32 [n][2].  All calls are
+ * stream-ordered on the stream given at creation and synchronise it before
+ * returning.  Weights start He-normal from the seed, biases at zero.
+ */
+typedef struct pixelsne_mlp pixelsne_mlp;
+
+pixelsne_mlp* pixelsne_mlp_create(int32_t d_in, int32_t h1, int32_t h2, uint64_t seed,
+                                  void* stream);
+void pixelsne_mlp_destroy(pixelsne_mlp* m);
+int64_t pixelsne_mlp_num_params(const pixelsne_mlp* m);
+/* theta: device float32 [num_params] */
+psne_status pixelsne_mlp_set_params(pixelsne_mlp* m, const float* theta);
+psne_status pixelsne_mlp_get_params(const pixelsne_mlp* m, float* theta);
+/* standardisation x^ = (x - mean) * inv_std; device float32 [d_in] each */
+psne_status pixelsne_mlp_set_norm(pixelsne_mlp* m, const float* mean, const float* inv_std);
+/* mean and 1 / population std of each feature of X (FP64 accumulation) */
+psne_status pixelsne_mlp_fit_norm(pixelsne_mlp* m, const float* X, int64_t n);
+/* loss = (1/n) sum_i |MLP(x_i) - y_i|^2 over one batch of n <= 2^20 rows and its
+ * gradient (device float32 [num_params], may be NULL); loss host double. */
+psne_status pixelsne_mlp_grad(pixelsne_mlp* m, const float* X, const float* Y01, int64_t n,
+                              float* grads_out, double* loss);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over `epochs` passes of shuffled full
+ * batches; the mean loss of the last epoch goes to *last_epoch_loss. */
+psne_status pixelsne_mlp_train(pixelsne_mlp* m, const float* X, const float* Y01, int64_t n,
+                               int32_t epochs, int32_t batch, float lr, double* last_epoch_loss);
+/* Y01_out device float32 [n][2] */
+psne_status pixelsne_mlp_forward(pixelsne_mlp* m, const float* X, int64_t n, float* Y01_out);
+/* Initial embedding for pixelsne_init_ex's Y_init: y = clamp(MLP(x), 0,
+ * 1 - 2^-24) * screen * s per axis, s = y units per pixel of the run the
+ * network was trained on (host double[2]).  Y_out device float64 [n][2]. */
+psne_status pixelsne_mlp_place(pixelsne_mlp* m, const float* X, int64_t n, int32_t screen,
+                               const double* s, double* Y_out);
 
 #ifdef __cplusplus
 }

@@ -486,6 +486,14 @@ psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_
     return PSNE_OK;
 }
 
+psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl) {
+    if (!c || !kl) return invalid("null argument");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    hipError_t e = run_kl(c, kl);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "kl");
+    return PSNE_OK;
+}
+
 psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
                          int32_t* idx, double* d2, void* stream) {
     if (n < 2 || n >= ((int64_t)1 << 31)) return invalid("n must be in [2, 2^31)");

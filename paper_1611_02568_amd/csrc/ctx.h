@@ -103,6 +103,8 @@ hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g);
 hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm,
                            uint32_t* prefix, uint32_t* count, double* sum);
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
+// exact-Z KL of the current state (synchronises)
+hipError_t run_kl(const pixelsne_ctx* c, double* kl);
 // renumbering (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_identity_order(pixelsne_ctx* c);

@@ -14,6 +14,8 @@
 //   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
 #include <math.h>
 
+#include <vector>
+
 #include "ctx.h"
 
 namespace psne {
@@ -875,6 +877,88 @@ __global__ __launch_bounds__(kBlock) void k_cast_val(const double* __restrict__ 
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < m) b[i] = (T)a[i];
 }
+// ---------------------------------------------------------------------------
+// KL(P || Q) of Eq. (4) with the exact normaliser Z = sum over ordered pairs
+// i != j of w_ij (O(n^2) pairs, FP32 terms summed in FP64 per 256-point tile)
+// and sum_nnz p (ln p - ln w_ij) in FP64.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kl_z(const T* __restrict__ zh,
+                                                 const DevScalars* __restrict__ sc, int64_t n,
+                                                 int r, double* __restrict__ part) {
+    __shared__ float2 tile[kBlock];
+    __shared__ double red[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const double s0 = sc->s[0], s1 = sc->s[1];
+    const float b1 = (float)(s0 * s0), b2 = (float)(s1 * s1);
+    float2 zi = float2{0.f, 0.f};
+    if (i < n) {
+        const v2_t<T> p = norm_pos<T>(zh, sc, i, r);
+        zi = float2{(float)p.x, (float)p.y};
+    }
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += kBlock) {
+        __syncthreads();
+        const int64_t j = j0 + threadIdx.x;
+        if (j < n) {
+            const v2_t<T> p = norm_pos<T>(zh, sc, j, r);
+            tile[threadIdx.x] = float2{(float)p.x, (float)p.y};
+        }
+        __syncthreads();
+        const int m = n - j0 < kBlock ? (int)(n - j0) : kBlock;
+        float sacc = 0.f;
+        for (int q = 0; q < m; q++) {
+            const float dx = zi.x - tile[q].x, dy = zi.y - tile[q].y;
+            const float w = __builtin_amdgcn_rcpf(1.0f + b1 * dx * dx + b2 * dy * dy);
+            sacc += (j0 + q == i) ? 0.f : w;
+        }
+        if (i < n) acc += (double)sacc;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// per row: sum p ln p - p ln w_ij and sum p (one wavefront per row)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kl_p(const int64_t* __restrict__ rp,
+                                                 const uint32_t* __restrict__ col,
+                                                 const T* __restrict__ val,
+                                                 const T* __restrict__ zh,
+                                                 const DevScalars* __restrict__ sc, int64_t n,
+                                                 int r, double* __restrict__ part) {
+    __shared__ double red[4][2];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + w, nw = (int64_t)gridDim.x * 4;
+    const double s0 = sc->s[0], s1 = sc->s[1];
+    const double b1 = s0 * s0, b2 = s1 * s1;
+    double a = 0.0, ps = 0.0;
+    for (int64_t i = wave; i < n; i += nw) {
+        const v2_t<T> zi = norm_pos<T>(zh, sc, i, r);
+        for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
+            const double p = (double)val[e];
+            if (!(p > 0.0)) continue;
+            const v2_t<T> zj = norm_pos<T>(zh, sc, col[e], r);
+            const double dx = (double)zi.x - (double)zj.x, dy = (double)zi.y - (double)zj.y;
+            const double w1 = 1.0 + b1 * dx * dx + b2 * dy * dy;     // 1 / w_ij
+            a += p * log(p) + p * log(w1);
+            ps += p;
+        }
+    }
+    a = wave_sum(a);
+    ps = wave_sum(ps);
+    if (lane == 0) { red[w][0] = a; red[w][1] = ps; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+        part[2 * blockIdx.x + 1] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    }
+}
+
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
 inline int64_t attract_blocks(int64_t n) {
@@ -1121,6 +1205,42 @@ hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm
         k_export_tree<<<grid_for(tb.max_nodes), kBlock, 0, c->stream>>>(
             tb.nodes, tb.nsum, tb.key[tb.sorted], c->sc, c->L, prefix, count, sum);
     return hipGetLastError();
+}
+
+hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
+    const int64_t nbz = ceil_div(c->n, kBlock);
+    const int64_t nbp = c->n / 4 < 4096 ? (c->n + 3) / 4 : 4096;
+    double* part = nullptr;
+    hipError_t e = hipMallocAsync((void**)&part, 8 * (size_t)(nbz + 2 * nbp), c->stream);
+    if (e != hipSuccess) return e;
+    if (fp64(c)) {
+        k_kl_z<double><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
+                                                                     c->n, c->r, part);
+        k_kl_p<double><<<dim3((unsigned)nbp), kBlock, 0, c->stream>>>(
+            c->row_ptr, c->col, (const double*)c->val, (const double*)c->zh, c->sc, c->n, c->r,
+            part + nbz);
+    } else {
+        k_kl_z<float><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const float*)c->zh, c->sc,
+                                                                    c->n, c->r, part);
+        k_kl_p<float><<<dim3((unsigned)nbp), kBlock, 0, c->stream>>>(
+            c->row_ptr, c->col, (const float*)c->val, (const float*)c->zh, c->sc, c->n, c->r,
+            part + nbz);
+    }
+    std::vector<double> h(nbz + 2 * nbp);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), part, 8 * h.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipFreeAsync(part, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    double Z = 0.0, a = 0.0, ps = 0.0;
+    for (int64_t b = 0; b < nbz; b++) Z += h[b];
+    for (int64_t b = 0; b < nbp; b++) {
+        a += h[nbz + 2 * b];
+        ps += h[nbz + 2 * b + 1];
+    }
+    *kl = a + ps * log(Z);
+    return hipSuccess;
 }
 
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64) {

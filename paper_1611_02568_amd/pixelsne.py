@@ -86,6 +86,19 @@ SIGNATURES = {
     "pixelsne_export_P": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp]),
     "pixelsne_knn": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "pixelsne_perplexity": (C.c_int, [_vp, _i64, _i32, _d, _vp, _vp, _vp]),
+    "pixelsne_mlp_create": (_vp, [_i32, _i32, _i32, _u64, _vp]),
+    "pixelsne_mlp_destroy": (None, [_vp]),
+    "pixelsne_mlp_num_params": (_i64, [_vp]),
+    "pixelsne_mlp_set_params": (C.c_int, [_vp, _vp]),
+    "pixelsne_mlp_get_params": (C.c_int, [_vp, _vp]),
+    "pixelsne_mlp_set_norm": (C.c_int, [_vp, _vp, _vp]),
+    "pixelsne_mlp_fit_norm": (C.c_int, [_vp, _vp, _i64]),
+    "pixelsne_mlp_grad": (C.c_int, [_vp, _vp, _vp, _i64, _vp, C.POINTER(C.c_double)]),
+    "pixelsne_mlp_train": (C.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, C.c_float,
+                                     C.POINTER(C.c_double)]),
+    "pixelsne_mlp_forward": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "pixelsne_mlp_place": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(C.c_double), _vp]),
+    "pixelsne_kl": (C.c_int, [_vp, C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -263,6 +276,12 @@ class Context:
         return {"level_size": sizes, "keys": keys, "perm": perm, "prefix": pre[:m],
                 "count": cnt[:m], "sum": sm[:m]}
 
+    def kl(self) -> float:
+        """KL(P || Q) with the exact normaliser (O(n^2) on the GPU)."""
+        v = C.c_double()
+        _check(load().pixelsne_kl(self._h, C.byref(v)))
+        return v.value
+
     def export_P(self):
         nnz = C.c_int64()
         _check(load().pixelsne_export_P(self._h, C.byref(nnz), None, None, None))
@@ -303,3 +322,74 @@ def perplexity(d2: torch.Tensor, u: float):
     beta = torch.empty(n, dtype=torch.float64, device=d2.device)
     _check(load().pixelsne_perplexity(_ptr(d2), n, k, float(u), _ptr(P), _ptr(beta), _stream()))
     return P, beta
+
+
+class MLP:
+    """Learned placement network on the GPU (wraps pixelsne_mlp*)."""
+
+    def __init__(self, d_in: int, h1: int, h2: int, seed: int = 0):
+        h = load().pixelsne_mlp_create(int(d_in), int(h1), int(h2), int(seed), _stream())
+        if not h:
+            raise PixelSNEError(PSNE_E_INVAL, _err())
+        self._h = C.c_void_p(h)
+        self.d, self.h1, self.h2 = d_in, h1, h2
+        self.n_params = load().pixelsne_mlp_num_params(self._h)
+
+    def params(self) -> torch.Tensor:
+        t = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(load().pixelsne_mlp_get_params(self._h, _ptr(t)))
+        return t
+
+    def set_params(self, theta):
+        t = torch.as_tensor(theta, dtype=torch.float32).cuda().contiguous()
+        _check(load().pixelsne_mlp_set_params(self._h, _ptr(t)))
+
+    def set_norm(self, mean, inv_std):
+        mu = torch.as_tensor(mean, dtype=torch.float32).cuda().contiguous()
+        isd = torch.as_tensor(inv_std, dtype=torch.float32).cuda().contiguous()
+        _check(load().pixelsne_mlp_set_norm(self._h, _ptr(mu), _ptr(isd)))
+
+    def fit_norm(self, X: torch.Tensor):
+        X = X.contiguous()
+        _check(load().pixelsne_mlp_fit_norm(self._h, _ptr(X), X.shape[0]))
+
+    def grad(self, X: torch.Tensor, Y01: torch.Tensor):
+        X, Y01 = X.contiguous(), Y01.contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        _check(load().pixelsne_mlp_grad(self._h, _ptr(X), _ptr(Y01), X.shape[0], _ptr(g),
+                                        C.byref(loss)))
+        return loss.value, g
+
+    def train(self, X: torch.Tensor, Y01: torch.Tensor, epochs: int, batch: int = 4096,
+              lr: float = 1e-3) -> float:
+        X, Y01 = X.contiguous(), Y01.contiguous()
+        loss = C.c_double()
+        _check(load().pixelsne_mlp_train(self._h, _ptr(X), _ptr(Y01), X.shape[0], int(epochs),
+                                         int(batch), float(lr), C.byref(loss)))
+        return loss.value
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.contiguous()
+        out = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda")
+        _check(load().pixelsne_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(out)))
+        return out
+
+    def place(self, X: torch.Tensor, screen: int, s) -> torch.Tensor:
+        """Initial embedding (float64 [n, 2], y frame) for Context.from_data(Y_init=...)."""
+        X = X.contiguous()
+        Y = torch.empty((X.shape[0], 2), dtype=torch.float64, device="cuda")
+        sv = (C.c_double * 2)(float(s[0]), float(s[1]))
+        _check(load().pixelsne_mlp_place(self._h, _ptr(X), X.shape[0], int(screen), sv, _ptr(Y)))
+        return Y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pixelsne_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

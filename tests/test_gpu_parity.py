@@ -285,3 +285,21 @@ def test_reorder_does_not_change_the_trajectory(psne, small_problem):
     ya = a.get_Y(psne.FRAME_Y).cpu().numpy()
     yb = b.get_Y(psne.FRAME_Y).cpu().numpy()
     assert np.max(np.abs(ya - yb)) <= 1e-8 * np.max(np.abs(yb))
+
+
+# --------------------------------------------------------------------------
+# KL with the exact normaliser (Eq. (4))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kl_matches_oracle(psne, small_problem, prec):
+    X, P, st = small_problem
+    dt = _state_dtype(prec)
+    zt = np.minimum(st.z.astype(dt), np.nextafter(dt(512), dt(0)))
+    ctx = _ctx(psne, P, 512, prec)
+    ctx.set_state(zt, st.s)
+    ref = oracle.kl(zt.astype(np.float64), st.s, P)
+    assert abs(ctx.kl() - ref) <= 1e-5 * ref
+    ctx.step(5)                                    # after steps: pending scaling + renumbering
+    got = ctx.get_state()
+    ref = oracle.kl(got["z"].double().cpu().numpy(), np.array(got["s"]), P)
+    assert abs(ctx.kl() - ref) <= 1e-5 * ref
