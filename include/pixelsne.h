@@ -224,6 +224,29 @@ psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_
  */
 psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl);
 
+/*
+ * The 32 nearest neighbours of every point in the current 2-D embedding
+ * y = s * z (distance b1 dz1^2 + b2 dz2^2 with b = s^2, FP64, self excluded,
+ * ties to the smaller index), by brute force on the GPU.
+ *   idx device int32 [n][32], caller order, ascending by distance.
+ * Requires n > 32.  Synchronises.
+ */
+psne_status pixelsne_knn2d(const pixelsne_ctx* c, int32_t* idx);
+
+/*
+ * Neighbourhood precision of Eq. (14) for each k in ks:
+ *   out[q] = (1 / (k N)) sum_i |N_D^(k)(i) intersect N_d^(k)(i)|,
+ * where N_D^(k)(i) is the first k entries of row i of hi_knn (the caller's
+ * high-dimensional neighbours, device int32 [n][k_hi], caller order, distinct
+ * entries, nearest first, e.g. from pixelsne_knn) and N_d^(k)(i) the first k
+ * of pixelsne_knn2d.  ks host int32 [nk] with 1 <= ks[q] <= min(k_hi, 32),
+ * 1 <= nk <= 64; out host double [nk].  Allocates scratch of 128 n bytes for
+ * the call.  Requires n > 32.  Synchronises.
+ */
+psne_status pixelsne_neighborhood_precision(const pixelsne_ctx* c, const int32_t* hi_knn,
+                                            int32_t k_hi, const int32_t* ks, int32_t nk,
+                                            double* out);
+
 /* ---------------------------------------------------------------------- */
 /* Setup stages as standalone calls (all device pointers, stream-ordered)  */
 /* ---------------------------------------------------------------------- */

@@ -16,6 +16,7 @@ Functions follow the paper's sections:
   normalize ............................. Section 3.2 (screen-driven scaling)
   gradient / iterate .................... Eq. 5 in the pixel frame, Eq. 13
   kl .................................... Eq. 4 with exact Z
+  neighborhood_precision ................ Eq. 14
 """
 from __future__ import annotations
 
@@ -329,3 +330,22 @@ def kl(z, s, P) -> float:
     z = _f64(z)
     rp, col, val = _csr(P)
     return float(_load().orc_kl(z, z.shape[0], _f64(s), rp, col, val))
+
+
+# --------------------------------------------------------------------------
+# Eq. 14: neighbourhood precision
+# --------------------------------------------------------------------------
+def neighborhood_precision(hi, lo, ks):
+    """(1 / kN) sum_i |N_D^(k)(i) intersect N_d^(k)(i)| for each k in ks, where
+    N_D^(k)(i) = first k entries of hi[i] (high-dimensional neighbours, nearest
+    first) and N_d^(k)(i) = first k of lo[i] (embedding neighbours)."""
+    hi = np.asarray(hi)
+    lo = np.asarray(lo)
+    n = hi.shape[0]
+    out = []
+    for k in ks:
+        common = 0
+        for i in range(n):
+            common += len(set(hi[i, :k].tolist()) & set(lo[i, :k].tolist()))
+        out.append(common / (k * n))
+    return out

@@ -23,6 +23,16 @@ psne_status device_error(pixelsne_ctx* c, hipError_t e, const char* where) {
     return e == hipErrorOutOfMemory ? PSNE_E_NOMEM : PSNE_E_DEVICE;
 }
 
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
 namespace {
 
 psne_status invalid(const std::string& m) {
@@ -65,16 +75,6 @@ psne_status check_screen(int32_t w, int32_t h, int* L) {
         return PSNE_E_UNSUPPORTED;
     }
     return PSNE_OK;
-}
-
-bool is_device_ptr(const void* p) {
-    if (!p) return false;
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
 template <typename P>

@@ -87,6 +87,30 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// largest value of T below r (positions are kept in [0, r))
+template <typename T> __device__ __forceinline__ T top_below(int r);
+template <> __device__ __forceinline__ float top_below<float>(int r) {
+    return __int_as_float(__float_as_int((float)r) - 1);
+}
+template <> __device__ __forceinline__ double top_below<double>(int r) {
+    return __longlong_as_double(__double_as_longlong((double)r) - 1);
+}
+
+// normalised position of point i: the pending screen scaling applied to zh
+// (same arithmetic as the snap pass)
+template <typename T>
+__device__ __forceinline__ v2_t<T> norm_pos(const T* __restrict__ zh,
+                                            const DevScalars* __restrict__ sc, int64_t i, int r) {
+    using V = v2_t<T>;
+    const T top = top_below<T>(r);
+    const V p = reinterpret_cast<const V*>(zh)[i];
+    T zx = (p.x - (T)sc->zmin[0]) * (T)sc->scale[0];
+    T zy = (p.y - (T)sc->zmin[1]) * (T)sc->scale[1];
+    zx = zx < T(0) ? T(0) : (zx > top ? top : zx);
+    zy = zy < T(0) ? T(0) : (zy > top ? top : zy);
+    return V{zx, zy};
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace psne

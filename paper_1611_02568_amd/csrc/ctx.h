@@ -83,6 +83,7 @@ namespace psne {
 
 void set_error(const std::string& msg);
 psne_status device_error(pixelsne_ctx* c, hipError_t e, const char* where);
+bool is_device_ptr(const void* p);
 
 // iteration passes (iter.hip); each enqueues on c->stream
 hipError_t run_snap(pixelsne_ctx* c);

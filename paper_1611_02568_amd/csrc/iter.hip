@@ -29,13 +29,6 @@ constexpr int kAttractBlocksMax = 8192;
 constexpr int kUnroll = 2;        // nonzeros per lane and row in flight in the attraction
 constexpr int kRows = 4;          // rows per wavefront at a time in the attraction
 
-template <typename T> __device__ __forceinline__ T top_below(int r);
-template <> __device__ __forceinline__ float top_below<float>(int r) {
-    return __int_as_float(__float_as_int((float)r) - 1);
-}
-template <> __device__ __forceinline__ double top_below<double>(int r) {
-    return __longlong_as_double(__double_as_longlong((double)r) - 1);
-}
 
 // ---------------------------------------------------------------------------
 // snap: z = clamp((zh - zmin) * scale, 0, r^-), key = Morton(floor(z))
@@ -778,20 +771,6 @@ __global__ __launch_bounds__(kBlock) void k_init_state(const double* __restrict_
     reinterpret_cast<V*>(zh)[i] = V{(T)y0, (T)y1};
     reinterpret_cast<V*>(u)[i] = V{T(0), T(0)};
     reinterpret_cast<V*>(g)[i] = V{T(1), T(1)};
-}
-
-// normalised position of point i (same arithmetic as k_snap)
-template <typename T>
-__device__ __forceinline__ v2_t<T> norm_pos(const T* __restrict__ zh,
-                                            const DevScalars* __restrict__ sc, int64_t i, int r) {
-    using V = v2_t<T>;
-    const T top = top_below<T>(r);
-    const V p = reinterpret_cast<const V*>(zh)[i];
-    T zx = (p.x - (T)sc->zmin[0]) * (T)sc->scale[0];
-    T zy = (p.y - (T)sc->zmin[1]) * (T)sc->scale[1];
-    zx = zx < T(0) ? T(0) : (zx > top ? top : zx);
-    zy = zy < T(0) ? T(0) : (zy > top ? top : zy);
-    return V{zx, zy};
 }
 
 template <typename T>

@@ -99,6 +99,9 @@ SIGNATURES = {
     "pixelsne_mlp_forward": (C.c_int, [_vp, _vp, _i64, _vp]),
     "pixelsne_mlp_place": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(C.c_double), _vp]),
     "pixelsne_kl": (C.c_int, [_vp, C.POINTER(C.c_double)]),
+    "pixelsne_knn2d": (C.c_int, [_vp, _vp]),
+    "pixelsne_neighborhood_precision": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32,
+                                                  C.POINTER(C.c_double)]),
 }
 
 _lib = None
@@ -281,6 +284,25 @@ class Context:
         v = C.c_double()
         _check(load().pixelsne_kl(self._h, C.byref(v)))
         return v.value
+
+    def knn2d(self) -> torch.Tensor:
+        """The 32 nearest neighbours of each point in the embedding, int32 [n, 32]."""
+        idx = torch.empty((self.n, 32), dtype=torch.int32, device="cuda")
+        _check(load().pixelsne_knn2d(self._h, _ptr(idx)))
+        return idx
+
+    def neighborhood_precision(self, hi_knn: torch.Tensor, ks) -> list:
+        """Eq. (14) precision of the embedding against high-dimensional neighbours
+        hi_knn (device int32 [n, k_hi], nearest first) for each k in ks."""
+        hi = hi_knn.to(torch.int32).contiguous()
+        if hi.dim() != 2 or hi.shape[0] != self.n or not hi.is_cuda:
+            raise ValueError("hi_knn must be a device tensor of shape [n, k_hi]")
+        ks = [int(k) for k in ks]
+        karr = (_i32 * len(ks))(*ks)
+        out = (C.c_double * len(ks))()
+        _check(load().pixelsne_neighborhood_precision(self._h, _ptr(hi), hi.shape[1], karr,
+                                                      len(ks), out))
+        return list(out)
 
     def export_P(self):
         nnz = C.c_int64()

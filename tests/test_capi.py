@@ -80,3 +80,6 @@ def test_null_context_calls(psne):
     lib.pixelsne_destroy(None)
     assert lib.pixelsne_knn(None, 10, 4, 0, 20, None, None, None) == psne.PSNE_E_INVAL
     assert lib.pixelsne_perplexity(None, 10, 5, -2.0, None, None, None) == psne.PSNE_E_INVAL
+    assert lib.pixelsne_kl(None, None) == psne.PSNE_E_INVAL
+    assert lib.pixelsne_knn2d(None, None) == psne.PSNE_E_INVAL
+    assert lib.pixelsne_neighborhood_precision(None, None, 10, None, 1, None) == psne.PSNE_E_INVAL

@@ -362,3 +362,38 @@ def test_kl_against_numpy(orc):
     s = np.array([0.03, 0.05])
     ref = ex.kl(z * s, ex.dense_from_csr(P, 120))
     assert abs(orc.kl(z, s, P) - ref) <= 1e-12 * abs(ref)
+
+
+def test_neighborhood_precision_hand_example(orc):
+    """Eq. 14 on five points on a line, counted by hand.
+
+    Embedding positions 0, 1, 3, 7, 15: the 2-D neighbour lists (nearest first)
+    are 0:[1,2,3,4] 1:[0,2,3,4] 2:[1,0,3,4] 3:[2,1,0,4] 4:[3,2,1,0].  The
+    high-dimensional lists below differ at chosen places:
+      k=1: agreements at points 0, 1, 3 -> 3/5
+      k=2: |{1,2}&{1,2}|=2, |{0,2}&{2,0}|=2, |{3,4}&{1,0}|=0,
+           |{2,1}&{2,1}|=2, |{0,1}&{3,2}|=0 -> 6/10
+      k=4: every list holds the other four points -> 1."""
+    y = np.array([[0.0, 0.0], [1.0, 0.0], [3.0, 0.0], [7.0, 0.0], [15.0, 0.0]])
+    lo, _ = orc.knn(y, 4)
+    assert lo.tolist() == [[1, 2, 3, 4], [0, 2, 3, 4], [1, 0, 3, 4], [2, 1, 0, 4], [3, 2, 1, 0]]
+    hi = np.array([[1, 2, 4, 3], [0, 2, 3, 4], [3, 4, 1, 0], [2, 1, 4, 0], [0, 1, 2, 3]])
+    p = orc.neighborhood_precision(hi, lo, [1, 2, 4])
+    assert p == [3 / 5, 6 / 10, 1.0]
+
+
+def test_neighborhood_precision_invariants(orc):
+    """Identical lists give 1; disjoint first-k lists give 0; precision of a
+    random list is k / (n - 1) in expectation (every other point equally
+    likely), checked on 400 points with 8 repeats."""
+    rng = np.random.default_rng(31)
+    n = 400
+    hi = np.stack([rng.permutation(np.delete(np.arange(n), i))[:30] for i in range(n)])
+    assert orc.neighborhood_precision(hi, hi, [1, 10, 30]) == [1.0, 1.0, 1.0]
+    lo = np.concatenate([hi[:, 5:], hi[:, :5]], axis=1)
+    assert orc.neighborhood_precision(hi, lo, [5]) == [0.0]
+    vals = []
+    for rep in range(8):
+        lo = np.stack([rng.permutation(np.delete(np.arange(n), i))[:30] for i in range(n)])
+        vals.append(orc.neighborhood_precision(hi, lo, [30])[0])
+    assert abs(np.mean(vals) - 30 / 399) < 0.006
