@@ -82,10 +82,11 @@ typedef struct {
     const double* Y_init;     /* optional device float64 [n][2] initial embedding
                                  (y frame); NULL => N(0, init_sigma^2) from seed */
     void* stream;             /* hipStream_t for all work; NULL => null stream */
-    int32_t reorder_every;    /* renumber points internally by their Morton order every
-                                 this many iterations (memory locality of the sparse
-                                 attraction); 0 = never [10].  Results are reported in the
-                                 caller's numbering either way. */
+    int32_t reorder_every;    /* renumber points internally by their Morton order after the
+                                 first iteration and then every this many iterations
+                                 (memory locality of the sparse attraction); 0 = never
+                                 [100].  Results are reported in the caller's numbering
+                                 either way. */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -98,7 +99,7 @@ void pixelsne_default_params(pixelsne_params* p);
  * sparse P = (P_cond + P_cond^T) / 2n in CSR (Section 2.3), an initial
  * embedding and its first screen scaling (Section 3.2).
  *   X          device, [n][D], float32 (pixelsne_init) or params.x_dtype
- *   n          number of points, 2 <= n < 2^31, k <= n - 1
+ *   n          number of points, 2 <= n < 2^27, k <= n - 1
  *   D          input dimension >= 1
  *   perplexity u > 0
  *   screen_w/h square power of two, 2 <= r <= 65536 (else PSNE_E_UNSUPPORTED)
@@ -113,7 +114,9 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
  * Create a context from a caller-built P instead of X (Section 2.3 CSR):
  *   row_ptr device int64 [n+1], col device int32 [nnz] (each row ascending,
  *   no diagonal), val device float64 [nnz] (sums to 1).  Copied into the
- *   context.  The initial embedding comes from params as for pixelsne_init_ex.
+ *   context; offsets and column ranges are checked on the device (NULL with
+ *   PSNE_E_INVAL if they are not a CSR of n rows).  2 <= n < 2^27.  The
+ *   initial embedding comes from params as for pixelsne_init_ex.
  */
 pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_ptr,
                                    const int32_t* col, const double* val, int32_t screen_w,

@@ -131,13 +131,15 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.leaf_of, 4 * (size_t)n)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.zs, v2)) != hipSuccess) return e;
-    // renumbering: spare copies of P and of the state, index maps
+    // renumbering: spare copies of the state, index maps, the chunked copy of P
     if ((e = dalloc(c, &c->orig, 4 * (size_t)n)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->orig2, 4 * (size_t)n)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->inv, 4 * (size_t)n)) != hipSuccess) return e;
-    if ((e = dalloc(c, &c->row_ptr2, 8 * (size_t)(n + 1))) != hipSuccess) return e;
-    if ((e = dalloc(c, &c->col2, 4 * (size_t)c->nnz)) != hipSuccess) return e;
-    if ((e = dalloc(c, &c->val2, state_bytes(c) * (size_t)c->nnz)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->rp_int, 8 * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->ch_row, 4 * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->ch_tmp, 8 * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->pk, 4 * (size_t)c->nnz)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->vch, state_bytes(c) * (size_t)c->nnz)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->zh2, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->u2, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->g2, v2)) != hipSuccess) return e;
@@ -171,8 +173,10 @@ psne_status finish_init(pixelsne_ctx* c) {
     if (e == hipErrorNotSupported) return PSNE_E_UNSUPPORTED;
     if (e != hipSuccess) return device_error(c, e, "allocation");
     if (c->prm.Y_init && !is_device_ptr(c->prm.Y_init)) return invalid("Y_init must be a device pointer");
-    e = run_identity_order(c);
-    if (e == hipSuccess) e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
+    // the initial state resets the device scalars; the chunked P (whose chunk
+    // count lives there) is built after it
+    e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
+    if (e == hipSuccess) e = run_identity_order(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_error(c, e, "initial embedding");
     return PSNE_OK;
@@ -208,7 +212,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->x_dtype = PSNE_X_F32;
     p->Y_init = nullptr;
     p->stream = nullptr;
-    p->reorder_every = 10;
+    p->reorder_every = 100;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -217,7 +221,7 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
     if (pin) p = *pin;
     else pixelsne_default_params(&p);
     if (check_params(&p) != PSNE_OK) return nullptr;
-    if (n < 2 || n >= ((int64_t)1 << 31)) { invalid("n must be in [2, 2^31)"); return nullptr; }
+    if (n < 2 || n >= ((int64_t)1 << kColBits)) { invalid("n must be in [2, 2^27)"); return nullptr; }
     if (D < 1) { invalid("D must be >= 1"); return nullptr; }
     if (!(perplexity > 0.0) || !isfinite(perplexity)) { invalid("perplexity must be > 0"); return nullptr; }
     const int64_t k = p.k > 0 ? p.k : (int64_t)floor(3.0 * perplexity);
@@ -276,7 +280,7 @@ pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_pt
     if (pin) p = *pin;
     else pixelsne_default_params(&p);
     if (check_params(&p) != PSNE_OK) return nullptr;
-    if (n < 2 || n >= ((int64_t)1 << 31)) { invalid("n must be in [2, 2^31)"); return nullptr; }
+    if (n < 2 || n >= ((int64_t)1 << kColBits)) { invalid("n must be in [2, 2^27)"); return nullptr; }
     if (nnz < 1) { invalid("nnz must be >= 1"); return nullptr; }
     int L;
     if (check_screen(screen_w, screen_h, &L) != PSNE_OK) return nullptr;
@@ -294,7 +298,15 @@ pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_pt
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->col, col, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = run_convert_val(c, val);
+    int64_t bad = 0;
+    if (e == hipSuccess) e = run_check_csr(c, &bad);
     if (e != hipSuccess) { device_error(c, e, "copying P"); free_ctx(c); return nullptr; }
+    if (bad) {
+        invalid("P is not a valid CSR (row_ptr from 0 to nnz, ascending; columns in [0, n) and off "
+                "the diagonal)");
+        free_ctx(c);
+        return nullptr;
+    }
     if (finish_init(c) != PSNE_OK) { free_ctx(c); return nullptr; }
     return c;
 }

@@ -11,6 +11,13 @@ namespace psne {
 constexpr int kWave = 64;
 constexpr int kMaxLevels = 17;          // L <= 16 (r <= 65536): levels 0..16
 
+// Row chunks of the attraction pass: at most kChunkRows rows; a chunk of more
+// than one row holds fewer than kChunkMaxNnz nonzeros.  Columns are packed
+// with the row-in-chunk into one word, so n < 2^kColBits.
+constexpr int kChunkRows = 32;
+constexpr int kChunkMaxNnz = 16384;
+constexpr int kColBits = 27;
+
 // Scalars that live on the device so that an iteration needs no host round
 // trip.  All FP64.
 struct DevScalars {
@@ -22,6 +29,7 @@ struct DevScalars {
     int32_t t;          // iterations done
     int32_t nonfinite;  // set when a non-finite position appears
     int64_t n_nodes;    // occupied cells of the last tree
+    int64_t n_chunks;   // row chunks of the attraction's copy of P
     uint32_t level_size[kMaxLevels];
     uint32_t level_base[kMaxLevels + 1];
 };

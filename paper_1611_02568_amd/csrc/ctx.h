@@ -40,7 +40,7 @@ struct pixelsne_ctx {
     int device = 0;
     bool poisoned = false;
 
-    // P in CSR
+    // P in CSR, in the caller's numbering (as given or as built by the setup)
     int64_t nnz = 0;
     int64_t* row_ptr = nullptr;
     uint32_t* col = nullptr;
@@ -62,19 +62,26 @@ struct pixelsne_ctx {
 
     // Internal order: points are renumbered by their Morton order every
     // prm.reorder_every iterations so that the neighbours of a CSR row sit
-    // close in memory.  orig[i] is the caller's index of internal point i.
+    // close in memory.  orig[i] is the caller's index of internal point i and
+    // inv its inverse.
     uint32_t* orig = nullptr;
     uint32_t* orig2 = nullptr;
     uint32_t* inv = nullptr;
-    int64_t* row_ptr2 = nullptr;
-    uint32_t* col2 = nullptr;
-    void* val2 = nullptr;
     void* zh2 = nullptr;
     void* u2 = nullptr;
     void* g2 = nullptr;
     int64_t* len_tmp = nullptr;              // [n + 1]
     int64_t* scan_tmp = nullptr;
     int32_t since_reorder = 0;
+
+    // P for the attraction pass: internal rows cut into chunks of at most
+    // kChunkRows consecutive rows; within a chunk the nonzeros are ordered by
+    // column, in runs of 64 that are each ordered by row.
+    int64_t* rp_int = nullptr;               // [n + 1] internal-order row offsets
+    uint32_t* ch_row = nullptr;              // [n + 1] first internal row of each chunk
+    int64_t* ch_tmp = nullptr;               // [n + 1] chunk numbering scratch
+    uint32_t* pk = nullptr;                  // [nnz] internal column | row-in-chunk << 27
+    void* vch = nullptr;                     // [nnz] values (state type)
 
     std::vector<void*> allocs;
 };
@@ -106,11 +113,14 @@ hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
 // exact-Z KL of the current state (synchronises)
 hipError_t run_kl(const pixelsne_ctx* c, double* kl);
-// renumbering (reorder.hip)
+// renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_identity_order(pixelsne_ctx* c);
-// P in the caller's numbering, columns ascending; row_ptr/col/val device, caller-owned
+// P in the caller's numbering; row_ptr/col/val device, caller-owned
 hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, double* val);
+// checks a caller's CSR (offsets monotone from 0 to nnz, columns in range and
+// off the diagonal); *bad (host) = number of violations.  Synchronises.
+hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad);
 // scatter an internal-order [n][2] state-type array to caller order
 hipError_t run_to_user_v2(const pixelsne_ctx* c, const void* in, void* out);
 hipError_t run_map_perm(const pixelsne_ctx* c, const uint32_t* perm, uint32_t* out);

@@ -26,8 +26,6 @@ constexpr int kBlock = 256;
 constexpr int kRsItems = 8;
 constexpr int kRsTile = kBlock * kRsItems;
 constexpr int kAttractBlocksMax = 8192;
-constexpr int kUnroll = 2;        // nonzeros per lane and row in flight in the attraction
-constexpr int kRows = 4;          // rows per wavefront at a time in the attraction
 
 
 // ---------------------------------------------------------------------------
@@ -554,84 +552,134 @@ template <typename T> __device__ __forceinline__ T sgn(T x) {
     return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
 }
 
-// One wavefront works on kRows consecutive rows at a time: the loads of all
-// of them are issued together (kRows x kUnroll column/value loads and
-// gathers per lane in flight), the row sums are reduced across the wave, and
-// lanes 0..kRows-1 apply the step to their row in parallel.
+// Lane-shifted copies within a wavefront (DPP).  CTRL selects the pattern:
+// row_shr:d moves lane l - d to lane l inside each row of 16 lanes;
+// row_bcast:15 / :31 broadcast lane 15 / 31 into the rows that follow.  Rows
+// outside ROWS keep their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_t(float v) {
+    return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_t(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROWS>((int)(uint32_t)b);
+    const int hi = dpp_i<CTRL, ROWS>((int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ void seg_step(T& x, T& y, int key, bool from_ok) {
+    const int k = dpp_i<CTRL, ROWS>(key);
+    const T ux = dpp_t<CTRL, ROWS>(x), uy = dpp_t<CTRL, ROWS>(y);
+    if (from_ok && k == key) {
+        x += ux;
+        y += uy;
+    }
+}
+
+// Inclusive scan of (x, y) over the lanes of each run of equal keys, for keys
+// ascending across the wave (Hillis-Steele: at each step a lane adds the
+// partial sum of the lane d below when both carry the same key; keys are
+// sorted, so that partial never leaves the run).  The last lane of a run ends
+// with the run's total.
+template <typename T>
+__device__ __forceinline__ void seg_scan(T& x, T& y, int key, int lane) {
+    seg_step<0x111, 0xF>(x, y, key, (lane & 15) >= 1);
+    seg_step<0x112, 0xF>(x, y, key, (lane & 15) >= 2);
+    seg_step<0x114, 0xF>(x, y, key, (lane & 15) >= 4);
+    seg_step<0x118, 0xF>(x, y, key, (lane & 15) >= 8);
+    seg_step<0x142, 0xA>(x, y, key, (lane & 16) != 0);
+    seg_step<0x143, 0xC>(x, y, key, lane >= 32);
+}
+
+constexpr int kBatches = 4;      // runs of 64 nonzeros per wavefront in flight
+
+// One block per row chunk (grid-stride over the chunks).  Wavefront w takes
+// the runs w, w + 4, ... of the chunk's nonzeros (column order, each run of
+// 64 ordered by row): loads kBatches runs at once, computes the terms
+// p_ij w_ij (z_i - z_j) with z_i from LDS, sums each row's terms across the
+// run with a segmented scan, and adds the totals to its own LDS partial sums
+// (one writer per address, no atomics).  Thread t < rows of the chunk then
+// adds the four waves' partials in a fixed order and applies the step to
+// row t.  Sums are therefore reproducible.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_attract(
-    const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
+    const uint32_t* __restrict__ ch_row, const int64_t* __restrict__ rp_int,
+    const uint32_t* __restrict__ pk, const T* __restrict__ val,
     const T* __restrict__ z, const T* __restrict__ R, T* __restrict__ u, T* __restrict__ g,
-    T* __restrict__ zh, DevScalars* __restrict__ sc, int64_t n, StepParams prm,
+    T* __restrict__ zh, DevScalars* __restrict__ sc, StepParams prm,
     const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout,
     double* __restrict__ mm_part) {
     using V = v2_t<T>;
+    __shared__ T acc[4][kChunkRows][2];
+    __shared__ V zrow[kChunkRows];
     __shared__ double red[4][4];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + w, nwaves = (int64_t)gridDim.x * 4;
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const double s0 = sc->s[0], s1 = sc->s[1];
     const T b1 = (T)(s0 * s0), b2 = (T)(s1 * s1);
     const double Z = sc->Z;
-    const int t = sc->t;
+    const int it = sc->t;
     const double alpha = MODE == 1 ? prm.alpha_override
-                                   : (t < prm.exag_iters ? prm.exaggeration : 1.0);
-    const T mu = (T)(t < prm.mom_switch ? prm.mom0 : prm.mom1);
+                                   : (it < prm.exag_iters ? prm.exaggeration : 1.0);
+    const T mu = (T)(it < prm.mom_switch ? prm.mom0 : prm.mom1);
     const T us0 = (T)sc->uscale[0], us1 = (T)sc->uscale[1];
     const T eta = (T)prm.eta, gmin = (T)prm.min_gain;
+    const int64_t nch = sc->n_chunks;
+    constexpr uint32_t kColMask = (1u << kColBits) - 1u;
     double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
     bool bad = false;
-    for (int64_t i0 = wave * kRows; i0 < n; i0 += nwaves * kRows) {
-        int64_t e0[kRows], e1[kRows];
-        V zi[kRows];
-        int64_t len = 0;
-#pragma unroll
-        for (int r = 0; r < kRows; r++) {
-            const int64_t i = i0 + r < n ? i0 + r : n - 1;
-            e0[r] = rp[i];
-            e1[r] = i0 + r < n ? rp[i + 1] : e0[r];
-            zi[r] = reinterpret_cast<const V*>(z)[i];
-            len = e1[r] - e0[r] > len ? e1[r] - e0[r] : len;
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const int64_t ra = ch_row[ch];
+        const int nr = (int)((int64_t)ch_row[ch + 1] - ra);
+        const int64_t e0 = rp_int[ra], e1 = rp_int[ra + nr];
+        if (t < kChunkRows) zrow[t] = t < nr ? reinterpret_cast<const V*>(z)[ra + t] : V{T(0), T(0)};
+        if (t < 4 * kChunkRows) {
+            acc[t / kChunkRows][t % kChunkRows][0] = T(0);
+            acc[t / kChunkRows][t % kChunkRows][1] = T(0);
         }
-        T ax[kRows], ay[kRows];
+        __syncthreads();
+        for (int64_t b = e0 + (int64_t)w * kWave; b < e1; b += (int64_t)kBlock * kBatches) {
+            uint32_t j[kBatches];
+            int r[kBatches];
+            T p[kBatches];
 #pragma unroll
-        for (int r = 0; r < kRows; r++) { ax[r] = T(0); ay[r] = T(0); }
-        for (int64_t base = lane; base < len; base += kWave * kUnroll) {
-            uint32_t j[kRows][kUnroll];
-            T p[kRows][kUnroll];
+            for (int q = 0; q < kBatches; q++) {
+                const int64_t x = b + q * kBlock + lane;
+                const bool ok = x < e1;
+                // streamed once: keep the per-CU cache for the gathered z_j
+                const uint32_t v = ok ? __builtin_nontemporal_load(&pk[x]) : 0u;
+                j[q] = v & kColMask;
+                r[q] = ok ? (int)(v >> kColBits) : kChunkRows;
+                p[q] = ok ? __builtin_nontemporal_load(&val[x]) : T(0);
+            }
+            V zj[kBatches];
 #pragma unroll
-            for (int r = 0; r < kRows; r++)
+            for (int q = 0; q < kBatches; q++) zj[q] = reinterpret_cast<const V*>(z)[j[q]];
 #pragma unroll
-                for (int q = 0; q < kUnroll; q++) {
-                    const int64_t e = e0[r] + base + q * kWave;
-                    const bool ok = e < e1[r];
-                    // streamed once: keep the per-CU cache for the gathered z_j
-                    j[r][q] = ok ? __builtin_nontemporal_load(&col[e]) : 0u;
-                    p[r][q] = ok ? __builtin_nontemporal_load(&val[e]) : T(0);
+            for (int q = 0; q < kBatches; q++) {
+                const V zi = zrow[r[q] < kChunkRows ? r[q] : 0];
+                const T dx = zi.x - zj[q].x, dy = zi.y - zj[q].y;
+                const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
+                const T pw = p[q] * wq;
+                T sx = pw * dx, sy = pw * dy;
+                seg_scan<T>(sx, sy, r[q], lane);
+                const int nk = __shfl_down(r[q], 1, kWave);
+                if (r[q] < kChunkRows && (lane == kWave - 1 || nk != r[q])) {
+                    acc[w][r[q]][0] += sx;
+                    acc[w][r[q]][1] += sy;
                 }
-            V zj[kRows][kUnroll];
-#pragma unroll
-            for (int r = 0; r < kRows; r++)
-#pragma unroll
-                for (int q = 0; q < kUnroll; q++) zj[r][q] = reinterpret_cast<const V*>(z)[j[r][q]];
-#pragma unroll
-            for (int r = 0; r < kRows; r++)
-#pragma unroll
-                for (int q = 0; q < kUnroll; q++) {
-                    const T dx = zi[r].x - zj[r][q].x, dy = zi[r].y - zj[r][q].y;
-                    const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
-                    const T pw = p[r][q] * wq;
-                    ax[r] += pw * dx;
-                    ay[r] += pw * dy;
-                }
+            }
         }
-        T mx = T(0), my = T(0);
-#pragma unroll
-        for (int r = 0; r < kRows; r++) {
-            const T sx = wave_sum(ax[r]), sy = wave_sum(ay[r]);
-            if (lane == r) { mx = sx; my = sy; }
-        }
-        const int64_t i = i0 + lane;
-        if (lane < kRows && i < n) {
+        __syncthreads();
+        if (t < nr) {
+            const T mx = ((acc[0][t][0] + acc[1][t][0]) + acc[2][t][0]) + acc[3][t][0];
+            const T my = ((acc[0][t][1] + acc[1][t][1]) + acc[2][t][1]) + acc[3][t][1];
+            const int64_t i = ra + t;
             const V Ri = reinterpret_cast<const V*>(R)[i];
             const T bx = (T)(alpha * (double)mx - (double)Ri.x / Z);
             const T by = (T)(alpha * (double)my - (double)Ri.y / Z);
@@ -639,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 if (Aout) reinterpret_cast<V*>(Aout)[orig[i]] = V{mx, my};
                 if (Bout) reinterpret_cast<V*>(Bout)[orig[i]] = V{bx, by};
             } else {
-                const V zii = reinterpret_cast<const V*>(z)[i];
+                const V zii = zrow[t];
                 V ui = reinterpret_cast<V*>(u)[i];
                 V gi = reinterpret_cast<V*>(g)[i];
                 ui.x *= us0;
@@ -661,6 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 mxy = fmax(mxy, (double)hy);
             }
         }
+        __syncthreads();
     }
     if (MODE == 1) return;
     if (ballot64(bad) && lane == 0) atomicOr(&sc->nonfinite, 1);
@@ -907,6 +956,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_kl_p(const int64_t* __restrict__ rp,
                                                  const uint32_t* __restrict__ col,
                                                  const T* __restrict__ val,
+                                                 const uint32_t* __restrict__ inv,
                                                  const T* __restrict__ zh,
                                                  const DevScalars* __restrict__ sc, int64_t n,
                                                  int r, double* __restrict__ part) {
@@ -917,11 +967,11 @@ __global__ __launch_bounds__(kBlock) void k_kl_p(const int64_t* __restrict__ rp,
     const double b1 = s0 * s0, b2 = s1 * s1;
     double a = 0.0, ps = 0.0;
     for (int64_t i = wave; i < n; i += nw) {
-        const v2_t<T> zi = norm_pos<T>(zh, sc, i, r);
+        const v2_t<T> zi = norm_pos<T>(zh, sc, inv[i], r);
         for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += kWave) {
             const double p = (double)val[e];
             if (!(p > 0.0)) continue;
-            const v2_t<T> zj = norm_pos<T>(zh, sc, col[e], r);
+            const v2_t<T> zj = norm_pos<T>(zh, sc, inv[col[e]], r);
             const double dx = (double)zi.x - (double)zj.x, dy = (double)zi.y - (double)zj.y;
             const double w1 = 1.0 + b1 * dx * dx + b2 * dy * dy;     // 1 / w_ij
             a += p * log(p) + p * log(w1);
@@ -941,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_kl_p(const int64_t* __restrict__ rp,
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
 inline int64_t attract_blocks(int64_t n) {
-    int64_t b = ceil_div(n, 4 * kRows);
+    int64_t b = ceil_div(n, kChunkRows / 2);
     return b < kAttractBlocksMax ? b : kAttractBlocksMax;
 }
 
@@ -1053,22 +1103,22 @@ hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B
         using T = double;
         if (mode == 0)
             k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
-                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, nullptr, nullptr, c->mm_part);
+                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
+                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, nullptr, nullptr, c->mm_part);
         else
             k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
-                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, (T*)A, (T*)B, c->mm_part);
+                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
+                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, (T*)A, (T*)B, c->mm_part);
     } else {
         using T = float;
         if (mode == 0)
             k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
-                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, nullptr, nullptr, c->mm_part);
+                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
+                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, nullptr, nullptr, c->mm_part);
         else
             k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
-                c->row_ptr, c->col, (const T*)c->val, (const T*)c->z, (const T*)c->R, (T*)c->u,
-                (T*)c->g, (T*)c->zh, c->sc, c->n, p, c->orig, (T*)A, (T*)B, c->mm_part);
+                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
+                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, (T*)A, (T*)B, c->mm_part);
     }
     return hipGetLastError();
 }
@@ -1196,13 +1246,13 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
         k_kl_z<double><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
                                                                      c->n, c->r, part);
         k_kl_p<double><<<dim3((unsigned)nbp), kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const double*)c->val, (const double*)c->zh, c->sc, c->n, c->r,
+            c->row_ptr, c->col, (const double*)c->val, c->inv, (const double*)c->zh, c->sc, c->n, c->r,
             part + nbz);
     } else {
         k_kl_z<float><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const float*)c->zh, c->sc,
                                                                     c->n, c->r, part);
         k_kl_p<float><<<dim3((unsigned)nbp), kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const float*)c->val, (const float*)c->zh, c->sc, c->n, c->r,
+            c->row_ptr, c->col, (const float*)c->val, c->inv, (const float*)c->zh, c->sc, c->n, c->r,
             part + nbz);
     }
     std::vector<double> h(nbz + 2 * nbp);

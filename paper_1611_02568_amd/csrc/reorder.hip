@@ -1,11 +1,16 @@
-// Internal renumbering of the points and conversions to the caller's order.
+// Internal renumbering of the points and the attraction pass's copy of P.
 //
 // The sparse attraction gathers z_j for every nonzero of row i.  When points
 // are numbered arbitrarily these gathers touch random cache lines of an
-// array larger than one XCD's L2.  Every few iterations the library therefore
-// renumbers the points by the Morton order of the last sort: P's rows and
-// columns and the per-point state are permuted on the device, so that rows
-// processed together and their neighbours occupy nearby memory.  The method's
+// array larger than one XCD's L2.  The library therefore renumbers the points
+// by the Morton order of a recent sort (after the first iteration, then every
+// params.reorder_every iterations): the per-point state is permuted, and P,
+// kept in the caller's numbering, is copied into the attraction's layout for
+// the new numbering.  That layout cuts the internal rows into chunks of up to
+// kChunkRows consecutive rows and orders each chunk's nonzeros by column, so
+// that the 64 gathers of one wavefront instruction fall on few cache lines;
+// each run of 64 is then ordered by row, which lets the attraction kernel sum
+// a row's terms with a segmented scan across the wave.  The method's
 // arithmetic is unchanged; only the order of the per-row summands changes.
 #include "ctx.h"
 
@@ -14,81 +19,22 @@ namespace psne {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int64_t kChunkHalf = kChunkMaxNnz / 2;
+constexpr int kBuildBlocksMax = 4096;
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 inline bool fp64(const pixelsne_ctx* c) { return c->prm.precision == PSNE_FP64; }
 
-// new index of old point perm[s] is s
+// new internal index of old internal point perm[s] is s
 __global__ __launch_bounds__(kBlock) void k_reorder_index(const uint32_t* __restrict__ perm,
                                                           const uint32_t* __restrict__ orig,
-                                                          const int64_t* __restrict__ rp,
                                                           int64_t n, uint32_t* __restrict__ inv,
-                                                          uint32_t* __restrict__ orig2,
-                                                          int64_t* __restrict__ len2) {
+                                                          uint32_t* __restrict__ orig2) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s < n) {
-        const uint32_t i = perm[s];
-        inv[i] = (uint32_t)s;
-        orig2[s] = orig[i];
-        len2[s] = rp[i + 1] - rp[i];
-    } else if (s == n) {
-        len2[n] = 0;
-    }
-}
-
-constexpr int kSortMax = 512;   // rows up to this length get their columns sorted
-
-// One wavefront per new row: the old row's columns are renumbered and, for
-// rows of at most kSortMax entries, sorted ascending (bitonic sort of
-// (column, position) keys in LDS), so that the attraction's gathers walk
-// memory in order.  Longer rows are copied in their old order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reorder_csr(
-    const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv,
-    const int64_t* __restrict__ rp2, uint32_t* __restrict__ col2, T* __restrict__ val2,
-    int64_t n) {
-    __shared__ uint64_t sk[kBlock / kWave][kSortMax];
-    const int lane = lane_id(), w = threadIdx.x >> 6;
-    uint64_t* key = sk[w];
-    const int64_t wave = (int64_t)blockIdx.x * (kBlock / kWave) + w;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t s = wave; s < n; s += nw) {
-        const uint32_t i = perm[s];
-        const int64_t b = rp[i], m = rp[i + 1] - b, o = rp2[s];
-        if (m > kSortMax) {
-            for (int64_t e = lane; e < m; e += kWave) {
-                col2[o + e] = inv[col[b + e]];
-                val2[o + e] = val[b + e];
-            }
-            continue;
-        }
-        int P = kWave;
-        while (P < m) P <<= 1;
-        for (int e = lane; e < P; e += kWave)
-            key[e] = e < m ? (((uint64_t)inv[col[b + e]] << 32) | (uint32_t)e) : ~0ull;
-        __builtin_amdgcn_wave_barrier();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < P / 2; t += kWave) {
-                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                    const int c = a | j;
-                    const uint64_t x = key[a], y = key[c];
-                    const bool up = (a & k) == 0;
-                    if ((x > y) == up) {
-                        key[a] = y;
-                        key[c] = x;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        for (int e = lane; e < m; e += kWave) {
-            const uint64_t kk = key[e];
-            col2[o + e] = (uint32_t)(kk >> 32);
-            val2[o + e] = val[b + (uint32_t)kk];
-        }
-        __builtin_amdgcn_wave_barrier();
+        const uint32_t u = orig[perm[s]];
+        orig2[s] = u;
+        inv[u] = (uint32_t)s;
     }
 }
 
@@ -108,9 +54,178 @@ __global__ __launch_bounds__(kBlock) void k_reorder_state(const uint32_t* __rest
     reinterpret_cast<V*>(b2)[s] = reinterpret_cast<const V*>(a2)[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_iota(uint32_t* __restrict__ a, int64_t n) {
+__global__ __launch_bounds__(kBlock) void k_iota2(uint32_t* __restrict__ a, uint32_t* __restrict__ b,
+                                                  int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) a[i] = (uint32_t)i;
+    if (i < n) {
+        a[i] = (uint32_t)i;
+        b[i] = (uint32_t)i;
+    }
+}
+
+// row lengths in internal order (entry n is 0, so that an exclusive scan of
+// n + 1 entries gives the offsets and the total)
+__global__ __launch_bounds__(kBlock) void k_int_len(const uint32_t* __restrict__ orig,
+                                                    const int64_t* __restrict__ rp, int64_t n,
+                                                    int64_t* __restrict__ len) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < n) {
+        const uint32_t u = orig[s];
+        len[s] = rp[u + 1] - rp[u];
+    } else if (s == n) {
+        len[n] = 0;
+    }
+}
+
+// A chunk starts at every kChunkRows-th row, where the row offset enters a
+// new window of kChunkHalf nonzeros, and around every row longer than
+// kChunkHalf.  So a chunk of several rows spans less than one window plus one
+// row of at most kChunkHalf: fewer than kChunkMaxNnz nonzeros.
+__device__ __forceinline__ bool chunk_start(const int64_t* __restrict__ rp, int64_t s) {
+    if (s == 0 || s % kChunkRows == 0) return true;
+    const int64_t a = rp[s - 1], b = rp[s], c = rp[s + 1];
+    return (a / kChunkHalf) != (b / kChunkHalf) || c - b > kChunkHalf || b - a > kChunkHalf;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_flags(const int64_t* __restrict__ rp, int64_t n,
+                                                        int64_t* __restrict__ flag) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < n) flag[s] = chunk_start(rp, s) ? 1 : 0;
+    else if (s == n) flag[n] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_rows(const int64_t* __restrict__ rp, int64_t n,
+                                                       const int64_t* __restrict__ cid,
+                                                       uint32_t* __restrict__ ch_row,
+                                                       DevScalars* __restrict__ sc) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < n) {
+        if (chunk_start(rp, s)) ch_row[cid[s]] = (uint32_t)s;
+    } else if (s == n) {
+        ch_row[cid[n]] = (uint32_t)n;
+        sc->n_chunks = cid[n];
+    }
+}
+
+// One block per chunk (grid-stride).  A chunk of one row is copied as it is.
+// For several rows (fewer than kChunkMaxNnz nonzeros), (column << 5 | row,
+// position) keys are sorted in LDS (bitonic), then every aligned run of 64 is
+// sorted again by (row, column); values are fetched from the caller-order CSR
+// through the positions.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_chunk_build(
+    const int64_t* __restrict__ rp_c, const uint32_t* __restrict__ col_c,
+    const T* __restrict__ val_c, const uint32_t* __restrict__ orig,
+    const uint32_t* __restrict__ inv, const int64_t* __restrict__ rp_int,
+    const uint32_t* __restrict__ ch_row, const DevScalars* __restrict__ sc,
+    uint32_t* __restrict__ pk, T* __restrict__ vch) {
+    __shared__ uint64_t key[kChunkMaxNnz];
+    __shared__ int64_t off[kChunkRows + 1];
+    __shared__ int64_t src[kChunkRows];
+    const int t = threadIdx.x;
+    const int64_t nch = sc->n_chunks;
+    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const int64_t ra = ch_row[ch], nr = (int64_t)ch_row[ch + 1] - ra;
+        const int64_t e0 = rp_int[ra], m = rp_int[ra + nr] - e0;
+        if (nr == 1 || m >= kChunkMaxNnz) {
+            // one row (any length), or a chunk the sort cannot hold (not made by
+            // the chunking rule): rows in order, each run of 64 is then ordered by row
+            for (int64_t lr = 0; lr < nr; lr++) {
+                const int64_t s0 = rp_c[orig[ra + lr]], o = rp_int[ra + lr];
+                const int64_t len = rp_int[ra + lr + 1] - o;
+                for (int64_t e = t; e < len; e += kBlock) {
+                    pk[o + e] = inv[col_c[s0 + e]] | ((uint32_t)lr << kColBits);
+                    vch[o + e] = val_c[s0 + e];
+                }
+            }
+            continue;
+        }
+        if (t <= nr) off[t] = rp_int[ra + t] - e0;
+        if (t < nr) src[t] = rp_c[orig[ra + t]];
+        __syncthreads();
+        int P = 64;
+        while (P < m) P <<= 1;
+        for (int e = t; e < P; e += kBlock) {
+            uint64_t k = ~0ull;
+            if (e < m) {
+                int lo = 0, hi = (int)nr;            // off[lo] <= e < off[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (off[mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t cn = inv[col_c[src[lo] + (e - off[lo])]];
+                k = ((uint64_t)((cn << 5) | (uint32_t)lo) << 32) | (uint32_t)e;
+            }
+            key[e] = k;
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int q = t; q < P / 2; q += kBlock) {
+                    const int a = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                    const int b = a | j;
+                    const uint64_t x = key[a], y = key[b];
+                    if ((x > y) == ((a & k) == 0)) {
+                        key[a] = y;
+                        key[b] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // re-key to (row, column, position): 5 + 27 + 14 bits
+        for (int p = t; p < m; p += kBlock) {
+            const uint64_t k = key[p];
+            const uint32_t hi = (uint32_t)(k >> 32);
+            key[p] = ((uint64_t)(hi & 31u) << 41) | ((uint64_t)(hi >> 5) << 14) |
+                     (uint64_t)(uint32_t)k;
+        }
+        __syncthreads();
+        for (int k = 2; k <= 64; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int q = t; q < P / 2; q += kBlock) {
+                    const int a = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                    const int b = a | j;
+                    const uint64_t x = key[a], y = key[b];
+                    const bool up = k == 64 || (a & k) == 0;
+                    if ((x > y) == up) {
+                        key[a] = y;
+                        key[b] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int p = t; p < m; p += kBlock) {
+            const uint64_t k = key[p];
+            const uint32_t lr = (uint32_t)(k >> 41);
+            const uint32_t cn = (uint32_t)(k >> 14) & ((1u << kColBits) - 1u);
+            const int64_t e = (int64_t)(k & 16383u);
+            pk[e0 + p] = cn | (lr << kColBits);
+            vch[e0 + p] = val_c[src[lr] + (e - off[lr])];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_csr(const int64_t* __restrict__ rp,
+                                                      const uint32_t* __restrict__ col, int64_t n,
+                                                      int64_t nnz,
+                                                      unsigned long long* __restrict__ bad) {
+    unsigned long long b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t a = rp[i], e = rp[i + 1];
+        if (i == 0 && a != 0) b++;
+        if (i == n - 1 && e != nnz) b++;
+        if (e < a || a < 0 || e > nnz) { b++; continue; }
+        for (int64_t q = a; q < e; q++) {
+            const uint32_t j = col[q];
+            if (j >= (uint64_t)n || j == (uint64_t)i) b++;
+        }
+    }
+    if (b) atomicAdd(bad, b);
 }
 
 template <typename T>
@@ -129,117 +244,98 @@ __global__ __launch_bounds__(kBlock) void k_map_perm(const uint32_t* __restrict_
     if (s < n) out[s] = orig[perm[s]];
 }
 
-// caller row u = internal row inv[u] (inv = inverse of orig)
-__global__ __launch_bounds__(kBlock) void k_user_index(const uint32_t* __restrict__ orig,
-                                                       const int64_t* __restrict__ rp, int64_t n,
-                                                       uint32_t* __restrict__ inv,
-                                                       int64_t* __restrict__ len) {
+__global__ __launch_bounds__(kBlock) void k_widen(const float* __restrict__ a, int64_t m,
+                                                  double* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-        const uint32_t u = orig[i];
-        inv[u] = (uint32_t)i;
-        len[u] = rp[i + 1] - rp[i];
-    } else if (i == n) {
-        len[n] = 0;
-    }
+    if (i < m) b[i] = (double)a[i];
 }
 
-constexpr int kRowLds = 4096;
-
-// One block per caller row: columns renumbered to the caller's indices and
-// sorted ascending (rank by counting; rows longer than kRowLds rank from
-// global memory), values widened to FP64.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_csr_to_user(
-    const int64_t* __restrict__ rp, const uint32_t* __restrict__ col, const T* __restrict__ val,
-    const uint32_t* __restrict__ orig, const uint32_t* __restrict__ inv,
-    const int64_t* __restrict__ rpu, int32_t* __restrict__ colu, double* __restrict__ valu) {
-    __shared__ uint32_t c_in[kRowLds];
-    const int64_t u = blockIdx.x;
-    const uint32_t i = inv[u];
-    const int64_t b = rp[i], m = rp[i + 1] - b, o = rpu[u];
-    const bool lds = m <= kRowLds;
-    if (lds)
-        for (int64_t e = threadIdx.x; e < m; e += kBlock) c_in[e] = orig[col[b + e]];
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < m; e += kBlock) {
-        const uint32_t ce = lds ? c_in[e] : orig[col[b + e]];
-        int64_t r = 0;
-        for (int64_t f = 0; f < m; f++) {
-            const uint32_t cf = lds ? c_in[f] : orig[col[b + f]];
-            r += (cf < ce || (cf == ce && f < e)) ? 1 : 0;
-        }
-        colu[o + r] = (int32_t)ce;
-        valu[o + r] = (double)val[b + e];
-    }
+hipError_t build_chunks(pixelsne_ctx* c) {
+    hipError_t e;
+    k_int_len<<<grid_for(c->n + 1), kBlock, 0, c->stream>>>(c->orig, c->row_ptr, c->n, c->len_tmp);
+    if ((e = scan_i64(c->len_tmp, c->n + 1, c->rp_int, c->scan_tmp, c->stream)) != hipSuccess) return e;
+    k_chunk_flags<<<grid_for(c->n + 1), kBlock, 0, c->stream>>>(c->rp_int, c->n, c->len_tmp);
+    if ((e = scan_i64(c->len_tmp, c->n + 1, c->ch_tmp, c->scan_tmp, c->stream)) != hipSuccess) return e;
+    k_chunk_rows<<<grid_for(c->n + 1), kBlock, 0, c->stream>>>(c->rp_int, c->n, c->ch_tmp, c->ch_row,
+                                                              c->sc);
+    const int64_t nb = c->n < kBuildBlocksMax ? c->n : kBuildBlocksMax;
+    if (fp64(c))
+        k_chunk_build<double><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(
+            c->row_ptr, c->col, (const double*)c->val, c->orig, c->inv, c->rp_int, c->ch_row, c->sc,
+            c->pk, (double*)c->vch);
+    else
+        k_chunk_build<float><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(
+            c->row_ptr, c->col, (const float*)c->val, c->orig, c->inv, c->rp_int, c->ch_row, c->sc,
+            c->pk, (float*)c->vch);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t run_identity_order(pixelsne_ctx* c) {
-    k_iota<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->orig, c->n);
-    c->since_reorder = 0;
-    return hipGetLastError();
+    k_iota2<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->orig, c->inv, c->n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the first renumbering follows the first iteration
+    c->since_reorder = c->prm.reorder_every > 0 ? c->prm.reorder_every - 1 : 0;
+    return build_chunks(c);
 }
 
 hipError_t run_reorder(pixelsne_ctx* c) {
     const TreeBufs& tb = c->tb;
     const uint32_t* perm = tb.idx[tb.sorted];
-    hipError_t e;
-    k_reorder_index<<<grid_for(c->n + 1), kBlock, 0, c->stream>>>(perm, c->orig, c->row_ptr, c->n,
-                                                                  c->inv, c->orig2, c->len_tmp);
-    if ((e = scan_i64(c->len_tmp, c->n + 1, c->row_ptr2, c->scan_tmp, c->stream)) != hipSuccess)
-        return e;
-    const int64_t waves = c->n < 32768 ? c->n : 32768;
-    const dim3 g((unsigned)ceil_div(waves, kBlock / kWave));
-    if (fp64(c)) {
-        k_reorder_csr<double><<<g, kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const double*)c->val, perm, c->inv, c->row_ptr2, c->col2,
-            (double*)c->val2, c->n);
+    k_reorder_index<<<grid_for(c->n), kBlock, 0, c->stream>>>(perm, c->orig, c->n, c->inv, c->orig2);
+    if (fp64(c))
         k_reorder_state<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             perm, (const double*)c->zh, (const double*)c->u, (const double*)c->g,
             (double*)c->zh2, (double*)c->u2, (double*)c->g2, c->n);
-    } else {
-        k_reorder_csr<float><<<g, kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const float*)c->val, perm, c->inv, c->row_ptr2, c->col2,
-            (float*)c->val2, c->n);
+    else
         k_reorder_state<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             perm, (const float*)c->zh, (const float*)c->u, (const float*)c->g, (float*)c->zh2,
             (float*)c->u2, (float*)c->g2, c->n);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    std::swap(c->row_ptr, c->row_ptr2);
-    std::swap(c->col, c->col2);
-    std::swap(c->val, c->val2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     std::swap(c->zh, c->zh2);
     std::swap(c->u, c->u2);
     std::swap(c->g, c->g2);
     std::swap(c->orig, c->orig2);
     c->since_reorder = 0;
-    return hipSuccess;
+    return build_chunks(c);
 }
 
 hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, double* val) {
-    int64_t* rp = row_ptr ? row_ptr : c->row_ptr2;
-    k_user_index<<<grid_for(c->n + 1), kBlock, 0, c->stream>>>(c->orig, c->row_ptr, c->n, c->inv,
-                                                               c->len_tmp);
-    hipError_t e = scan_i64(c->len_tmp, c->n + 1, rp, c->scan_tmp, c->stream);
-    if (e != hipSuccess || (!col && !val)) return e;
-    int32_t* cu = col ? col : (int32_t*)c->col2;
-    double* vu = val;
-    double* vtmp = nullptr;
-    if (!vu) {
-        if ((e = hipMallocAsync((void**)&vtmp, 8 * (size_t)c->nnz, c->stream)) != hipSuccess) return e;
-        vu = vtmp;
+    hipError_t e = hipSuccess;
+    if (row_ptr)
+        e = hipMemcpyAsync(row_ptr, c->row_ptr, 8 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e == hipSuccess && col)
+        e = hipMemcpyAsync(col, c->col, 4 * (size_t)c->nnz, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && val) {
+        if (fp64(c)) {
+            e = hipMemcpyAsync(val, c->val, 8 * (size_t)c->nnz, hipMemcpyDeviceToDevice, c->stream);
+        } else {
+            k_widen<<<grid_for(c->nnz), kBlock, 0, c->stream>>>((const float*)c->val, c->nnz, val);
+            e = hipGetLastError();
+        }
     }
-    if (fp64(c))
-        k_csr_to_user<double><<<dim3((unsigned)c->n), kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const double*)c->val, c->orig, c->inv, rp, cu, vu);
-    else
-        k_csr_to_user<float><<<dim3((unsigned)c->n), kBlock, 0, c->stream>>>(
-            c->row_ptr, c->col, (const float*)c->val, c->orig, c->inv, rp, cu, vu);
-    e = hipGetLastError();
-    if (vtmp) (void)hipFreeAsync(vtmp, c->stream);
+    return e;
+}
+
+hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad) {
+    unsigned long long* d = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d, sizeof(unsigned long long), c->stream);
+    if (e != hipSuccess) return e;
+    unsigned long long h = 0;
+    e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        const int64_t nb = ceil_div(c->n, kBlock) < 4096 ? ceil_div(c->n, kBlock) : 4096;
+        k_check_csr<<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(c->row_ptr, c->col, c->n, c->nnz, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFreeAsync(d, c->stream);
+    *bad = (int64_t)h;
     return e;
 }
 

@@ -254,7 +254,7 @@ def test_reorder_keeps_caller_order(psne, small_problem, prec):
     dt = _state_dtype(prec)
     ctx = psne.Context.from_P(*P, screen=512, Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=4)),
                               precision=prec, reorder_every=3)
-    ctx.step(10)                                  # three renumberings
+    ctx.step(10)                                  # renumbered after iterations 1, 4, 7, 10
     zt = np.minimum(st.z.astype(dt), np.nextafter(dt(512), dt(0)))
     ctx.set_state(zt, st.s)
     got = ctx.get_state()
