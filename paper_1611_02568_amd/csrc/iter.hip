@@ -467,9 +467,15 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
         const int level = (int)(info >> 8);
         const bool act = (mask >> lane) & 1ull;
         const double diag2 = ldexp(bsum, 2 * (L - level));
-        for (uint32_t q = 0; q < nsib; q++) {
+        // the group's records (children are consecutive) in one batch of scalar loads
+        Node grp[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) grp[q] = nodes[first + q];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; q++) {
+            if (q >= nsib) break;
             const uint32_t c = first + q;
-            const Node nd = nodes[c];
+            const Node nd = grp[q];
             bool open = false;
             if (act) {
                 nvis++;

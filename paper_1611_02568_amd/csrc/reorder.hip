@@ -107,21 +107,25 @@ __global__ __launch_bounds__(kBlock) void k_chunk_rows(const int64_t* __restrict
     }
 }
 
+constexpr int kBuildThreads = 1024;
+
 // One block per chunk (grid-stride).  A chunk of one row is copied as it is.
-// For several rows (fewer than kChunkMaxNnz nonzeros), (column << 5 | row,
-// position) keys are sorted in LDS (bitonic), then every aligned run of 64 is
-// sorted again by (row, column); values are fetched from the caller-order CSR
-// through the positions.
+// For several rows (fewer than kChunkMaxNnz nonzeros), the keys
+// column << 5 | row (unique: a row holds a column once) are sorted in LDS
+// (bitonic), then every aligned run of 64 is sorted again by (row, column).
+// A value is found in its caller row by binary search for the caller's column
+// (rows of the caller's P are ascending).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_chunk_build(
+__global__ __launch_bounds__(kBuildThreads) void k_chunk_build(
     const int64_t* __restrict__ rp_c, const uint32_t* __restrict__ col_c,
     const T* __restrict__ val_c, const uint32_t* __restrict__ orig,
     const uint32_t* __restrict__ inv, const int64_t* __restrict__ rp_int,
     const uint32_t* __restrict__ ch_row, const DevScalars* __restrict__ sc,
     uint32_t* __restrict__ pk, T* __restrict__ vch) {
-    __shared__ uint64_t key[kChunkMaxNnz];
+    __shared__ uint32_t key[kChunkMaxNnz];
     __shared__ int64_t off[kChunkRows + 1];
     __shared__ int64_t src[kChunkRows];
+    constexpr uint32_t kColMask = (1u << kColBits) - 1u;
     const int t = threadIdx.x;
     const int64_t nch = sc->n_chunks;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_build(
             for (int64_t lr = 0; lr < nr; lr++) {
                 const int64_t s0 = rp_c[orig[ra + lr]], o = rp_int[ra + lr];
                 const int64_t len = rp_int[ra + lr + 1] - o;
-                for (int64_t e = t; e < len; e += kBlock) {
+                for (int64_t e = t; e < len; e += kBuildThreads) {
                     pk[o + e] = inv[col_c[s0 + e]] | ((uint32_t)lr << kColBits);
                     vch[o + e] = val_c[s0 + e];
                 }
@@ -145,8 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_build(
         __syncthreads();
         int P = 64;
         while (P < m) P <<= 1;
-        for (int e = t; e < P; e += kBlock) {
-            uint64_t k = ~0ull;
+        for (int e = t; e < P; e += kBuildThreads) {
+            uint32_t k = ~0u;
             if (e < m) {
                 int lo = 0, hi = (int)nr;            // off[lo] <= e < off[hi]
                 while (hi - lo > 1) {
@@ -154,18 +158,17 @@ __global__ __launch_bounds__(kBlock) void k_chunk_build(
                     if (off[mid] <= e) lo = mid;
                     else hi = mid;
                 }
-                const uint32_t cn = inv[col_c[src[lo] + (e - off[lo])]];
-                k = ((uint64_t)((cn << 5) | (uint32_t)lo) << 32) | (uint32_t)e;
+                k = (inv[col_c[src[lo] + (e - off[lo])]] << 5) | (uint32_t)lo;
             }
             key[e] = k;
         }
         __syncthreads();
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int q = t; q < P / 2; q += kBlock) {
+                for (int q = t; q < P / 2; q += kBuildThreads) {
                     const int a = ((q & ~(j - 1)) << 1) | (q & (j - 1));
                     const int b = a | j;
-                    const uint64_t x = key[a], y = key[b];
+                    const uint32_t x = key[a], y = key[b];
                     if ((x > y) == ((a & k) == 0)) {
                         key[a] = y;
                         key[b] = x;
@@ -174,20 +177,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_build(
                 __syncthreads();
             }
         }
-        // re-key to (row, column, position): 5 + 27 + 14 bits
-        for (int p = t; p < m; p += kBlock) {
-            const uint64_t k = key[p];
-            const uint32_t hi = (uint32_t)(k >> 32);
-            key[p] = ((uint64_t)(hi & 31u) << 41) | ((uint64_t)(hi >> 5) << 14) |
-                     (uint64_t)(uint32_t)k;
+        // re-key to row << 27 | column and order each run of 64
+        for (int p = t; p < m; p += kBuildThreads) {
+            const uint32_t k = key[p];
+            key[p] = ((k & 31u) << kColBits) | (k >> 5);
         }
         __syncthreads();
         for (int k = 2; k <= 64; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int q = t; q < P / 2; q += kBlock) {
+                for (int q = t; q < P / 2; q += kBuildThreads) {
                     const int a = ((q & ~(j - 1)) << 1) | (q & (j - 1));
                     const int b = a | j;
-                    const uint64_t x = key[a], y = key[b];
+                    const uint32_t x = key[a], y = key[b];
                     const bool up = k == 64 || (a & k) == 0;
                     if ((x > y) == up) {
                         key[a] = y;
@@ -197,13 +198,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_build(
                 __syncthreads();
             }
         }
-        for (int p = t; p < m; p += kBlock) {
-            const uint64_t k = key[p];
-            const uint32_t lr = (uint32_t)(k >> 41);
-            const uint32_t cn = (uint32_t)(k >> 14) & ((1u << kColBits) - 1u);
-            const int64_t e = (int64_t)(k & 16383u);
-            pk[e0 + p] = cn | (lr << kColBits);
-            vch[e0 + p] = val_c[src[lr] + (e - off[lr])];
+        for (int p = t; p < m; p += kBuildThreads) {
+            const uint32_t k = key[p];
+            const uint32_t lr = k >> kColBits, cn = k & kColMask;
+            const uint32_t cu = orig[cn];
+            int64_t lo = src[lr], hi = src[lr] + (off[lr + 1] - off[lr]);   // col_c[pos] == cu
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col_c[mid] <= cu) lo = mid;
+                else hi = mid;
+            }
+            pk[e0 + p] = k;                                // column | row << 27
+            vch[e0 + p] = val_c[lo];
         }
         __syncthreads();
     }
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_check_csr(const int64_t* __restrict_
         if (e < a || a < 0 || e > nnz) { b++; continue; }
         for (int64_t q = a; q < e; q++) {
             const uint32_t j = col[q];
-            if (j >= (uint64_t)n || j == (uint64_t)i) b++;
+            if (j >= (uint64_t)n || j == (uint64_t)i || (q > a && j <= col[q - 1])) b++;
         }
     }
     if (b) atomicAdd(bad, b);
@@ -260,11 +266,11 @@ hipError_t build_chunks(pixelsne_ctx* c) {
                                                               c->sc);
     const int64_t nb = c->n < kBuildBlocksMax ? c->n : kBuildBlocksMax;
     if (fp64(c))
-        k_chunk_build<double><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(
+        k_chunk_build<double><<<dim3((unsigned)nb), kBuildThreads, 0, c->stream>>>(
             c->row_ptr, c->col, (const double*)c->val, c->orig, c->inv, c->rp_int, c->ch_row, c->sc,
             c->pk, (double*)c->vch);
     else
-        k_chunk_build<float><<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(
+        k_chunk_build<float><<<dim3((unsigned)nb), kBuildThreads, 0, c->stream>>>(
             c->row_ptr, c->col, (const float*)c->val, c->orig, c->inv, c->rp_int, c->ch_row, c->sc,
             c->pk, (float*)c->vch);
     return hipGetLastError();

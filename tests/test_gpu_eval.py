@@ -108,6 +108,9 @@ def test_precision_identity_and_minimum_size(psne):
 
 
 def _ring_P(n):
+    """Each point's two ring neighbours, p = 1/(2n) each (one neighbour for n = 2)."""
+    if n == 2:
+        return np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([0.5, 0.5])
     rp = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
     col = np.stack([(np.arange(n) - 1) % n, (np.arange(n) + 1) % n], 1)
     col = np.sort(col, 1).ravel().astype(np.int32)
