@@ -480,25 +480,25 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             if (act) {
                 nvis++;
                 double cx = nd.cx, cy = nd.cy, m = (double)nd.count;
-                bool use;
-                if (level == L) {
-                    if (c == own) {
-                        m -= 1.0;
-                        if (m > 0.0 && com_mode != PSNE_COM_CELL_CENTER) {
-                            const double2 sm = nsum[c];
-                            cx = (sm.x - zx) / m;
-                            cy = (sm.y - zy) / m;
-                        }
+                bool use = true;
+                if (level == L && c == own) {
+                    m -= 1.0;
+                    if (m > 0.0 && com_mode != PSNE_COM_CELL_CENTER) {
+                        const double2 sm = nsum[c];
+                        cx = (sm.x - zx) / m;
+                        cy = (sm.y - zy) / m;
                     }
                     use = m > 0.0;
-                } else {
-                    const double dx = zx - cx, dy = zy - cy;
-                    use = diag2 < mul_nc(th2, dist2(b1, b2, dx, dy));
+                }
+                // one distance serves the opening test and the force term
+                const double dx = zx - cx, dy = zy - cy;
+                const double d2 = dist2(b1, b2, dx, dy);
+                if (level != L) {
+                    use = diag2 < mul_nc(th2, d2);
                     open = !use;
                 }
                 if (use) {
-                    const double dx = zx - cx, dy = zy - cy;
-                    bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, m, zacc, rx, ry);
+                    bh_term<T>(d2, dx, dy, m, zacc, rx, ry);
                     nuse++;
                 }
             }
