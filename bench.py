@@ -15,6 +15,7 @@ roofline numbers.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,8 +32,31 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 78.6
 
 
+# Hardware byte counters per launch of the dominant kernels (rocprofv3 FETCH_SIZE
+# and WRITE_SIZE, scaled by what the counters read for a copy of known size),
+# valid while the kernel's source file is unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1M.json")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel's source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            entry = json.load(f)["kernels"].get(kernel)
+        if not entry:
+            return None
+        with open(os.path.join(ROOT, entry["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != entry["source_sha256"]:
+                return None
+        return (entry["fetch_kib"] * 1024 * entry["fetch_scale"]
+                + entry["write_kib"] * 1024 * entry["write_scale"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def tree_bytes(n, n_nodes, sb):
@@ -65,15 +89,27 @@ def run_gpu(args):
     Xd = torch.from_numpy(X).cuda()
     torch.cuda.synchronize()
 
-    log("[bench] setup (kNN, perplexity, P) in FP64")
+    g = 0 if args.no_graphs else 1
     t0 = time.perf_counter()
-    ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
+    if args.no_fp64:
+        log("[bench] setup (kNN, perplexity, P) for the FP32 path")
+        ctx64 = None
+        ctx32 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP32,
+                                           graphs=g)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+    else:
+        # one setup; the FP32 context takes the same P
+        log("[bench] setup (kNN, perplexity, P) in FP64")
+        ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64,
+                                           graphs=g)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        rp, col, val = ctx64.export_P()
+        ctx32 = pixelsne.Context.from_P(rp, col, val, 2048, Y_init=y0, precision=pixelsne.FP32,
+                                        graphs=g)
+        del rp, col, val
     del Xd
-    rp, col, val = ctx64.export_P()
-    ctx32 = pixelsne.Context.from_P(rp, col, val, 2048, Y_init=y0, precision=pixelsne.FP32)
-    del rp, col, val
     nnz = ctx32.stats().nnz
     log(f"[bench] setup {setup_s:.2f} s, nnz {nnz} ({nnz / n:.1f} per row)")
 
@@ -86,15 +122,15 @@ def run_gpu(args):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        # the timed region: K iterations, with HIP events recorded by the library
+        # on its stream (the caller's) between the passes of every iteration
         e0.record()
-        ctx.step_async(args.steps)
+        pt = ctx.step_profiled(args.steps).as_dict()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         st = ctx.stats()
         log(f"[bench] {name}: {args.steps} iterations in {ms:.1f} ms")
-        # the same number of iterations again, with per-pass HIP events
-        pt = ctx.step_profiled(args.steps).as_dict()
         g = ctx.gradient(1.0)
         vis = g["visits"].double().mean().item()
         used = g["used"].double().mean().item()
@@ -125,7 +161,34 @@ def run_gpu(args):
         if name == "fp32" and args.ttkl:
             # the FP32 run has now done 2,020 iterations: a converged embedding
             out["time_to_kl"] = time_to_kl(ctx, X, mix, args)
+    if "fp64" in out:
+        out["fp32_vs_fp64"] = compare_precisions(ctx32, ctx64)
     return out, setup_s, nnz
+
+
+def compare_precisions(ctx32, ctx64):
+    """Error of the FP32 path against the FP64 path on one snapshot (the FP64
+    run's final state rounded to FP32, loaded into both), and the final KL of
+    each run (exact Z)."""
+    import torch
+
+    kl32, kl64 = ctx32.kl(), ctx64.kl()
+    st = ctx64.get_state()
+    z = st["z"].float()
+    ctx64.set_state(z.double(), st["s"])
+    ctx32.set_state(z, st["s"])
+    g64, g32 = ctx64.gradient(1.0), ctx32.gradient(1.0)
+
+    def rel(k):
+        a, b = g32[k].double(), g64[k].double()
+        return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+
+    res = {"A_rel": rel("A"), "R_rel": rel("R"), "B_rel": rel("B"),
+           "Z_rel": abs(g32["Z"] - g64["Z"]) / g64["Z"],
+           "visits_equal_frac": (g32["visits"] == g64["visits"]).double().mean().item(),
+           "final_kl_fp32": kl32, "final_kl_fp64": kl64}
+    log(f"[bench] fp32 vs fp64: {json.dumps(res)}")
+    return res
 
 
 def _refine_until(ctx, target, max_iters, t_start, sync):
@@ -251,6 +314,8 @@ def main():
                     help="skip the learned-placement time-to-KL comparison")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--heldout", type=int, default=200_000)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch kernels one by one outside the timed region too")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this size once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -286,6 +351,7 @@ def main():
         ach = main32["tree_build"]["GBps"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    roof["traffic"] = measured_traffic(roof["kernel"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -316,6 +382,7 @@ def main():
                                      "ms_per_step": res["fp64"]["ms_per_step"]},
         "setup_s": setup_s,
         "time_to_kl": res.get("time_to_kl"),
+        "fp32_vs_fp64": res.get("fp32_vs_fp64"),
         "passes": {k: v for k, v in res.items() if k in ("fp32", "fp64")},
     }
     print(json.dumps(line), flush=True)

@@ -87,6 +87,10 @@ typedef struct {
                                  (memory locality of the sparse attraction); 0 = never
                                  [100].  Results are reported in the caller's numbering
                                  either way. */
+    int32_t graphs;           /* 1: pixelsne_step / _async replay one iteration as a HIP
+                                 graph (captured on first use; no launch overhead per
+                                 kernel); 0: launch the kernels one by one [1].  Results
+                                 are identical. */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */

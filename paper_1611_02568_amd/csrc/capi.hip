@@ -60,6 +60,7 @@ psne_status check_params(const pixelsne_params* p) {
         return invalid("unknown x_dtype");
     if (p->exag_iters < 0 || p->mom_switch < 0) return invalid("negative schedule length");
     if (p->reorder_every < 0) return invalid("reorder_every must be >= 0");
+    if (p->graphs != 0 && p->graphs != 1) return invalid("graphs must be 0 or 1");
     return PSNE_OK;
 }
 
@@ -153,8 +154,53 @@ void free_ctx(pixelsne_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    for (hipGraphExec_t& g : c->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
+}
+
+// The iteration's passes captured once per state-buffer parity on a private
+// stream (nothing runs during the capture) and replayed on the caller's stream.
+hipError_t capture_iteration(pixelsne_ctx* c, hipGraphExec_t* out) {
+    hipError_t e = hipSuccess;
+    if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e1 = e == hipSuccess ? run_iteration_passes(c) : e;
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    if (e == hipSuccess) e = e1;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+hipError_t step_one(pixelsne_ctx* c) {
+    hipError_t e = hipSuccess;
+    bool done = false;
+    if (c->prm.graphs && !c->graph_failed) {
+        hipGraphExec_t& ge = c->gexec[c->parity];
+        if (!ge && capture_iteration(c, &ge) != hipSuccess) {
+            // capture unavailable: launch the kernels directly from now on
+            (void)hipGetLastError();
+            if (ge) (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
+            c->graph_failed = true;
+        }
+        if (ge) {
+            e = hipGraphLaunch(ge, c->stream);
+            done = true;
+        }
+    }
+    if (!done) e = run_iteration_passes(c);
+    if (e == hipSuccess && c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
+        e = run_reorder(c);
+    return e;
 }
 
 pixelsne_ctx* new_ctx(int64_t n, int L, int32_t r, const pixelsne_params* p) {
@@ -214,6 +260,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->Y_init = nullptr;
     p->stream = nullptr;
     p->reorder_every = 100;
+    p->graphs = 1;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -317,7 +364,7 @@ psne_status pixelsne_step_async(pixelsne_ctx* c, int32_t n_iter) {
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
     if (n_iter < 0) return invalid("n_iter must be >= 0");
     for (int32_t it = 0; it < n_iter; it++) {
-        hipError_t e = run_iteration(c);
+        hipError_t e = step_one(c);
         if (e != hipSuccess) return device_error(c, e, "iteration");
     }
     return PSNE_OK;

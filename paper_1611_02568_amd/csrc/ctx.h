@@ -83,6 +83,13 @@ struct pixelsne_ctx {
     uint32_t* pk = nullptr;                  // [nnz] internal column | row-in-chunk << 27
     void* vch = nullptr;                     // [nnz] values (state type)
 
+    // one iteration captured as a HIP graph, one per state-buffer parity
+    // (renumbering swaps the state buffers with their spares)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int32_t parity = 0;
+    bool graph_failed = false;
+
     std::vector<void*> allocs;
 };
 
@@ -101,7 +108,8 @@ hipError_t run_zsum(pixelsne_ctx* c);
 // mode 0: gradient step; mode 1: write A and B only (no update)
 hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B);
 hipError_t run_finalize(pixelsne_ctx* c, int advance);
-hipError_t run_iteration(pixelsne_ctx* c);
+// the passes of one iteration without the renumbering
+hipError_t run_iteration_passes(pixelsne_ctx* c);
 // one iteration with events recorded before each pass and after the last (9 events)
 hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev);
 hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma);

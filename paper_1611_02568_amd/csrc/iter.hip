@@ -1135,7 +1135,7 @@ hipError_t run_finalize(pixelsne_ctx* c, int advance) {
     return hipGetLastError();
 }
 
-hipError_t run_iteration(pixelsne_ctx* c) {
+hipError_t run_iteration_passes(pixelsne_ctx* c) {
     hipError_t e;
     if ((e = run_snap(c)) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
@@ -1143,10 +1143,7 @@ hipError_t run_iteration(pixelsne_ctx* c) {
     if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;
     if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = run_finalize(c, 1)) != hipSuccess) return e;
-    if (c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
-        return run_reorder(c);
-    return hipSuccess;
+    return run_finalize(c, 1);
 }
 
 hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev) {
@@ -1246,7 +1243,7 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
     const int64_t nbz = ceil_div(c->n, kBlock);
     const int64_t nbp = c->n / 4 < 4096 ? (c->n + 3) / 4 : 4096;
     double* part = nullptr;
-    hipError_t e = hipMallocAsync((void**)&part, 8 * (size_t)(nbz + 2 * nbp), c->stream);
+    hipError_t e = hipMalloc((void**)&part, 8 * (size_t)(nbz + 2 * nbp));
     if (e != hipSuccess) return e;
     if (fp64(c)) {
         k_kl_z<double><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
@@ -1265,8 +1262,8 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
     e = hipGetLastError();
     if (e == hipSuccess)
         e = hipMemcpyAsync(h.data(), part, 8 * h.size(), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipFreeAsync(part, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(part);
     if (e != hipSuccess) return e;
     double Z = 0.0, a = 0.0, ps = 0.0;
     for (int64_t b = 0; b < nbz; b++) Z += h[b];

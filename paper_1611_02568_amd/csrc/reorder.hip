@@ -305,6 +305,7 @@ hipError_t run_reorder(pixelsne_ctx* c) {
     std::swap(c->u, c->u2);
     std::swap(c->g, c->g2);
     std::swap(c->orig, c->orig2);
+    c->parity ^= 1;
     c->since_reorder = 0;
     return build_chunks(c);
 }
@@ -329,7 +330,7 @@ hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, d
 
 hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad) {
     unsigned long long* d = nullptr;
-    hipError_t e = hipMallocAsync((void**)&d, sizeof(unsigned long long), c->stream);
+    hipError_t e = hipMalloc((void**)&d, sizeof(unsigned long long));
     if (e != hipSuccess) return e;
     unsigned long long h = 0;
     e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
@@ -340,7 +341,7 @@ hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFreeAsync(d, c->stream);
+    (void)hipFree(d);
     *bad = (int64_t)h;
     return e;
 }

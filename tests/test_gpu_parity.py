@@ -290,6 +290,25 @@ def test_reorder_does_not_change_the_trajectory(psne, small_problem):
     assert np.max(np.abs(ya - yb)) <= 1e-8 * np.max(np.abs(yb))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_matches_direct_launches(psne, small_problem, prec):
+    """Stepping through the captured iteration graph gives bit-identical states
+    to launching the kernels one by one, across renumberings (which switch
+    between the two captured graphs) and with other work between the calls."""
+    X, P, _ = small_problem
+    y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=6))
+    a = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3, graphs=1)
+    b = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3, graphs=0)
+    for k in (1, 2, 5, 4):
+        a.step(k)
+        b.step(k)
+        ya, yb = a.get_Y(psne.FRAME_Y), b.get_Y(psne.FRAME_Y)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, yb), k
+        sa, sb = a.get_state(), b.get_state()
+        assert torch.equal(sa["u"], sb["u"]) and torch.equal(sa["g"], sb["g"])
+
+
 # --------------------------------------------------------------------------
 # KL with the exact normaliser (Eq. (4))
 # --------------------------------------------------------------------------
