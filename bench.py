@@ -99,16 +99,14 @@ def run_gpu(args):
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
     else:
-        # one setup; the FP32 context takes the same P
-        log("[bench] setup (kNN, perplexity, P) in FP64")
-        ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64,
+        # the same setup for each path (identical P and initial numbering)
+        log("[bench] setup (kNN, perplexity, P), FP32 and FP64 paths")
+        ctx32 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP32,
                                            graphs=g)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
-        rp, col, val = ctx64.export_P()
-        ctx32 = pixelsne.Context.from_P(rp, col, val, 2048, Y_init=y0, precision=pixelsne.FP32,
-                                        graphs=g)
-        del rp, col, val
+        ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64,
+                                           graphs=g)
     del Xd
     nnz = ctx32.stats().nnz
     log(f"[bench] setup {setup_s:.2f} s, nnz {nnz} ({nnz / n:.1f} per row)")

@@ -87,6 +87,13 @@ typedef struct {
                                  (memory locality of the sparse attraction); 0 = never
                                  [100].  Results are reported in the caller's numbering
                                  either way. */
+    int32_t data_order;       /* pixelsne_init_ex only.  1: number the points internally by
+                                 a Morton code of three random projections of X, so that
+                                 neighbours in P sit close in memory before the embedding
+                                 has formed; the first renumbering by the embedding then
+                                 follows the early exaggeration.  0: start from the
+                                 caller's order [1].  Results are reported in the caller's
+                                 numbering either way. */
     int32_t graphs;           /* 1: pixelsne_step / _async replay one iteration as a HIP
                                  graph (captured on first use; no launch overhead per
                                  kernel); 0: launch the kernels one by one [1].  Results

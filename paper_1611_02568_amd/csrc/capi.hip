@@ -61,6 +61,7 @@ psne_status check_params(const pixelsne_params* p) {
     if (p->exag_iters < 0 || p->mom_switch < 0) return invalid("negative schedule length");
     if (p->reorder_every < 0) return invalid("reorder_every must be >= 0");
     if (p->graphs != 0 && p->graphs != 1) return invalid("graphs must be 0 or 1");
+    if (p->data_order != 0 && p->data_order != 1) return invalid("data_order must be 0 or 1");
     return PSNE_OK;
 }
 
@@ -260,6 +261,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->Y_init = nullptr;
     p->stream = nullptr;
     p->reorder_every = 100;
+    p->data_order = 1;
     p->graphs = 1;
 }
 
@@ -311,6 +313,11 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
     cleanup();
     if (e != hipSuccess) { device_error(c, e, "storing P"); free_ctx(c); return nullptr; }
     if (finish_init(c) != PSNE_OK) { free_ctx(c); return nullptr; }
+    if (p.data_order) {
+        e = run_data_order(c, X, D, p.x_dtype);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { device_error(c, e, "data order"); free_ctx(c); return nullptr; }
+    }
     return c;
 }
 

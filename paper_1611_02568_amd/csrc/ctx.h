@@ -102,6 +102,8 @@ bool is_device_ptr(const void* p);
 // iteration passes (iter.hip); each enqueues on c->stream
 hipError_t run_snap(pixelsne_ctx* c);
 hipError_t run_sort(pixelsne_ctx* c);
+// stable sort of (tb.key[0], index) on the low `bits` key bits
+hipError_t run_sort_bits(pixelsne_ctx* c, int bits);
 hipError_t run_tree(pixelsne_ctx* c);
 hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi);
 hipError_t run_zsum(pixelsne_ctx* c);
@@ -124,6 +126,10 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl);
 // renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_identity_order(pixelsne_ctx* c);
+// renumber by a Morton code of three random projections of X (rows of D
+// elements of x_dtype) and delay the first renumbering by the embedding to the
+// end of the early exaggeration
+hipError_t run_data_order(pixelsne_ctx* c, const void* X, int32_t D, int32_t x_dtype);
 // P in the caller's numbering; row_ptr/col/val device, caller-owned
 hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, double* val);
 // checks a caller's CSR (offsets monotone from 0 to nnz, columns in range and
@@ -136,6 +142,10 @@ hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hip
 int64_t scan_i64_tmp_len(int64_t m);
 
 // setup passes (setup.hip)
+// 30-bit Morton code of three random (+-1) projections of each row of X,
+// each quantised to 10 bits over its range; keys device uint32 [n]
+hipError_t projection_keys(const void* X, int64_t n, int32_t D, int32_t x_dtype, uint32_t* keys,
+                           hipStream_t s);
 hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,
                double* d2, hipStream_t s, std::string* err);
 hipError_t perplexity(const double* d2, int64_t n, int32_t k, double u, double* P,

@@ -1030,9 +1030,10 @@ hipError_t run_snap(pixelsne_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t run_sort(pixelsne_ctx* c) {
+hipError_t run_sort(pixelsne_ctx* c) { return run_sort_bits(c, 2 * c->L); }
+
+hipError_t run_sort_bits(pixelsne_ctx* c, int bits) {
     TreeBufs& tb = c->tb;
-    const int bits = 2 * c->L;
     const int passes = (bits + 7) / 8;
     int cur = 0;
     for (int p = 0; p < passes; p++) {

@@ -287,6 +287,20 @@ hipError_t run_identity_order(pixelsne_ctx* c) {
     return build_chunks(c);
 }
 
+hipError_t run_data_order(pixelsne_ctx* c, const void* X, int32_t D, int32_t x_dtype) {
+    hipError_t e = projection_keys(X, c->n, D, x_dtype, c->tb.key[0], c->stream);
+    if (e == hipSuccess) e = run_sort_bits(c, 30);
+    if (e == hipSuccess) e = run_reorder(c);
+    if (e != hipSuccess) return e;
+    // the embedding's own order is worth following once the early exaggeration
+    // has formed its clusters
+    if (c->prm.reorder_every > 0) {
+        const int32_t first = c->prm.exag_iters > 1 ? c->prm.exag_iters : 1;
+        c->since_reorder = c->prm.reorder_every - first;
+    }
+    return hipSuccess;
+}
+
 hipError_t run_reorder(pixelsne_ctx* c) {
     const TreeBufs& tb = c->tb;
     const uint32_t* perm = tb.idx[tb.sorted];

@@ -558,7 +558,123 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
     return fail(hipSuccess);
 }
 
+// ---------------------------------------------------------------------------
+// initial numbering: three random +-1 projections of each row, quantised and
+// interleaved into a Morton code (points close in X get close codes)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rademacher(int axis, int d) {
+    uint32_t h = (uint32_t)d * 0x9E3779B1u ^ (uint32_t)(axis + 1) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (h & 1u) ? 1.0f : -1.0f;
+}
+
+// one wavefront per row; proj [n][3]; per-block min/max of each axis
+template <typename X>
+__global__ __launch_bounds__(256) void k_project(const X* __restrict__ Xm, int64_t n, int D,
+                                                 float* __restrict__ proj,
+                                                 float* __restrict__ part) {
+    __shared__ float red[4][6];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+        float a[3] = {0.f, 0.f, 0.f};
+        for (int d = lane; d < D; d += 64) {
+            const float v = to_f32(Xm[i * D + d]);
+#pragma unroll
+            for (int q = 0; q < 3; q++) a[q] += rademacher(q, d) * v;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            a[q] = wave_sum(a[q]);
+            mn[q] = fminf(mn[q], a[q]);
+            mx[q] = fmaxf(mx[q], a[q]);
+        }
+        if (lane == 0) {
+            proj[3 * i + 0] = a[0];
+            proj[3 * i + 1] = a[1];
+            proj[3 * i + 2] = a[2];
+        }
+    }
+    if (lane == 0)
+        for (int q = 0; q < 3; q++) {
+            red[w][q] = mn[q];
+            red[w][3 + q] = mx[q];
+        }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        float v = red[0][q];
+        for (int k = 1; k < 4; k++) v = q < 3 ? fminf(v, red[k][q]) : fmaxf(v, red[k][q]);
+        part[6 * blockIdx.x + q] = v;
+    }
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {     // 10 bits -> every third bit
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_project_keys(const float* __restrict__ proj, int64_t n,
+                                                      const float* __restrict__ part, int nb,
+                                                      uint32_t* __restrict__ keys) {
+    __shared__ float lo[3], hi[3];
+    if (threadIdx.x < 3) {
+        float a = INFINITY, b = -INFINITY;
+        for (int k = 0; k < nb; k++) {
+            a = fminf(a, part[6 * k + threadIdx.x]);
+            b = fmaxf(b, part[6 * k + 3 + threadIdx.x]);
+        }
+        lo[threadIdx.x] = a;
+        hi[threadIdx.x] = b;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint32_t code = 0;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const float span = hi[q] - lo[q];
+        float f = span > 0.f ? (proj[3 * i + q] - lo[q]) / span * 1024.f : 0.f;
+        f = f < 0.f ? 0.f : (f > 1023.f ? 1023.f : f);
+        code |= spread3((uint32_t)f) << q;
+    }
+    keys[i] = code;
+}
+
 }  // namespace
+
+hipError_t projection_keys(const void* X, int64_t n, int32_t D, int32_t x_dtype, uint32_t* keys,
+                           hipStream_t s) {
+    const int nb = (int)(ceil_div(n, 4) < 1024 ? ceil_div(n, 4) : 1024);
+    float *proj = nullptr, *part = nullptr;
+    hipError_t e = hipMalloc(&proj, sizeof(float) * 3 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&part, sizeof(float) * 6 * (size_t)nb);
+    if (e == hipSuccess) {
+        switch (x_dtype) {
+            case PSNE_X_F32:
+                k_project<float><<<nb, 256, 0, s>>>((const float*)X, n, D, proj, part);
+                break;
+            case PSNE_X_F64:
+                k_project<double><<<nb, 256, 0, s>>>((const double*)X, n, D, proj, part);
+                break;
+            default:
+                k_project<uint8_t><<<nb, 256, 0, s>>>((const uint8_t*)X, n, D, proj, part);
+                break;
+        }
+        k_project_keys<<<dim3((unsigned)ceil_div(n, 256)), 256, 0, s>>>(proj, n, part, nb, keys);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(proj);
+    hipFree(part);
+    return e;
+}
 
 hipError_t scan_i64(const int64_t* a, int64_t m, int64_t* out, int64_t* tmp, hipStream_t s) {
     return scan_i64_local(a, m, out, tmp, s);

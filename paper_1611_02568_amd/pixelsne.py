@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64), ("precision", C.c_int32), ("com_mode", C.c_int32),
         ("x_dtype", C.c_int32), ("Y_init", C.c_void_p), ("stream", C.c_void_p),
         ("reorder_every", C.c_int32),
+        ("data_order", C.c_int32),
         ("graphs", C.c_int32),
     ]
 
