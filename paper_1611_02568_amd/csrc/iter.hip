@@ -375,15 +375,17 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restric
 // ---------------------------------------------------------------------------
 // Barnes-Hut traversal
 // ---------------------------------------------------------------------------
+// one accepted cell: Z_i += m q and R_i += m q^2 (z_i - c), q = 1 / (1 + d^2)
+// (Eq. (11), (12)); m in the state type
 template <typename T>
-__device__ __forceinline__ void bh_term(double d2, double dx, double dy, double m, double& zacc,
+__device__ __forceinline__ void bh_term(double d2, double dx, double dy, T m, double& zacc,
                                         T& rx, T& ry);
 
 template <>
-__device__ __forceinline__ void bh_term<float>(double d2, double dx, double dy, double m,
+__device__ __forceinline__ void bh_term<float>(double d2, double dx, double dy, float m,
                                                double& zacc, float& rx, float& ry) {
     const float q = __builtin_amdgcn_rcpf((float)(1.0 + d2));
-    const float mq = (float)m * q;
+    const float mq = m * q;
     zacc += (double)mq;
     const float f = mq * q;
     rx += f * (float)dx;
@@ -423,7 +425,7 @@ __device__ __forceinline__ int put_lane(int v, int sel, int old) {
     return lane_id() == sel ? v : old;
 }
 
-template <typename T>
+template <typename T, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_traverse(
     const Node* __restrict__ nodes, const double2* __restrict__ nsum, const T* __restrict__ zs,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
@@ -477,29 +479,39 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             const uint32_t c = first + q;
             const Node nd = grp[q];
             bool open = false;
-            if (act) {
-                nvis++;
-                double cx = nd.cx, cy = nd.cy, m = (double)nd.count;
-                bool use = true;
-                if (level == L && c == own) {
-                    m -= 1.0;
-                    if (m > 0.0 && com_mode != PSNE_COM_CELL_CENTER) {
-                        const double2 sm = nsum[c];
-                        cx = (sm.x - zx) / m;
-                        cy = (sm.y - zy) / m;
-                    }
-                    use = m > 0.0;
-                }
-                // one distance serves the opening test and the force term
-                const double dx = zx - cx, dy = zy - cy;
+            if (level < L) {
+                // inner cell: the opening test and, for lanes that accept, the
+                // force term share one distance
+                const double dx = zx - nd.cx, dy = zy - nd.cy;
                 const double d2 = dist2(b1, b2, dx, dy);
-                if (level != L) {
-                    use = diag2 < mul_nc(th2, d2);
-                    open = !use;
+                const bool far = diag2 < mul_nc(th2, d2);
+                open = act && !far;
+                if (act && far) {
+                    bh_term<T>(d2, dx, dy, (T)nd.count, zacc, rx, ry);
+                    if (COUNT) nuse++;
+                }
+                if (COUNT && act) nvis++;
+            } else if (act) {
+                // leaf (one pixel): always used; at its own leaf a point counts
+                // the others only, at their centre of mass in mass mode
+                if (COUNT) nvis++;
+                double cx = nd.cx, cy = nd.cy;
+                T m = (T)nd.count;
+                bool use = true;
+                if (c == own) {
+                    const uint32_t others = nd.count - 1u;
+                    m = (T)others;
+                    if (others > 0u && com_mode != PSNE_COM_CELL_CENTER) {
+                        const double2 sm = nsum[c];
+                        cx = (sm.x - zx) / (double)others;
+                        cy = (sm.y - zy) / (double)others;
+                    }
+                    use = others > 0u;
                 }
                 if (use) {
-                    bh_term<T>(d2, dx, dy, m, zacc, rx, ry);
-                    nuse++;
+                    const double dx = zx - cx, dy = zy - cy;
+                    bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, m, zacc, rx, ry);
+                    if (COUNT) nuse++;
                 }
             }
             const uint64_t om = ballot64(open);
@@ -1083,18 +1095,25 @@ hipError_t run_tree(pixelsne_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi) {
+template <typename T, bool COUNT>
+void launch_traverse(pixelsne_ctx* c, double th2, uint32_t* visits, uint32_t* used, double* Zi) {
     TreeBufs& tb = c->tb;
+    k_traverse<T, COUNT><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+        tb.nodes, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc, c->n, c->L, th2,
+        c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
+}
+
+hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi) {
     const double th2 = c->prm.theta * c->prm.theta;
-    const uint32_t* perm = tb.idx[tb.sorted];
-    if (fp64(c))
-        k_traverse<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            tb.nodes, tb.nsum, (const double*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
-            c->prm.com_mode, (double*)c->R, c->zpart, c->orig, Zi, visits, used);
-    else
-        k_traverse<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            tb.nodes, tb.nsum, (const float*)tb.zs, perm, tb.leaf_of, c->sc, c->n, c->L, th2,
-            c->prm.com_mode, (float*)c->R, c->zpart, c->orig, Zi, visits, used);
+    // per-point counters only when they are asked for
+    const bool count = visits || used;
+    if (fp64(c)) {
+        if (count) launch_traverse<double, true>(c, th2, visits, used, Zi);
+        else launch_traverse<double, false>(c, th2, visits, used, Zi);
+    } else {
+        if (count) launch_traverse<float, true>(c, th2, visits, used, Zi);
+        else launch_traverse<float, false>(c, th2, visits, used, Zi);
+    }
     return hipGetLastError();
 }
 
