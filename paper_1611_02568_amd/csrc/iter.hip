@@ -375,6 +375,17 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restric
 // ---------------------------------------------------------------------------
 // Barnes-Hut traversal
 // ---------------------------------------------------------------------------
+// 1 / x for x >= 1: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each roughly squaring the relative error, which ends
+// within an ulp or two of the correctly rounded quotient
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // one accepted cell: Z_i += m q and R_i += m q^2 (z_i - c), q = 1 / (1 + d^2)
 // (Eq. (11), (12)); m in the state type
 template <typename T>
@@ -395,7 +406,7 @@ __device__ __forceinline__ void bh_term<float>(double d2, double dx, double dy, 
 template <>
 __device__ __forceinline__ void bh_term<double>(double d2, double dx, double dy, double m,
                                                 double& zacc, double& rx, double& ry) {
-    const double q = 1.0 / (1.0 + d2);
+    const double q = rcp_nr(1.0 + d2);
     const double mq = m * q;
     zacc += mq;
     rx += mq * q * dx;
@@ -564,7 +575,7 @@ template <typename T> __device__ __forceinline__ T rcp_fast(T x);
 template <> __device__ __forceinline__ float rcp_fast<float>(float x) {
     return __builtin_amdgcn_rcpf(x);
 }
-template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return rcp_nr(x); }
 
 template <typename T> __device__ __forceinline__ T sgn(T x) {
     return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
