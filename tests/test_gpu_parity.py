@@ -216,6 +216,42 @@ def test_P_parity(psne, prec):
     assert abs(val.sum() - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_data_order_changes_nothing_but_the_layout(psne, prec):
+    """The numbering from random projections of X leaves P, the initial state,
+    the gradient (visits exact, B within the parity bar) and the run's KL
+    (within 1% after 300 iterations, past the first renumbering by the
+    embedding) as they are with the caller's numbering."""
+    X, _ = datagen.small_mixture(n=2000)
+    y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=9))
+    a, b = (psne.Context.from_data(torch.as_tensor(X).cuda(), 30.0, 512, precision=prec,
+                                   Y_init=y0, data_order=o) for o in (1, 0))
+    for ta, tb in zip(a.export_P(), b.export_P()):
+        assert torch.equal(ta, tb)
+    assert torch.equal(a.get_Y(psne.FRAME_PIXEL), b.get_Y(psne.FRAME_PIXEL))
+    ga, gb = a.gradient(12.0), b.gradient(12.0)
+    assert torch.equal(ga["visits"], gb["visits"])
+    Ba, Bb = ga["B"].double(), gb["B"].double()
+    assert (torch.linalg.vector_norm(Ba - Bb) / torch.linalg.vector_norm(Bb)).item() <= TOL_B[prec]
+    a.step(300)
+    b.step(300)
+    ka, kb = a.kl(), b.kl()
+    assert abs(ka - kb) <= 0.01 * kb, (ka, kb)
+
+
+def test_data_order_uint8_input(psne):
+    """uint8 rows go through the same projection; the run stays finite and
+    reports in the caller's numbering (P equals the oracle's)."""
+    X, _ = datagen.uint8_mixture(n=3001, D=100)
+    ctx = psne.Context.from_data(torch.as_tensor(X).cuda(), 10.0, 256, precision=0,
+                                 Y_init=torch.as_tensor(datagen.initial_embedding(3001, seed=3)))
+    rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
+    orp, ocol, oval = oracle.build_P(X.astype(np.float64), 10.0)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    ctx.step(20)
+    assert np.isfinite(ctx.kl())
+
+
 # --------------------------------------------------------------------------
 # optimisation: screen scaling invariants and final KL
 # --------------------------------------------------------------------------
