@@ -1,7 +1,7 @@
 // One-time setup on gfx950: the sparse affinity matrix P (paper Section 2.2-2.3).
 //
 //   knn          brute-force k nearest neighbours.  Distance tiles come from
-//                FP32 MFMA (v_mfma_f32_16x16x4f32): d = |x|^2 + |y|^2 - 2 x.y;
+//                FP32 MFMA (v_mfma_f32_32x32x2f32): d = |x|^2 + |y|^2 - 2 x.y;
 //                each row keeps a candidate list (global memory, per-row
 //                threshold in LDS) that is compacted to the K' = k + 32 best
 //                by a block-wide bitonic sort whenever it fills up.  The K'
@@ -19,11 +19,10 @@ namespace psne {
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kQB = 64;        // query rows per block
-constexpr int kCB = 64;        // candidate columns per tile
-constexpr int kKC = 32;        // reduction chunk staged in LDS
+constexpr int kQB = 128;       // query rows per block
+constexpr int kCB = 128;       // candidate columns per tile
+constexpr int kKC = 16;        // reduction chunk staged in LDS (2 threads x 8 per row)
 constexpr int kCap = 512;      // candidate list capacity per row
 constexpr int kMargin = 32;    // extra candidates kept for the exact re-rank
 
@@ -90,79 +89,125 @@ __device__ void compact_row(int q, int64_t grow, uint32_t* cnt, float* thr, uint
     __syncthreads();
 }
 
-// Candidate generation: one block per 64 query rows, all candidate tiles.
+// Candidate generation.  One block (four waves) per kQB query rows sweeps all
+// candidate columns in tiles of kCB; the 128 x 128 distance tile comes from
+// FP32 MFMA (v_mfma_f32_32x32x2f32), each wave owning a 64 x 64 quarter as
+// 2 x 2 MFMA tiles.  X is staged through LDS in chunks of kKC dimensions,
+// k-major so that a fragment read is 32 consecutive words, with the next
+// chunk's global loads in flight while the current one is multiplied.
+typedef float v16f __attribute__((ext_vector_type(16)));
+
 template <typename X>
 __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm, int64_t n,
                                                         int D, const float* __restrict__ nrm,
                                                         int kp, uint64_t* __restrict__ cand,
                                                         uint32_t* __restrict__ cand_cnt,
                                                         float* __restrict__ cand_thr) {
-    __shared__ float As[kQB][kKC + 1];
-    __shared__ float Bs[kCB][kKC + 1];
+    // [buffer][k][row]: rows 0..127 queries, 128..255 candidates
+    __shared__ float S[2][kKC][2 * kQB + 4];
     __shared__ uint32_t cnt[kQB];
     __shared__ float thr[kQB];
     __shared__ float nq[kQB];
     __shared__ float nc[kCB];
     __shared__ uint64_t sbuf[512];
-    __shared__ int need;
 
     const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
     const int64_t q0 = (int64_t)blockIdx.x * kQB;
     if (t < kQB) {
         cnt[t] = 0;
         thr[t] = INFINITY;
         nq[t] = q0 + t < n ? nrm[q0 + t] : 0.0f;
     }
-    const int lr = t >> 2, lc = (t & 3) * 8;   // loader: row lr, 8 columns from lc
+    const int nk = (D + kKC - 1) / kKC;
 
     for (int64_t c0 = 0; c0 < n; c0 += kCB) {
-        v4f acc[4];
+        v16f acc[2][2];
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) acc[a][b][v] = 0.0f;
         if (t < kCB) nc[t] = c0 + t < n ? nrm[c0 + t] : 0.0f;
-        for (int k0 = 0; k0 < D; k0 += kKC) {
+        // query rows q0.. as staging rows 0..127, candidates c0.. as 128..255:
+        // thread t loads row t / 2 of the queries (h = 0) and of the candidates (h = 1)
+        float g[kKC];                           // kKC / 2 query and kKC / 2 candidate values
+        const int64_t rq = q0 + (t >> 1), rc = c0 + (t >> 1);
+        const bool okq = rq < n, okc = rc < n;
+        constexpr int kH = kKC / 2;                     // dimensions per thread and row
+        const X* pq = Xm + (okq ? rq : 0) * (int64_t)D + kH * (t & 1);
+        const X* pc = Xm + (okc ? rc : 0) * (int64_t)D + kH * (t & 1);
+        auto fetch = [&](int k0) {
+            const int lim = D - k0 - kH * (t & 1);          // elements left in the row
+#pragma unroll
+            for (int e = 0; e < kH; e++) {
+                g[e] = (okq && e < lim) ? to_f32(pq[k0 + e]) : 0.0f;
+                g[kH + e] = (okc && e < lim) ? to_f32(pc[k0 + e]) : 0.0f;
+            }
+        };
+        auto store = [&](int buf) {
+            const int row = t >> 1, kb = kH * (t & 1);
+#pragma unroll
+            for (int e = 0; e < kH; e++) {
+                S[buf][kb + e][row] = g[e];
+                S[buf][kb + e][kQB + row] = g[kH + e];
+            }
+        };
+        __syncthreads();                       // previous tile's readers are done
+        fetch(0);
+        store(0);
+        __syncthreads();
+        for (int kc = 0; kc < nk; kc++) {
+            const int buf = kc & 1;
+            if (kc + 1 < nk) fetch((kc + 1) * kKC);
+#pragma unroll
+            for (int kk = 0; kk < kKC; kk += 2) {
+                const int k = kk + (lane >> 5);
+                const float a0 = S[buf][k][wr + (lane & 31)];
+                const float a1 = S[buf][k][wr + 32 + (lane & 31)];
+                const float b0 = S[buf][k][kQB + wc + (lane & 31)];
+                const float b1 = S[buf][k][kQB + wc + 32 + (lane & 31)];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+            if (kc + 1 < nk) store(buf ^ 1);
             __syncthreads();
-            {
-                const int64_t ra = q0 + lr, rb = c0 + lr;
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    const int d = k0 + lc + e;
-                    As[lr][lc + e] = (ra < n && d < D) ? to_f32(Xm[ra * D + d]) : 0.0f;
-                    Bs[lr][lc + e] = (rb < n && d < D) ? to_f32(Xm[rb * D + d]) : 0.0f;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < kKC; kk += 4) {
-                const float a = As[16 * w + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const float b = Bs[16 * j + (lane & 15)][kk + (lane >> 4)];
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
-                }
-            }
         }
-        // filter: output row 16w + 4(lane/16) + i, column 16j + lane%16
+        // filter, one 32 x 32 MFMA tile at a time through a wave-private LDS
+        // tile (the staging buffer is free after the last chunk): element v of
+        // tile (a, b) is row 8(v / 4) + 4(lane / 32) + v % 4, column lane % 32
+        float* T = &S[0][0][0] + w * (32 * 33);
+        const int cj = lane & 31;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int rl = 16 * w + 4 * (lane >> 4) + i;
-                const int cl = 16 * j + (lane & 15);
-                const int64_t gr = q0 + rl, gc = c0 + cl;
-                const float d = nq[rl] + nc[cl] - 2.0f * acc[j][i];
-                if (gr < n && gc < n && gc != gr && d <= thr[rl]) {
-                    const uint32_t pos = atomicAdd(&cnt[rl], 1u);
-                    cand[gr * kCap + pos] = cand_key(d, (uint32_t)gc);
+            for (int b = 0; b < 2; b++) {
+#pragma unroll
+                for (int v = 0; v < 16; v++)
+                    T[(8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) * 33 + cj] = acc[a][b][v];
+                const int cl = wc + 32 * b + cj;
+                const int64_t gc = c0 + cl;
+                const float ncv = nc[cl];
+#pragma unroll 2
+                for (int m = 0; m < 16; m++) {
+                    const int i = 2 * m + (lane >> 5);
+                    const int rl = wr + 32 * a + i;
+                    const int64_t gr = q0 + rl;
+                    const float d = nq[rl] + ncv - 2.0f * T[i * 33 + cj];
+                    if (gr < n && gc < n && gc != gr && d <= thr[rl]) {
+                        const uint32_t pos = atomicAdd(&cnt[rl], 1u);
+                        cand[gr * kCap + pos] = cand_key(d, (uint32_t)gc);
+                    }
                 }
             }
-        }
         __syncthreads();
         // compact the rows that could overflow during the next tile
         for (int q = 0; q < kQB; q++) {
             if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
         }
-        (void)need;
     }
     for (int q = 0; q < kQB; q++) {
         if (q0 + q < n) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
