@@ -50,6 +50,7 @@ struct pixelsne_mlp {
     uint16_t* da1b = nullptr;
     float* splitk = nullptr;            // split-K partials
     int64_t splitk_len = 0;
+    float* part = nullptr;              // row-slice partial sums of the batch reductions
     double* lossbuf = nullptr;          // per-block loss partials
     int64_t lossbuf_len = 0;
     uint32_t* order = nullptr;          // batch row order (device)
@@ -76,6 +77,43 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2 };
+
+// Stage rows r0..r0+63, k0..k0+31 of an operand into S[row][k] (k < ke, row
+// < R zero-filled beyond).  kmaj: stored [row][ld] with k contiguous;
+// otherwise stored [k][ld] with rows contiguous.  Thread t moves 8 elements,
+// with one 16-byte load when the run is inside the matrix and aligned.
+__device__ __forceinline__ void load_tile(const uint16_t* __restrict__ G, int ld, int kmaj,
+                                          int r0, int R, int k0, int ke, int t,
+                                          uint16_t (*S)[40]) {
+    union {
+        uint4 q;
+        uint16_t h[8];
+    } v;
+    if (kmaj) {
+        const int r = t >> 2, c = (t & 3) * 8;                 // row r, k c..c+7
+        const int gr = r0 + r, gk = k0 + c;
+        const uint16_t* p = G + (int64_t)gr * ld + gk;
+        if (gr < R && gk + 8 <= ke && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+            v.q = *reinterpret_cast<const uint4*>(p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) v.h[e] = (gr < R && gk + e < ke) ? p[e] : (uint16_t)0;
+        }
+        *reinterpret_cast<uint4*>(&S[r][c]) = v.q;
+    } else {
+        const int k = t >> 3, c = (t & 7) * 8;                 // k, rows c..c+7
+        const int gk = k0 + k, gr = r0 + c;
+        const uint16_t* p = G + (int64_t)gk * ld + gr;
+        if (gk < ke && gr + 8 <= R && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+            v.q = *reinterpret_cast<const uint4*>(p);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; e++) v.h[e] = (gk < ke && gr + e < R) ? p[e] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; e++) S[c + e][k] = v.h[e];
+    }
+}
 
 // C[M,N] = op(A)[M,K] * op(B)[K,N], bfloat16 operands, FP32 accumulate.
 // ta: A stored [K][lda] (transposed); tb: B stored [N][ldb] (transposed).
@@ -104,26 +142,11 @@ __global__ __launch_bounds__(kT) void k_gemm_bf16(const uint16_t* __restrict__ A
         for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     for (int k0 = kb; k0 < ke; k0 += 32) {
         __syncthreads();
-        // 64 x 32 elements per tile, 8 per thread
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const int idx = e * kT + t;
-            // A: rows m, k contiguous in LDS
-            int r, c;
-            if (!ta) { r = idx >> 5; c = idx & 31; }     // coalesced along k
-            else { c = idx >> 6; r = idx & 63; }          // coalesced along m
-            const int gm = m0 + r, gk = k0 + c;
-            uint16_t va = 0;
-            if (gm < M && gk < ke) va = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-            As[r][c] = va;
-            int rb, cb;
-            if (tb) { rb = idx >> 5; cb = idx & 31; }    // B^T stored [N][K]: along k
-            else { cb = idx >> 6; rb = idx & 63; }        // B stored [K][N]: along n
-            const int gn = n0 + rb, gk2 = k0 + cb;
-            uint16_t vb = 0;
-            if (gn < N && gk2 < ke) vb = tb ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
-            Bs[rb][cb] = vb;
-        }
+        // 64 x 32 elements per operand and step: one run of 8 consecutive
+        // elements (16 bytes) per thread, along k for an operand stored with k
+        // contiguous and along m (n) for a transposed one
+        load_tile(A, lda, !ta, m0, M, k0, ke, t, As);
+        load_tile(B, ldb, tb, n0, N, k0, ke, t, Bs);
         __syncthreads();
         v8bf af[2], bfr[2];
 #pragma unroll
@@ -232,27 +255,46 @@ __global__ __launch_bounds__(kT) void k_head_fwd(const uint16_t* __restrict__ h2
 }
 
 // dW3[j][d] = sum_b H2[b][j] dout[b][d];  db3[d] = sum_b dout[b][d]
-__global__ __launch_bounds__(kT) void k_head_wgrad(const uint16_t* __restrict__ h2b, int h2,
-                                                   const float* __restrict__ dout, int Bn,
-                                                   float* __restrict__ dw3, float* __restrict__ db3) {
-    const int j = blockIdx.x * kT + threadIdx.x;
-    if (j < h2) {
-        float s0 = 0.f, s1 = 0.f;
-        for (int b = 0; b < Bn; b++) {
+// Batch reductions are split into kSlices row slices: block (x, z) sums its
+// slice for 64 columns (4 row phases x 64 columns, then the phases in order)
+// into part[z][...]; k_sum_slices adds the slices in slice order.
+constexpr int kSlices = 32;
+
+// dW3[j][c] = sum_b H2[b][j] dout[b][c]; columns j < h2 give 2 outputs each,
+// and block x == 0 also sums dout itself (db3) into part[z][2 h2 + c]
+__global__ __launch_bounds__(kT) void k_head_wgrad_part(const uint16_t* __restrict__ h2b, int h2,
+                                                        const float* __restrict__ dout, int Bn,
+                                                        float* __restrict__ part) {
+    __shared__ float red[4][64][3];
+    const int t = threadIdx.x, cj = t & 63, ph = t >> 6;
+    const int j = blockIdx.x * 64 + cj;
+    const int per = (Bn + kSlices - 1) / kSlices;
+    const int b0 = blockIdx.z * per, b1 = b0 + per < Bn ? b0 + per : Bn;
+    float s0 = 0.f, s1 = 0.f, d0 = 0.f, d1 = 0.f;
+    for (int b = b0 + ph; b < b1; b += 4) {
+        const float o0 = dout[2 * b], o1 = dout[2 * b + 1];
+        if (j < h2) {
             const float h = bf2f(h2b[(int64_t)b * h2 + j]);
-            s0 += h * dout[2 * b];
-            s1 += h * dout[2 * b + 1];
+            s0 += h * o0;
+            s1 += h * o1;
         }
-        dw3[2 * j] = s0;
-        dw3[2 * j + 1] = s1;
-    } else if (j == h2) {
-        float s0 = 0.f, s1 = 0.f;
-        for (int b = 0; b < Bn; b++) {
-            s0 += dout[2 * b];
-            s1 += dout[2 * b + 1];
+        d0 += o0;
+        d1 += o1;
+    }
+    red[ph][cj][0] = s0;
+    red[ph][cj][1] = s1;
+    red[ph][cj][2] = cj == 0 ? d0 : (cj == 1 ? d1 : 0.f);
+    __syncthreads();
+    if (ph == 0) {
+        const float a0 = ((red[0][cj][0] + red[1][cj][0]) + red[2][cj][0]) + red[3][cj][0];
+        const float a1 = ((red[0][cj][1] + red[1][cj][1]) + red[2][cj][1]) + red[3][cj][1];
+        float* p = part + (int64_t)blockIdx.z * (2 * h2 + 2);
+        if (j < h2) {
+            p[2 * j] = a0;
+            p[2 * j + 1] = a1;
         }
-        db3[0] = s0;
-        db3[1] = s1;
+        if (blockIdx.x == 0 && cj < 2)
+            p[2 * h2 + cj] = ((red[0][cj][2] + red[1][cj][2]) + red[2][cj][2]) + red[3][cj][2];
     }
 }
 
@@ -272,14 +314,30 @@ __global__ __launch_bounds__(kT) void k_head_bgrad(const float* __restrict__ dou
     da2b[i] = f2bf(d);
 }
 
-// column sums over the batch (bias gradients)
-__global__ __launch_bounds__(kT) void k_colsum(const float* __restrict__ a, int rows, int cols,
-                                               float* __restrict__ out) {
-    const int j = blockIdx.x * kT + threadIdx.x;
-    if (j >= cols) return;
+// column sums over the batch (bias gradients), per row slice
+__global__ __launch_bounds__(kT) void k_colsum_part(const float* __restrict__ a, int rows, int cols,
+                                                    float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int t = threadIdx.x, cj = t & 63, ph = t >> 6;
+    const int j = blockIdx.x * 64 + cj;
+    const int per = (rows + kSlices - 1) / kSlices;
+    const int b0 = blockIdx.z * per, b1 = b0 + per < rows ? b0 + per : rows;
     float s = 0.f;
-    for (int b = 0; b < rows; b++) s += a[(int64_t)b * cols + j];
-    out[j] = s;
+    if (j < cols)
+        for (int b = b0 + ph; b < b1; b += 4) s += a[(int64_t)b * cols + j];
+    red[ph][cj] = s;
+    __syncthreads();
+    if (ph == 0 && j < cols)
+        part[(int64_t)blockIdx.z * cols + j] = ((red[0][cj] + red[1][cj]) + red[2][cj]) + red[3][cj];
+}
+
+__global__ __launch_bounds__(kT) void k_sum_slices(const float* __restrict__ part, int m,
+                                                   float* __restrict__ out) {
+    const int i = blockIdx.x * kT + threadIdx.x;
+    if (i >= m) return;
+    float s = 0.f;
+    for (int z = 0; z < kSlices; z++) s += part[(int64_t)z * m + i];
+    out[i] = s;
 }
 
 __global__ __launch_bounds__(kT) void k_adam(float* __restrict__ th, const float* __restrict__ g,
@@ -383,7 +441,7 @@ hipError_t ensure_batch(pixelsne_mlp* m, int64_t B) {
     if ((e = mal(m, &m->da1b, 2 * B * m->h1)) != hipSuccess) return e;
     m->lossbuf_len = ceil_div(B, 4);
     if ((e = mal(m, &m->lossbuf, 8 * m->lossbuf_len)) != hipSuccess) return e;
-    (void)h;
+    if (!m->part && (e = mal(m, &m->part, 4 * (size_t)kSlices * (2 * h + 2))) != hipSuccess) return e;
     m->cap_batch = B;
     return hipSuccess;
 }
@@ -445,11 +503,15 @@ hipError_t forward_batch(pixelsne_mlp* m, int Bn, bool with_targets) {
 hipError_t backward_batch(pixelsne_mlp* m, int Bn) {
     hipError_t e;
     float* g = m->grad;
-    k_head_wgrad<<<g1(m->h2 + 1), kT, 0, m->stream>>>(m->h2b, m->h2, m->dout, Bn, g + off_W3(m),
-                                                      g + off_b3(m));
+    // dW3 and db3 are adjacent in the flat gradient: 2 h2 + 2 values
+    k_head_wgrad_part<<<dim3((unsigned)ceil_div(m->h2, 64), 1, kSlices), kT, 0, m->stream>>>(
+        m->h2b, m->h2, m->dout, Bn, m->part);
+    k_sum_slices<<<g1(2 * m->h2 + 2), kT, 0, m->stream>>>(m->part, 2 * m->h2 + 2, g + off_W3(m));
     k_head_bgrad<<<g1((int64_t)Bn * m->h2), kT, 0, m->stream>>>(m->dout, m->w3b, m->a2, m->h2, Bn,
                                                                m->da2, m->da2b);
-    k_colsum<<<g1(m->h2), kT, 0, m->stream>>>(m->da2, Bn, m->h2, g + off_b2(m));
+    k_colsum_part<<<dim3((unsigned)ceil_div(m->h2, 64), 1, kSlices), kT, 0, m->stream>>>(
+        m->da2, Bn, m->h2, m->part);
+    k_sum_slices<<<g1(m->h2), kT, 0, m->stream>>>(m->part, m->h2, g + off_b2(m));
     // dW2 = H1^T dA2 : A = H1 stored [B][h1] (transposed), B = dA2 [B][h2]
     if ((e = gemm(m, EPI_F32, m->h1b, m->h1, 1, m->da2b, m->h2, 0, m->h1, m->h2, Bn,
                   g + off_W2(m), nullptr, nullptr, nullptr)) != hipSuccess)
@@ -458,7 +520,9 @@ hipError_t backward_batch(pixelsne_mlp* m, int Bn) {
     if ((e = gemm(m, EPI_GELU_GRAD, m->da2b, m->h2, 0, m->w2b, m->h2, 1, Bn, m->h1, m->h2, m->da1,
                   nullptr, m->a1, m->da1b)) != hipSuccess)
         return e;
-    k_colsum<<<g1(m->h1), kT, 0, m->stream>>>(m->da1, Bn, m->h1, g + off_b1(m));
+    k_colsum_part<<<dim3((unsigned)ceil_div(m->h1, 64), 1, kSlices), kT, 0, m->stream>>>(
+        m->da1, Bn, m->h1, m->part);
+    k_sum_slices<<<g1(m->h1), kT, 0, m->stream>>>(m->part, m->h1, g + off_b1(m));
     // dW1 = X^T dA1
     return gemm(m, EPI_F32, m->xb, m->d, 1, m->da1b, m->h1, 0, m->d, m->h1, Bn, g + off_W1(m),
                 nullptr, nullptr, nullptr);
