@@ -172,3 +172,28 @@ def clustered_pixels(n: int, r: int, seed: int, n_clusters: int = 8, spread: flo
     z[0] = (0, 0)
     z[1] = (top, top)
     return z
+
+
+def circulant_affinities(n: int, half_degree: int, seed: int):
+    """A symmetric sparse matrix of n rows with 2 * half_degree nonzeros per row,
+    standing in for P at a given size and row length where building P from
+    data would take too long on the CPU: row i holds the columns i +- d mod n
+    for half_degree distinct random offsets d in [1, n / 2), with a positive
+    random weight per unordered pair (the same for (i, j) and (j, i)), all
+    weights scaled to sum to 1.  Returns (row_ptr int64 [n+1], col int32 [nnz]
+    ascending per row, val float64 [nnz])."""
+    rng = np.random.default_rng(seed)
+    offs = rng.choice(np.arange(1, (n - 1) // 2), size=half_degree, replace=False)
+    offs = np.concatenate([offs, -offs]).astype(np.int64)
+    rows = np.arange(n, dtype=np.int64)[:, None]
+    col = np.sort((rows + offs[None, :]) % n, axis=1)
+    lo = np.minimum(rows, col)
+    hi = np.maximum(rows, col)
+    h = (lo * 0x9E3779B1 + hi * 0x85EBCA77 + seed) & 0xFFFFFFFF
+    h = (h ^ (h >> 15)) * 0x2C1B3C6D & 0xFFFFFFFF
+    h = h ^ (h >> 12)
+    val = 0.5 + (h & 0xFFFF).astype(np.float64) / 65536.0
+    val /= val.sum()
+    deg = 2 * half_degree
+    rp = np.arange(0, n * deg + 1, deg, dtype=np.int64)
+    return rp, col.astype(np.int32).ravel(), val.ravel()
