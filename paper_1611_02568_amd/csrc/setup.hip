@@ -1,7 +1,8 @@
 // One-time setup on gfx950: the sparse affinity matrix P (paper Section 2.2-2.3).
 //
 //   knn          brute-force k nearest neighbours.  Distance tiles come from
-//                FP32 MFMA (v_mfma_f32_32x32x2f32): d = |x|^2 + |y|^2 - 2 x.y;
+//                FP32 MFMA (v_mfma_f32_32x32x2f32): d = |x|^2 + |y|^2 - 2 x.y,
+//                or, for uint8 rows, exactly from INT8 MFMA on x - 128;
 //                each row keeps a candidate list (global memory, per-row
 //                threshold in LDS) that is compacted to the K' = k + 32 best
 //                by a block-wide bitonic sort whenever it fills up.  The K'
@@ -12,6 +13,7 @@
 #include <math.h>
 
 #include <string>
+#include <type_traits>
 
 #include "ctx.h"
 
@@ -70,8 +72,14 @@ __device__ __forceinline__ uint64_t cand_key(float d, uint32_t j) {
     return ((uint64_t)__float_as_uint(c) << 32) | (uint64_t)j;
 }
 
+// A candidate key is (distance bits << 32 | column): the bits of a
+// non-negative float, or an exact integer distance, both ordered as unsigned
+// integers.  A row's threshold is the distance bits of its kp-th best key
+// (kNoThr while the list is not full).
+constexpr uint32_t kNoThr = 0xFFFFFFFFu;
+
 // Compact the candidate list of local row q to its kp best (sorted).
-__device__ void compact_row(int q, int64_t grow, uint32_t* cnt, float* thr, uint64_t* cand,
+__device__ void compact_row(int q, int64_t grow, uint32_t* cnt, uint32_t* thr, uint64_t* cand,
                             uint64_t* sbuf, int kp) {
     const int t = threadIdx.x;
     const int m = (int)cnt[q];
@@ -84,7 +92,7 @@ __device__ void compact_row(int q, int64_t grow, uint32_t* cnt, float* thr, uint
     __syncthreads();
     if (t == 0) {
         cnt[q] = (uint32_t)keep;
-        thr[q] = keep == kp ? __uint_as_float((uint32_t)(sbuf[kp - 1] >> 32)) : INFINITY;
+        thr[q] = keep == kp ? (uint32_t)(sbuf[kp - 1] >> 32) : kNoThr;
     }
     __syncthreads();
 }
@@ -102,11 +110,11 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
                                                         int D, const float* __restrict__ nrm,
                                                         int kp, uint64_t* __restrict__ cand,
                                                         uint32_t* __restrict__ cand_cnt,
-                                                        float* __restrict__ cand_thr) {
+                                                        uint32_t* __restrict__ cand_thr) {
     // [buffer][k][row]: rows 0..127 queries, 128..255 candidates
     __shared__ float S[2][kKC][2 * kQB + 4];
     __shared__ uint32_t cnt[kQB];
-    __shared__ float thr[kQB];
+    __shared__ uint32_t thr[kQB];
     __shared__ float nq[kQB];
     __shared__ float nc[kCB];
     __shared__ uint64_t sbuf[512];
@@ -116,7 +124,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
     const int64_t q0 = (int64_t)blockIdx.x * kQB;
     if (t < kQB) {
         cnt[t] = 0;
-        thr[t] = INFINITY;
+        thr[t] = kNoThr;
         nq[t] = q0 + t < n ? nrm[q0 + t] : 0.0f;
     }
     const int nk = (D + kKC - 1) / kKC;
@@ -197,14 +205,166 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
                     const int rl = wr + 32 * a + i;
                     const int64_t gr = q0 + rl;
                     const float d = nq[rl] + ncv - 2.0f * T[i * 33 + cj];
-                    if (gr < n && gc < n && gc != gr && d <= thr[rl]) {
+                    const uint64_t key = cand_key(d, (uint32_t)gc);
+                    if (gr < n && gc < n && gc != gr && (uint32_t)(key >> 32) <= thr[rl]) {
                         const uint32_t pos = atomicAdd(&cnt[rl], 1u);
-                        cand[gr * kCap + pos] = cand_key(d, (uint32_t)gc);
+                        cand[gr * kCap + pos] = key;
                     }
                 }
             }
         __syncthreads();
         // compact the rows that could overflow during the next tile
+        for (int q = 0; q < kQB; q++) {
+            if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
+        }
+    }
+    for (int q = 0; q < kQB; q++) {
+        if (q0 + q < n) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
+    }
+    if (t < kQB && q0 + t < n) {
+        cand_cnt[q0 + t] = cnt[t];
+        cand_thr[q0 + t] = thr[t];
+    }
+}
+
+// Exact candidates for uint8 rows: x' = x - 128 as int8 through
+// v_mfma_i32_32x32x16_i8, so that every distance |x'|^2 + |y'|^2 - 2 x'.y'
+// is an exact int32 (|x'| <= 128, D <= 32768).  Same blocking as the FP32
+// kernel: 128 x 128 tile per block, a 64 x 64 quarter per wave; X staged in
+// LDS row-major, kKB bytes of each row per chunk.
+typedef int v16i __attribute__((ext_vector_type(16)));
+constexpr int kKB = 64;
+
+__global__ __launch_bounds__(256) void k_row_norms_i8(const uint8_t* __restrict__ Xm, int64_t n,
+                                                      int D, int32_t* __restrict__ nrm) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (i >= n) return;
+    int a = 0;
+    for (int d = lane; d < D; d += 64) {
+        const int v = (int)Xm[i * D + d] - 128;
+        a += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) nrm[i] = a;
+}
+
+__global__ __launch_bounds__(256) void k_knn_candidates_i8(const uint8_t* __restrict__ Xm,
+                                                           int64_t n, int D,
+                                                           const int32_t* __restrict__ nrm,
+                                                           int kp, uint64_t* __restrict__ cand,
+                                                           uint32_t* __restrict__ cand_cnt,
+                                                           uint32_t* __restrict__ cand_thr) {
+    // [buffer][row][k]: rows 0..127 queries, 128..255 candidates; 16 bytes pad
+    __shared__ __attribute__((aligned(16))) int8_t S[2][2 * kQB][kKB + 16];
+    __shared__ int32_t T[4][32][33];
+    __shared__ uint32_t cnt[kQB];
+    __shared__ uint32_t thr[kQB];
+    __shared__ int32_t nq[kQB];
+    __shared__ int32_t nc[kCB];
+    __shared__ uint64_t sbuf[512];
+
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+    const int64_t q0 = (int64_t)blockIdx.x * kQB;
+    if (t < kQB) {
+        cnt[t] = 0;
+        thr[t] = kNoThr;
+        nq[t] = q0 + t < n ? nrm[q0 + t] : 0;
+    }
+    const int nk = (D + kKB - 1) / kKB;
+    const int seg = 16 * (t & 3);                  // this thread's 16 bytes of a row
+
+    for (int64_t c0 = 0; c0 < n; c0 += kCB) {
+        v16i acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int v = 0; v < 16; v++) acc[a][b][v] = 0;
+        if (t < kCB) nc[t] = c0 + t < n ? nrm[c0 + t] : 0;
+        // thread t stages staging rows t / 4 + 64 h (h = 0..3), bytes seg..seg+15
+        uint4 g[4];
+        auto fetch = [&](int k0) {
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                const int row = (t >> 2) + 64 * h;
+                const int64_t gr = row < kQB ? q0 + row : c0 + (row - kQB);
+                const int kb = k0 + seg;
+                union {
+                    uint4 q;
+                    uint8_t b[16];
+                } v;
+                const uint8_t* src = Xm + (gr < n ? gr : 0) * (int64_t)D + kb;
+                if (gr < n && kb + 16 <= D && ((reinterpret_cast<uintptr_t>(src) & 15u) == 0)) {
+                    v.q = *reinterpret_cast<const uint4*>(src);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 16; e++)
+                        v.b[e] = (gr < n && kb + e < D) ? src[e] : (uint8_t)128;   // x' = 0
+                }
+                // centre: x - 128 as int8 is the byte with its top bit flipped
+                v.q.x ^= 0x80808080u;
+                v.q.y ^= 0x80808080u;
+                v.q.z ^= 0x80808080u;
+                v.q.w ^= 0x80808080u;
+                g[h] = v.q;
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int h = 0; h < 4; h++)
+                *reinterpret_cast<uint4*>(&S[buf][(t >> 2) + 64 * h][seg]) = g[h];
+        };
+        __syncthreads();                       // previous tile's readers are done
+        fetch(0);
+        store(0);
+        __syncthreads();
+        for (int kc = 0; kc < nk; kc++) {
+            const int buf = kc & 1;
+            if (kc + 1 < nk) fetch((kc + 1) * kKB);
+#pragma unroll
+            for (int kk = 0; kk < kKB; kk += 16) {
+                const int kb = kk + 8 * (lane >> 5);
+                const long a0 = *reinterpret_cast<const long*>(&S[buf][wr + (lane & 31)][kb]);
+                const long a1 = *reinterpret_cast<const long*>(&S[buf][wr + 32 + (lane & 31)][kb]);
+                const long b0 = *reinterpret_cast<const long*>(&S[buf][kQB + wc + (lane & 31)][kb]);
+                const long b1 =
+                    *reinterpret_cast<const long*>(&S[buf][kQB + wc + 32 + (lane & 31)][kb]);
+                acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x16_i8(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x16_i8(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x16_i8(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x16_i8(a1, b1, acc[1][1], 0, 0, 0);
+            }
+            if (kc + 1 < nk) store(buf ^ 1);
+            __syncthreads();
+        }
+        // filter through a wave-private LDS tile, as in the FP32 kernel
+        const int cj = lane & 31;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+#pragma unroll
+                for (int v = 0; v < 16; v++)
+                    T[w][8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)][cj] = acc[a][b][v];
+                const int cl = wc + 32 * b + cj;
+                const int64_t gc = c0 + cl;
+                const int32_t ncv = nc[cl];
+#pragma unroll 2
+                for (int m = 0; m < 16; m++) {
+                    const int i = 2 * m + (lane >> 5);
+                    const int rl = wr + 32 * a + i;
+                    const int64_t gr = q0 + rl;
+                    const int32_t d = nq[rl] + ncv - 2 * T[w][i][cj];
+                    if (gr < n && gc < n && gc != gr && (uint32_t)d <= thr[rl]) {
+                        const uint32_t pos = atomicAdd(&cnt[rl], 1u);
+                        cand[gr * kCap + pos] = ((uint64_t)(uint32_t)d << 32) | (uint64_t)gc;
+                    }
+                }
+            }
+        __syncthreads();
         for (int q = 0; q < kQB; q++) {
             if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
         }
@@ -225,8 +385,9 @@ template <typename X>
 __global__ __launch_bounds__(256) void k_knn_rerank(const X* __restrict__ Xm, int64_t n, int D,
                                                     int k, const uint64_t* __restrict__ cand,
                                                     const uint32_t* __restrict__ cand_cnt,
-                                                    const float* __restrict__ cand_thr,
+                                                    const uint32_t* __restrict__ cand_thr,
                                                     const float* __restrict__ nrm, float nrm_max,
+                                                    int exact_keys,
                                                     int32_t* __restrict__ idx,
                                                     double* __restrict__ d2,
                                                     uint32_t* __restrict__ flag) {
@@ -272,11 +433,19 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const X* __restrict__ Xm, in
         d2[i * k + e] = dv[e];
     }
     if (t == 0) {
-        // |fp32(d) - d| <= (D + 4) 2^-24 (|x| + |y|)^2  (conservative)
-        const double tau = (double)cand_thr[i];
-        const double sx = sqrt((double)nrm[i]), sy = sqrt((double)nrm_max);
-        const double err = (double)(D + 4) * 0x1.0p-24 * (sx + sy) * (sx + sy) * 1.01;
-        flag[i] = (isfinite(tau) && !(dv[k - 1] < tau - err)) ? 1u : 0u;
+        const uint32_t tb = cand_thr[i];
+        if (tb == kNoThr) {
+            flag[i] = 0u;                        // every candidate was kept
+        } else if (exact_keys) {
+            // exact integer distances: only a tie at the threshold is unproven
+            flag[i] = dv[k - 1] < (double)tb ? 0u : 1u;
+        } else {
+            // |fp32(d) - d| <= (D + 4) 2^-24 (|x| + |y|)^2  (conservative)
+            const double tau = (double)__uint_as_float(tb);
+            const double sx = sqrt((double)nrm[i]), sy = sqrt((double)nrm_max);
+            const double err = (double)(D + 4) * 0x1.0p-24 * (sx + sy) * (sx + sy) * 1.01;
+            flag[i] = dv[k - 1] < tau - err ? 0u : 1u;
+        }
     }
 }
 
@@ -553,17 +722,17 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
     const int kp = (int)((int64_t)(k + kMargin) < n - 1 ? (k + kMargin) : (n - 1));
     float* nrm = nullptr;
     uint64_t* cand = nullptr;
-    uint32_t *ccnt = nullptr, *flag = nullptr;
-    float* cthr = nullptr;
+    uint32_t *ccnt = nullptr, *flag = nullptr, *cthr = nullptr;
+    int32_t* nrm_i = nullptr;
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t x) {
-        hipFree(nrm); hipFree(cand); hipFree(ccnt); hipFree(flag); hipFree(cthr);
+        hipFree(nrm); hipFree(cand); hipFree(ccnt); hipFree(flag); hipFree(cthr); hipFree(nrm_i);
         return x;
     };
     if ((e = hipMalloc(&nrm, sizeof(float) * n)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&cand, sizeof(uint64_t) * kCap * n)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&ccnt, sizeof(uint32_t) * n)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc(&cthr, sizeof(float) * n)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&cthr, sizeof(uint32_t) * n)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&flag, sizeof(uint32_t) * n)) != hipSuccess) return fail(e);
     k_row_norms<X><<<dim3((unsigned)ceil_div(n, 4)), 256, 0, s>>>(Xm, n, D, nrm);
     std::vector<float> hn(n);
@@ -578,10 +747,21 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
         }
         nmax = v > nmax ? v : nmax;
     }
-    k_knn_candidates<X><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(Xm, n, D, nrm, kp, cand,
-                                                                         ccnt, cthr);
+    // exact while 256^2 D fits an int32
+    const bool kExact = std::is_same<X, uint8_t>::value && D <= 32768;
+    if (kExact) {
+        // uint8 rows: exact integer distances from INT8 MFMA
+        if ((e = hipMalloc(&nrm_i, sizeof(int32_t) * n)) != hipSuccess) return fail(e);
+        k_row_norms_i8<<<dim3((unsigned)ceil_div(n, 4)), 256, 0, s>>>(
+            (const uint8_t*)Xm, n, D, nrm_i);
+        k_knn_candidates_i8<<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(
+            (const uint8_t*)Xm, n, D, nrm_i, kp, cand, ccnt, cthr);
+    } else {
+        k_knn_candidates<X><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(Xm, n, D, nrm, kp,
+                                                                             cand, ccnt, cthr);
+    }
     k_knn_rerank<X><<<dim3((unsigned)n), 256, 0, s>>>(Xm, n, D, k, cand, ccnt, cthr, nrm, nmax,
-                                                      idx, d2, flag);
+                                                      kExact ? 1 : 0, idx, d2, flag);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     std::vector<uint32_t> hf(n);
     if ((e = hipMemcpyAsync(hf.data(), flag, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
