@@ -254,13 +254,19 @@ def time_to_kl(ctx_train, X_train, mix, args):
         kl_plain = plain.kl()
         prec_plain = plain.neighborhood_precision(hi, [1, 10, 30])
         del plain
-        t0 = time.perf_counter()
-        Yp = net.place(Xhd, r, s_train)
-        sync()
-        t_place = time.perf_counter() - t0
         res = {"plain_1000_s": t_plain, "plain_kl": kl_plain, "target_kl": 1.01 * kl_plain,
-               "plain_precision_k1_10_30": prec_plain, "place_s": t_place}
-        for rlabel, reta in (("refine_eta200", 200.0), ("refine_eta_n_over_12", nh / 12.0)):
+               "plain_precision_k1_10_30": prec_plain}
+        # placed scale: the training run's s, and s times sqrt(n_heldout / n_train)
+        # (the embedding's extent grows with the number of points)
+        fsq = (nh / X_train.shape[0]) ** 0.5
+        for rlabel, reta, fs in (("refine_eta200", 200.0, 1.0),
+                                 ("refine_eta200_s_sqrt_n_ratio", 200.0, fsq),
+                                 ("refine_eta_n_over_12", nh / 12.0, 1.0),
+                                 ("refine_eta_n_over_12_s_sqrt_n_ratio", nh / 12.0, fsq)):
+            t0 = time.perf_counter()
+            Yp = net.place(Xhd, r, (s_train[0] * fs, s_train[1] * fs))
+            sync()
+            t_place = time.perf_counter() - t0
             placed = pixelsne.Context.from_data(Xhd, 50.0, r, Y_init=Yp, precision=pixelsne.FP32,
                                                 exag_iters=0, mom_switch=0, eta=reta)
             sync()
@@ -269,8 +275,9 @@ def time_to_kl(ctx_train, X_train, mix, args):
             rr["kl_placed"] = k0
             rr["speedup"] = (t_plain / rr["seconds"]) if rr["seconds"] else None
             rr["precision_k1_10_30"] = placed.neighborhood_precision(hi, [1, 10, 30])
+            rr["place_s"] = t_place
             res[rlabel] = rr
-            del placed
+            del placed, Yp
         out["plain_" + label] = res
         log(f"[bench] time-to-KL plain {label}: {json.dumps(res)}")
     return out
