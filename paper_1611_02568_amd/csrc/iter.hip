@@ -315,49 +315,78 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
 }
 
 // Leaf sums, part 2 (one thread per leaf): a leaf that spans several waves
-// adds its pieces in wave order; every leaf writes its cell record.
+// adds its pieces in wave order: the first piece, then the whole-wave pieces,
+// then the last piece.  Up to kLeafSerial whole-wave pieces the leaf's own
+// thread adds them one after another; a longer leaf (a dense pixel, up to
+// thousands of pieces) is summed by the whole wavefront: lane j adds pieces
+// j, j + 64, ... in order and the 64 lane sums are combined by a fixed
+// butterfly, so the result does not depend on timing either way.  Every leaf
+// writes its cell record.
+constexpr uint32_t kLeafSerial = 8;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tree_leaves(
     const uint32_t* __restrict__ keys, int64_t n, int L, int com_mode,
     const DevScalars* __restrict__ sc, Node* __restrict__ nodes, double2* __restrict__ nsum,
     const double2* __restrict__ wfirst, const double2* __restrict__ wlast) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = lane_id();
     const uint32_t nleaf = sc->level_size[L];
-    if (t >= nleaf) return;
-    const uint32_t gid = sc->level_base[L] + (uint32_t)t;
-    const uint32_t start = nodes[gid].start;
-    const uint32_t end = (t + 1 < nleaf) ? nodes[gid + 1].start : (uint32_t)n;
+    // whole waves past the last leaf leave; the others keep every lane for
+    // the cooperative sums
+    if ((t & ~(int64_t)(kWave - 1)) >= (int64_t)nleaf) return;
+    const bool valid = t < (int64_t)nleaf;
+    const uint32_t gid = sc->level_base[L] + (uint32_t)(valid ? t : 0);
+    const uint32_t start = valid ? nodes[gid].start : 0u;
+    const uint32_t end = !valid ? 1u : (t + 1 < nleaf) ? nodes[gid + 1].start : (uint32_t)n;
     const uint32_t wa = start / kWave, wb = (end - 1) / kWave;
-    double sx, sy;
-    if (wa == wb) {
+    double sx = 0.0, sy = 0.0;
+    const bool spans = valid && wa != wb;
+    const bool coop = spans && wb - wa - 1 > kLeafSerial;
+    if (valid && !spans) {
         const double2 v = nsum[gid];
         sx = v.x;
         sy = v.y;
-    } else {
-        sx = wlast[wa].x;
-        sy = wlast[wa].y;
+    } else if (spans && !coop) {
         for (uint32_t w = wa + 1; w < wb; w++) {
             sx += wfirst[w].x;
             sy += wfirst[w].y;
         }
-        sx += wfirst[wb].x;
-        sy += wfirst[wb].y;
+    }
+    uint64_t todo = ballot64(coop);
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const uint32_t a = (uint32_t)__shfl((int)wa, src, kWave);
+        const uint32_t b = (uint32_t)__shfl((int)wb, src, kWave);
+        double px = 0.0, py = 0.0;
+        for (uint32_t w = a + 1 + (uint32_t)lane; w < b; w += kWave) {
+            px += wfirst[w].x;
+            py += wfirst[w].y;
+        }
+        px = wave_sum(px);
+        py = wave_sum(py);
+        if (lane == src) {
+            sx = px;
+            sy = py;
+        }
+    }
+    if (!valid) return;
+    if (spans) {
+        sx = (wlast[wa].x + sx) + wfirst[wb].x;
+        sy = (wlast[wa].y + sy) + wfirst[wb].y;
     }
     write_node(nodes, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
 }
 
-// One level of inner cells (one thread per cell): counts and sums of the
-// children (consecutive in the next level) added in child order.
-__global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restrict__ keys, int l,
-                                                       int L, int com_mode,
-                                                       const DevScalars* __restrict__ sc,
-                                                       const uint32_t* __restrict__ first_child,
-                                                       Node* __restrict__ nodes,
-                                                       double2* __restrict__ nsum) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t m = sc->level_size[l];
-    if (t >= m) return;
-    const uint32_t g = sc->level_base[l] + (uint32_t)t;
+// One inner cell: count and sums of its children (consecutive in the next
+// level) added in child order.
+__device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, int l, int L,
+                                           int com_mode, const DevScalars* __restrict__ sc,
+                                           const uint32_t* __restrict__ first_child,
+                                           Node* __restrict__ nodes, double2* __restrict__ nsum,
+                                           uint32_t t, uint32_t m) {
+    const uint32_t g = sc->level_base[l] + t;
     const uint32_t fc = first_child[g];
     const uint32_t lc = (t + 1 < m) ? first_child[g + 1] : sc->level_base[l + 1] + sc->level_size[l + 1];
     double ax = 0.0, ay = 0.0;
@@ -370,6 +399,39 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restric
     }
     write_node(nodes, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30), keys[nodes[g].start],
                com_mode);
+}
+
+// One level of inner cells, one thread per cell.
+__global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restrict__ keys, int l,
+                                                       int L, int com_mode,
+                                                       const DevScalars* __restrict__ sc,
+                                                       const uint32_t* __restrict__ first_child,
+                                                       Node* __restrict__ nodes,
+                                                       double2* __restrict__ nsum) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t m = sc->level_size[l];
+    if (t >= m) return;
+    inner_cell(keys, l, L, com_mode, sc, first_child, nodes, nsum, (uint32_t)t, m);
+}
+
+// Levels top..0 in one block (a level l holds at most 4^l cells, so at most
+// kTopThreads for l <= kTopLevel): the block finishes a level before it
+// starts the one above.
+constexpr int kTopLevel = 5;
+constexpr int kTopThreads = 1024;
+
+__global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __restrict__ keys,
+                                                          int top, int L, int com_mode,
+                                                          const DevScalars* __restrict__ sc,
+                                                          const uint32_t* __restrict__ first_child,
+                                                          Node* __restrict__ nodes,
+                                                          double2* __restrict__ nsum) {
+    for (int l = top; l >= 0; l--) {
+        const uint32_t m = sc->level_size[l];
+        for (uint32_t t = threadIdx.x; t < m; t += kTopThreads)
+            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, nsum, t, m);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -626,7 +688,7 @@ __device__ __forceinline__ void seg_scan(T& x, T& y, int key, int lane) {
     seg_step<0x143, 0xC>(x, y, key, lane >= 32);
 }
 
-constexpr int kBatches = 4;      // runs of 64 nonzeros per wavefront in flight
+constexpr int kBatches = 8;      // runs of 64 nonzeros per wavefront in flight
 
 // One block per row chunk (grid-stride over the chunks).  Wavefront w takes
 // the runs w, w + 4, ... of the chunk's nonzeros (column order, each run of
@@ -1098,11 +1160,15 @@ hipError_t run_tree(pixelsne_ctx* c) {
         k_tree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
     }
-    for (int l = c->L - 1; l >= 0; l--) {
+    const int top = c->L - 1 < kTopLevel ? c->L - 1 : kTopLevel;
+    for (int l = c->L - 1; l > top; l--) {
         const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;
         k_tree_level<<<grid_for(cap < c->n ? cap : c->n), kBlock, 0, c->stream>>>(
             keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.nsum);
     }
+    if (top >= 0)
+        k_tree_top<<<1, kTopThreads, 0, c->stream>>>(keys, top, c->L, c->prm.com_mode, c->sc,
+                                                     tb.first_child, tb.nodes, tb.nsum);
     return hipGetLastError();
 }
 
