@@ -645,47 +645,54 @@ template <typename T> __device__ __forceinline__ T sgn(T x) {
 
 // Lane-shifted copies within a wavefront (DPP).  CTRL selects the pattern:
 // row_shr:d moves lane l - d to lane l inside each row of 16 lanes;
-// row_bcast:15 / :31 broadcast lane 15 / 31 into the rows that follow.  Rows
-// outside ROWS keep their own value.
+// row_bcast:15 / :31 broadcast lane 15 / 31 into the rows that follow.  Lanes
+// without a source (the first d of a row, rows outside ROWS) get OLD.
 template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
+__device__ __forceinline__ int dpp_i(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
 }
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_t(float v) {
-    return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(v)));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_t(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = dpp_i<CTRL, ROWS>((int)(uint32_t)b);
-    const int hi = dpp_i<CTRL, ROWS>((int)(uint32_t)(b >> 32));
+    const int lo = dpp_i<CTRL, ROWS>(0, (int)(uint32_t)b);
+    const int hi = dpp_i<CTRL, ROWS>(0, (int)(uint32_t)(b >> 32));
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
+// One step of the segmented scan: add the partial sums of the source lane
+// when it carries the same key (a lane without a source sees key -1, which no
+// lane carries).  The add is a multiply by 1 or 0, which keeps the step free
+// of branches; x + 1 * u and x + 0 * u are exactly x + u and x.
 template <int CTRL, int ROWS, typename T>
-__device__ __forceinline__ void seg_step(T& x, T& y, int key, bool from_ok) {
-    const int k = dpp_i<CTRL, ROWS>(key);
+__device__ __forceinline__ void seg_step(T& x, T& y, int key) {
+    const int k = dpp_i<CTRL, ROWS>(-1, key);
     const T ux = dpp_t<CTRL, ROWS>(x), uy = dpp_t<CTRL, ROWS>(y);
-    if (from_ok && k == key) {
-        x += ux;
-        y += uy;
-    }
+    const T m = k == key ? T(1) : T(0);
+    x = fma(ux, m, x);
+    y = fma(uy, m, y);
 }
 
 // Inclusive scan of (x, y) over the lanes of each run of equal keys, for keys
 // ascending across the wave (Hillis-Steele: at each step a lane adds the
 // partial sum of the lane d below when both carry the same key; keys are
 // sorted, so that partial never leaves the run).  The last lane of a run ends
-// with the run's total.
+// with the run's total.  CONT has bit l set when lane l continues the run of
+// lane l - 1; steps that no run needs are skipped (wave-uniform branches):
+// the shift by d only when some run is longer than d, the broadcast of lane
+// 15 / 47 or 31 only when a run crosses it.
 template <typename T>
-__device__ __forceinline__ void seg_scan(T& x, T& y, int key, int lane) {
-    seg_step<0x111, 0xF>(x, y, key, (lane & 15) >= 1);
-    seg_step<0x112, 0xF>(x, y, key, (lane & 15) >= 2);
-    seg_step<0x114, 0xF>(x, y, key, (lane & 15) >= 4);
-    seg_step<0x118, 0xF>(x, y, key, (lane & 15) >= 8);
-    seg_step<0x142, 0xA>(x, y, key, (lane & 16) != 0);
-    seg_step<0x143, 0xC>(x, y, key, lane >= 32);
+__device__ __forceinline__ void seg_scan(T& x, T& y, int key, uint64_t cont) {
+    const uint64_t c2 = cont & (cont >> 1), c4 = c2 & (c2 >> 2), c8 = c4 & (c4 >> 4);
+    if (cont) seg_step<0x111, 0xF>(x, y, key);
+    if (c2) seg_step<0x112, 0xF>(x, y, key);
+    if (c4) seg_step<0x114, 0xF>(x, y, key);
+    if (c8) seg_step<0x118, 0xF>(x, y, key);
+    if (cont & ((1ull << 16) | (1ull << 48))) seg_step<0x142, 0xA>(x, y, key);
+    if (cont & (1ull << 32)) seg_step<0x143, 0xC>(x, y, key);
 }
 
 constexpr int kBatches = 8;      // runs of 64 nonzeros per wavefront in flight
@@ -758,9 +765,13 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
                 const T pw = p[q] * wq;
                 T sx = pw * dx, sy = pw * dy;
-                seg_scan<T>(sx, sy, r[q], lane);
                 const int nk = __shfl_down(r[q], 1, kWave);
-                if (r[q] < kChunkRows && (lane == kWave - 1 || nk != r[q])) {
+                const bool last = lane == kWave - 1 || nk != r[q];
+                // lanes past the chunk's end (key kChunkRows) count as runs of
+                // their own: their sums are never used
+                const uint64_t cont = ~((ballot64(last) << 1) | 1ull) & ballot64(r[q] < kChunkRows);
+                seg_scan<T>(sx, sy, r[q], cont);
+                if (r[q] < kChunkRows && last) {
                     acc[w][r[q]][0] += sx;
                     acc[w][r[q]][1] += sy;
                 }

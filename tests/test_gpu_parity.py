@@ -165,6 +165,39 @@ def test_gradient_degenerate_single_pixel(psne, prec):
     _grad_check(psne, P, z, np.array([0.02, 0.02]), r, prec, 0.5, alpha=1.0)
 
 
+def _skewed_P(n, seed):
+    """Symmetric P with two hub rows -- row 0 joined to every point (more
+    nonzeros than one row chunk holds) and row 1 to 9,000 points (a chunk of
+    its own) -- besides a ring and ~3 random edges per point (rows of 2 to
+    ~12 nonzeros sharing chunks); random weights, summing to 1."""
+    rng = np.random.default_rng(seed)
+    e = np.concatenate([
+        np.stack([np.zeros(n - 1, np.int64), np.arange(1, n)], 1),
+        np.stack([np.ones(9000, np.int64), np.arange(2, 9002)], 1),
+        np.stack([np.arange(n), (np.arange(n) + 1) % n], 1),
+        rng.integers(0, n, (3 * n, 2))])
+    e = np.unique(np.sort(e[e[:, 0] != e[:, 1]], 1), axis=0)
+    w = rng.uniform(0.5, 1.5, len(e))
+    rows = np.concatenate([e[:, 0], e[:, 1]])
+    cols = np.concatenate([e[:, 1], e[:, 0]])
+    vals = np.concatenate([w, w])
+    o = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(np.bincount(rows, minlength=n))
+    return rp, cols[o].astype(np.int32), vals[o] / vals.sum()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_skewed_rows(psne, prec):
+    """Row lengths from 2 to 19,999: every way the attraction cuts rows into
+    chunks, and runs of one row across whole wavefronts."""
+    n, r = 20000, 1024
+    P = _skewed_P(n, seed=31)
+    assert np.diff(P[0]).max() == n - 1 and np.diff(P[0])[1] > 9000
+    z = datagen.clustered_pixels(n, r, seed=32, n_clusters=20, spread=0.03)
+    _grad_check(psne, P, z, np.array([0.011, 0.009]), r, prec, 0.5, alpha=4.0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_two_points(psne, prec):
     P = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([0.5, 0.5]))
