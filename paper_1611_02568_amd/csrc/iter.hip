@@ -695,6 +695,31 @@ __device__ __forceinline__ void seg_scan(T& x, T& y, int key, uint64_t cont) {
     if (cont & (1ull << 32)) seg_step<0x143, 0xC>(x, y, key);
 }
 
+// The chunk's column words and values are read once per iteration through
+// buffer resources over the chunk's range: 32-bit offsets, and the hardware's
+// range check returns 0 past the end instead of a per-lane select.  Loads
+// carry the non-temporal hint, which keeps the caches for the gathered z_j.
+// A chunk holds fewer than 2^27 nonzeros, so offsets in bytes fit in 31 bits.
+constexpr int kRawBufferWord3 = 0x00020000;   // descriptor word 3: untyped 32-bit access
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const E* base, int64_t count) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(count * sizeof(E)),
+                                             kRawBufferWord3);
+}
+constexpr int kStreamPolicy = 2;   // non-temporal
+template <typename E> __device__ __forceinline__ E stream_load(__amdgpu_buffer_rsrc_t r, int i);
+template <> __device__ __forceinline__ uint32_t stream_load<uint32_t>(__amdgpu_buffer_rsrc_t r,
+                                                                      int i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kStreamPolicy);
+}
+template <> __device__ __forceinline__ float stream_load<float>(__amdgpu_buffer_rsrc_t r, int i) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kStreamPolicy));
+}
+template <> __device__ __forceinline__ double stream_load<double>(__amdgpu_buffer_rsrc_t r, int i) {
+    return __longlong_as_double(
+        (long long)__builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kStreamPolicy));
+}
+
 constexpr int kBatches = 8;      // runs of 64 nonzeros per wavefront in flight
 
 // One block per row chunk (grid-stride over the chunks).  Wavefront w takes
@@ -741,6 +766,8 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             acc[t / kChunkRows][t % kChunkRows][1] = T(0);
         }
         __syncthreads();
+        const __amdgpu_buffer_rsrc_t rpk = stream_rsrc(pk + e0, e1 - e0);
+        const __amdgpu_buffer_rsrc_t rval = stream_rsrc(val + e0, e1 - e0);
         for (int64_t b = e0 + (int64_t)w * kWave; b < e1; b += (int64_t)kBlock * kBatches) {
             uint32_t j[kBatches];
             int r[kBatches];
@@ -748,12 +775,11 @@ __global__ __launch_bounds__(kBlock) void k_attract(
 #pragma unroll
             for (int q = 0; q < kBatches; q++) {
                 const int64_t x = b + q * kBlock + lane;
-                const bool ok = x < e1;
-                // streamed once: keep the per-CU cache for the gathered z_j
-                const uint32_t v = ok ? __builtin_nontemporal_load(&pk[x]) : 0u;
+                const int off = (int)(x - e0);
+                const uint32_t v = stream_load<uint32_t>(rpk, off);
                 j[q] = v & kColMask;
-                r[q] = ok ? (int)(v >> kColBits) : kChunkRows;
-                p[q] = ok ? __builtin_nontemporal_load(&val[x]) : T(0);
+                r[q] = x < e1 ? (int)(v >> kColBits) : kChunkRows;
+                p[q] = stream_load<T>(rval, off);
             }
             V zj[kBatches];
 #pragma unroll
