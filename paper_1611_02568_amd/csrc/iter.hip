@@ -551,26 +551,29 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             if (q >= nsib) break;
             const uint32_t c = first + q;
             const Node nd = grp[q];
-            bool open = false;
+            uint64_t om = 0;   // lanes that open the cell
+            // Every lane evaluates the term; lanes that do not take the cell
+            // add it with mass 0, which leaves their sums bit for bit as they
+            // were and keeps the loop free of divergent branches.
             if (level < L) {
                 // inner cell: the opening test and, for lanes that accept, the
                 // force term share one distance
                 const double dx = zx - nd.cx, dy = zy - nd.cy;
                 const double d2 = dist2(b1, b2, dx, dy);
-                const bool far = diag2 < mul_nc(th2, d2);
-                open = act && !far;
-                if (act && far) {
-                    bh_term<T>(d2, dx, dy, (T)nd.count, zacc, rx, ry);
-                    if (COUNT) nuse++;
+                const bool near = !(diag2 < mul_nc(th2, d2));
+                om = ballot64(near) & mask;   // every lane runs this loop
+                const bool use = act && !near;
+                bh_term<T>(d2, dx, dy, use ? (T)nd.count : T(0), zacc, rx, ry);
+                if (COUNT) {
+                    nuse += use ? 1u : 0u;
+                    nvis += act ? 1u : 0u;
                 }
-                if (COUNT && act) nvis++;
-            } else if (act) {
+            } else {
                 // leaf (one pixel): always used; at its own leaf a point counts
                 // the others only, at their centre of mass in mass mode
-                if (COUNT) nvis++;
                 double cx = nd.cx, cy = nd.cy;
                 T m = (T)nd.count;
-                bool use = true;
+                bool use = act;
                 if (c == own) {
                     const uint32_t others = nd.count - 1u;
                     m = (T)others;
@@ -579,15 +582,15 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                         cx = (sm.x - zx) / (double)others;
                         cy = (sm.y - zy) / (double)others;
                     }
-                    use = others > 0u;
+                    use = act && others > 0u;
                 }
-                if (use) {
-                    const double dx = zx - cx, dy = zy - cy;
-                    bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, m, zacc, rx, ry);
-                    if (COUNT) nuse++;
+                const double dx = zx - cx, dy = zy - cy;
+                bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, use ? m : T(0), zacc, rx, ry);
+                if (COUNT) {
+                    nuse += use ? 1u : 0u;
+                    nvis += act ? 1u : 0u;
                 }
             }
-            const uint64_t om = ballot64(open);
             if (om) {
                 st_first = put_lane((int)(nd.child & 0x3FFFFFFFu), sp, st_first);
                 st_info = put_lane((int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
