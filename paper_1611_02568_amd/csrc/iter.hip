@@ -493,9 +493,21 @@ __device__ __forceinline__ double add_nc(double a, double b) {
     return a + b;
 }
 
-// replace lane `sel` of a per-lane register (sel is wave-uniform)
-__device__ __forceinline__ int put_lane(int v, int sel, int old) {
-    return lane_id() == sel ? v : old;
+// Write a stack entry (four wave-uniform words, in scalar registers) into
+// lane `sel` of the four per-lane stack registers.  With one scalar operand
+// per vector instruction the lane select goes through m0, written here by a
+// scalar move; the s_nop adds two wait states before it is read.
+__device__ __forceinline__ void push_entry(int& a, int& b, int& c, int& d, int va, int vb,
+                                           int vc, int vd, int sel) {
+    asm("s_mov_b32 m0, %8\n\t"
+        "s_nop 1\n\t"
+        "v_writelane_b32 %0, %4, m0\n\t"
+        "v_writelane_b32 %1, %5, m0\n\t"
+        "v_writelane_b32 %2, %6, m0\n\t"
+        "v_writelane_b32 %3, %7, m0"
+        : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
+        : "s"(va), "s"(vb), "s"(vc), "s"(vd), "s"(sel)
+        : "m0");
 }
 
 template <typename T, bool COUNT>
@@ -527,9 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     int sp = 0;
     const uint64_t m0 = ballot64(valid);
     if (m0) {
-        st_info = put_lane(1, 0, st_info);
-        st_mlo = put_lane((int)(uint32_t)m0, 0, st_mlo);
-        st_mhi = put_lane((int)(uint32_t)(m0 >> 32), 0, st_mhi);
+        push_entry(st_first, st_info, st_mlo, st_mhi, 0, 1, (int)(uint32_t)m0,
+                   (int)(uint32_t)(m0 >> 32), 0);
         sp = 1;
     }
     while (sp > 0) {
@@ -592,11 +603,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 }
             }
             if (om) {
-                st_first = put_lane((int)(nd.child & 0x3FFFFFFFu), sp, st_first);
-                st_info = put_lane((int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
-                                                     sp, st_info);
-                st_mlo = put_lane((int)(uint32_t)om, sp, st_mlo);
-                st_mhi = put_lane((int)(uint32_t)(om >> 32), sp, st_mhi);
+                push_entry(st_first, st_info, st_mlo, st_mhi, (int)(nd.child & 0x3FFFFFFFu),
+                           (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
+                           (int)(uint32_t)om, (int)(uint32_t)(om >> 32), sp);
                 sp++;
             }
         }
