@@ -83,10 +83,11 @@ typedef struct {
                                  (y frame); NULL => N(0, init_sigma^2) from seed */
     void* stream;             /* hipStream_t for all work; NULL => null stream */
     int32_t reorder_every;    /* renumber points internally by their Morton order after the
-                                 first iteration and then every this many iterations
-                                 (memory locality of the sparse attraction); 0 = never
-                                 [100].  Results are reported in the caller's numbering
-                                 either way. */
+                                 first iteration and then after intervals that start at
+                                 this many iterations and grow by reorder_growth (memory
+                                 locality of the sparse attraction); 0 = never [100].
+                                 Results are reported in the caller's numbering either
+                                 way. */
     int32_t data_order;       /* pixelsne_init_ex only.  1: number the points internally by
                                  a Morton code of three random projections of X, so that
                                  neighbours in P sit close in memory before the embedding
@@ -98,6 +99,11 @@ typedef struct {
                                  graph (captured on first use; no launch overhead per
                                  kernel); 0: launch the kernels one by one [1].  Results
                                  are identical. */
+    double reorder_growth;    /* factor by which the interval between renumberings grows
+                                 after each one, >= 1 (1: a fixed period) [2].  The layout
+                                 moves less and less per iteration as the embedding
+                                 settles, so the locality a renumbering restores decays
+                                 more slowly the later it is made. */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -180,6 +186,7 @@ typedef struct {
     double s[2];              /* y units per pixel, per axis (beta_d = s_d^2, Eq. 13) */
     double Z;                 /* last Barnes-Hut normaliser */
     int64_t level_size[17];   /* occupied cells per level 0..L of the last tree */
+    int32_t renumberings;     /* scheduled internal renumberings so far */
 } pixelsne_stats;
 
 /* Synchronises the stream. */

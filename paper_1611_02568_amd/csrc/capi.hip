@@ -60,6 +60,8 @@ psne_status check_params(const pixelsne_params* p) {
         return invalid("unknown x_dtype");
     if (p->exag_iters < 0 || p->mom_switch < 0) return invalid("negative schedule length");
     if (p->reorder_every < 0) return invalid("reorder_every must be >= 0");
+    if (!(p->reorder_growth >= 1.0 && p->reorder_growth <= 1e6))
+        return invalid("reorder_growth must be in [1, 1e6]");
     if (p->graphs != 0 && p->graphs != 1) return invalid("graphs must be 0 or 1");
     if (p->data_order != 0 && p->data_order != 1) return invalid("data_order must be 0 or 1");
     return PSNE_OK;
@@ -199,8 +201,7 @@ hipError_t step_one(pixelsne_ctx* c) {
         }
     }
     if (!done) e = run_iteration_passes(c);
-    if (e == hipSuccess && c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
-        e = run_reorder(c);
+    if (e == hipSuccess) e = run_scheduled_reorder(c);
     return e;
 }
 
@@ -263,6 +264,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->reorder_every = 100;
     p->data_order = 1;
     p->graphs = 1;
+    p->reorder_growth = 2.0;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -455,6 +457,7 @@ psne_status pixelsne_get_stats(const pixelsne_ctx* c, pixelsne_stats* out) {
     out->s[1] = h.s[1];
     out->Z = h.Z;
     for (int l = 0; l <= c->L && l < 17; l++) out->level_size[l] = h.level_size[l];
+    out->renumberings = c->scheduled_reorders;
     return PSNE_OK;
 }
 

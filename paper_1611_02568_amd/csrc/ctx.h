@@ -60,9 +60,9 @@ struct pixelsne_ctx {
     psne::DevScalars* sc = nullptr;
     psne::TreeBufs tb;
 
-    // Internal order: points are renumbered by their Morton order every
-    // prm.reorder_every iterations so that the neighbours of a CSR row sit
-    // close in memory.  orig[i] is the caller's index of internal point i and
+    // Internal order: points are renumbered by their Morton order on a
+    // schedule (prm.reorder_every, prm.reorder_growth) so that the neighbours
+    // of a CSR row sit close in memory.  orig[i] is the caller's index of internal point i and
     // inv its inverse.
     uint32_t* orig = nullptr;
     uint32_t* orig2 = nullptr;
@@ -72,7 +72,9 @@ struct pixelsne_ctx {
     void* g2 = nullptr;
     int64_t* len_tmp = nullptr;              // [n + 1]
     int64_t* scan_tmp = nullptr;
-    int32_t since_reorder = 0;
+    int32_t since_reorder = 0;               // iterations since the last renumbering
+    int64_t reorder_interval = 0;            // ... at which the next one is due
+    int32_t scheduled_reorders = 0;
 
     // P for the attraction pass: internal rows cut into chunks of at most
     // kChunkRows consecutive rows; within a chunk the nonzeros are ordered by
@@ -125,6 +127,7 @@ hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
 hipError_t run_kl(const pixelsne_ctx* c, double* kl);
 // renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
+hipError_t run_scheduled_reorder(pixelsne_ctx* c);
 hipError_t run_identity_order(pixelsne_ctx* c);
 // renumber by a Morton code of three random projections of X (rows of D
 // elements of x_dtype) and delay the first renumbering by the embedding to the

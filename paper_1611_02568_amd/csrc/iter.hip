@@ -1309,8 +1309,7 @@ hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev) {
     if ((e = hipEventRecord(ev[6], c->stream)) != hipSuccess) return e;
     if ((e = run_finalize(c, 1)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[7], c->stream)) != hipSuccess) return e;
-    if (c->prm.reorder_every > 0 && ++c->since_reorder >= c->prm.reorder_every)
-        if ((e = run_reorder(c)) != hipSuccess) return e;
+    if ((e = run_scheduled_reorder(c)) != hipSuccess) return e;
     return hipEventRecord(ev[8], c->stream);
 }
 

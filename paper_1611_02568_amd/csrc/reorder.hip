@@ -3,8 +3,9 @@
 // The sparse attraction gathers z_j for every nonzero of row i.  When points
 // are numbered arbitrarily these gathers touch random cache lines of an
 // array larger than one XCD's L2.  The library therefore renumbers the points
-// by the Morton order of a recent sort (after the first iteration, then every
-// params.reorder_every iterations): the per-point state is permuted, and P,
+// by the Morton order of a recent sort (after the first iteration or the early
+// exaggeration, then after intervals of params.reorder_every iterations that
+// grow by params.reorder_growth): the per-point state is permuted, and P,
 // kept in the caller's numbering, is copied into the attraction's layout for
 // the new numbering.  That layout cuts the internal rows into chunks of up to
 // kChunkRows consecutive rows and orders each chunk's nonzeros by column, so
@@ -12,6 +13,8 @@
 // each run of 64 is then ordered by row, which lets the attraction kernel sum
 // a row's terms with a segmented scan across the wave.  The method's
 // arithmetic is unchanged; only the order of the per-row summands changes.
+#include <cmath>
+
 #include "ctx.h"
 
 namespace psne {
@@ -283,6 +286,7 @@ hipError_t run_identity_order(pixelsne_ctx* c) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the first renumbering follows the first iteration
+    c->reorder_interval = c->prm.reorder_every;
     c->since_reorder = c->prm.reorder_every > 0 ? c->prm.reorder_every - 1 : 0;
     return build_chunks(c);
 }
@@ -294,11 +298,25 @@ hipError_t run_data_order(pixelsne_ctx* c, const void* X, int32_t D, int32_t x_d
     if (e != hipSuccess) return e;
     // the embedding's own order is worth following once the early exaggeration
     // has formed its clusters
+    c->reorder_interval = c->prm.reorder_every;
     if (c->prm.reorder_every > 0) {
         const int32_t first = c->prm.exag_iters > 1 ? c->prm.exag_iters : 1;
         c->since_reorder = c->prm.reorder_every - first;
     }
     return hipSuccess;
+}
+
+// After an iteration: renumber when the schedule says so.  The interval after
+// the first scheduled renumbering is reorder_every; after each later one it
+// grows by reorder_growth.
+hipError_t run_scheduled_reorder(pixelsne_ctx* c) {
+    if (c->prm.reorder_every <= 0 || ++c->since_reorder < c->reorder_interval) return hipSuccess;
+    const hipError_t e = run_reorder(c);
+    if (c->scheduled_reorders++ > 0) {
+        const double next = std::ceil((double)c->reorder_interval * c->prm.reorder_growth);
+        c->reorder_interval = next < 2147483647.0 ? (int64_t)next : 2147483647;
+    }
+    return e;
 }
 
 hipError_t run_reorder(pixelsne_ctx* c) {

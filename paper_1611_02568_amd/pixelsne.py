@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("reorder_every", C.c_int32),
         ("data_order", C.c_int32),
         ("graphs", C.c_int32),
+        ("reorder_growth", C.c_double),
     ]
 
 
@@ -52,6 +53,7 @@ class Stats(C.Structure):
         ("r", C.c_int32), ("L", C.c_int32), ("k", C.c_int32),
         ("precision", C.c_int32), ("com_mode", C.c_int32), ("iteration", C.c_int32),
         ("s", C.c_double * 2), ("Z", C.c_double), ("level_size", C.c_int64 * 17),
+        ("renumberings", C.c_int32),
     ]
 
 

@@ -40,6 +40,7 @@ def test_params_layout_matches(psne):
     assert p.struct_size == C.sizeof(psne.Params)
     assert (p.theta, p.eta, p.exaggeration, p.exag_iters, p.mom_switch) == (0.5, 200.0, 12.0, 250, 250)
     assert (p.mom0, p.mom1, p.min_gain, p.eps, p.init_sigma) == (0.5, 0.8, 0.01, 1e-6, 1e-4)
+    assert (p.reorder_every, p.reorder_growth, p.data_order, p.graphs) == (100, 2.0, 1, 1)
 
 
 def _init(psne, X, n, D, u, w, h, **kw):
@@ -66,7 +67,8 @@ def test_init_validation(psne, args, frag):
 
 @pytest.mark.parametrize("kw,frag", [({"theta": 1.0}, "theta"), ({"precision": 7}, "precision"),
                                      ({"com_mode": 3}, "com_mode"), ({"struct_size": 8}, "struct_size"),
-                                     ({"eta": 0.0}, "eta")])
+                                     ({"eta": 0.0}, "eta"), ({"reorder_growth": 0.5}, "reorder_growth"),
+                                     ({"reorder_every": -1}, "reorder_every")])
 def test_params_validation(psne, kw, frag):
     X = np.zeros((10, 4), np.float32)
     assert not _init(psne, X.ctypes.data, 10, 4, 3.0, 512, 512, **kw)

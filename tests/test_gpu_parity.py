@@ -325,7 +325,7 @@ def test_reorder_keeps_caller_order(psne, small_problem, prec):
     X, P, st = small_problem
     dt = _state_dtype(prec)
     ctx = psne.Context.from_P(*P, screen=512, Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=4)),
-                              precision=prec, reorder_every=3)
+                              precision=prec, reorder_every=3, reorder_growth=1.0)
     ctx.step(10)                                  # renumbered after iterations 1, 4, 7, 10
     zt = np.minimum(st.z.astype(dt), np.nextafter(dt(512), dt(0)))
     ctx.set_state(zt, st.s)
@@ -359,6 +359,28 @@ def test_reorder_does_not_change_the_trajectory(psne, small_problem):
     assert np.max(np.abs(ya - yb)) <= 1e-8 * np.max(np.abs(yb))
 
 
+@pytest.mark.parametrize("growth,want", [(2.0, [1, 4, 10, 22]),
+                                         (1.0, [1, 4, 7, 10, 13, 16, 19, 22])])
+def test_reorder_schedule(psne, small_problem, growth, want):
+    """From the caller's order: a renumbering after the first iteration, then
+    after intervals of reorder_every = 3 iterations growing by reorder_growth
+    (3, 6, 12 for growth 2).  Graph replay and direct launches keep the same
+    schedule."""
+    X, P, _ = small_problem
+    y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=8))
+    for graphs in (1, 0):
+        ctx = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=0, reorder_every=3,
+                                  reorder_growth=growth, graphs=graphs)
+        got, done = [], 0
+        for it in range(1, 25):
+            ctx.step(1)
+            k = ctx.stats().renumberings
+            if k > done:
+                got.append(it)
+                done = k
+        assert got == want, (graphs, got)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_graph_replay_matches_direct_launches(psne, small_problem, prec):
     """Stepping through the captured iteration graph gives bit-identical states
@@ -366,8 +388,10 @@ def test_graph_replay_matches_direct_launches(psne, small_problem, prec):
     between the two captured graphs) and with other work between the calls."""
     X, P, _ = small_problem
     y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=6))
-    a = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3, graphs=1)
-    b = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3, graphs=0)
+    a = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3,
+                            reorder_growth=1.0, graphs=1)
+    b = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=3,
+                            reorder_growth=1.0, graphs=0)
     for k in (1, 2, 5, 4):
         a.step(k)
         b.step(k)
