@@ -80,20 +80,26 @@ __global__ __launch_bounds__(kBlock) void k_int_len(const uint32_t* __restrict__
     }
 }
 
-// A chunk starts at every kChunkRows-th row, where the row offset enters a
-// new window of kChunkHalf nonzeros, and around every row longer than
-// kChunkHalf.  So a chunk of several rows spans less than one window plus one
-// row of at most kChunkHalf: fewer than kChunkMaxNnz nonzeros.
-__device__ __forceinline__ bool chunk_start(const int64_t* __restrict__ rp, int64_t s) {
-    if (s == 0 || s % kChunkRows == 0) return true;
-    const int64_t a = rp[s - 1], b = rp[s], c = rp[s + 1];
+// Chunks are the groups of kChunkRows consecutive rows.  A group with
+// kChunkMaxNnz nonzeros or more is cut further: a chunk starts where the row
+// offset (from the group's start) enters a new window of kChunkHalf nonzeros,
+// and around every row longer than kChunkHalf.  So a chunk of several rows
+// holds fewer than kChunkMaxNnz nonzeros (one window plus one row of at most
+// kChunkHalf).  Full groups keep the attraction's per-chunk work (prologue,
+// barriers, the last partly filled batch) small against its streaming.
+__device__ __forceinline__ bool chunk_start(const int64_t* __restrict__ rp, int64_t n, int64_t s) {
+    if (s % kChunkRows == 0) return true;
+    const int64_t g0 = s - s % kChunkRows, g1 = g0 + kChunkRows < n ? g0 + kChunkRows : n;
+    const int64_t base = rp[g0];
+    if (rp[g1] - base < kChunkMaxNnz) return false;
+    const int64_t a = rp[s - 1] - base, b = rp[s] - base, c = rp[s + 1] - base;
     return (a / kChunkHalf) != (b / kChunkHalf) || c - b > kChunkHalf || b - a > kChunkHalf;
 }
 
 __global__ __launch_bounds__(kBlock) void k_chunk_flags(const int64_t* __restrict__ rp, int64_t n,
                                                         int64_t* __restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s < n) flag[s] = chunk_start(rp, s) ? 1 : 0;
+    if (s < n) flag[s] = chunk_start(rp, n, s) ? 1 : 0;
     else if (s == n) flag[n] = 0;
 }
 
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_rows(const int64_t* __restrict
                                                        DevScalars* __restrict__ sc) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s < n) {
-        if (chunk_start(rp, s)) ch_row[cid[s]] = (uint32_t)s;
+        if (chunk_start(rp, n, s)) ch_row[cid[s]] = (uint32_t)s;
     } else if (s == n) {
         ch_row[cid[n]] = (uint32_t)n;
         sc->n_chunks = cid[n];
