@@ -44,15 +44,17 @@ def log(msg):
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if there is none or the kernel's source changed since."""
+    None if there is none or a source the kernel's traffic depends on (its
+    own, and the layout it reads) changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             entry = json.load(f)["kernels"].get(kernel)
         if not entry:
             return None
-        with open(os.path.join(ROOT, entry["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != entry["source_sha256"]:
-                return None
+        for path, sha in entry["sources_sha256"].items():
+            with open(os.path.join(ROOT, path), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != sha:
+                    return None
         return (entry["fetch_kib"] * 1024 * entry["fetch_scale"]
                 + entry["write_kib"] * 1024 * entry["write_scale"])
     except (OSError, KeyError, ValueError):
@@ -466,12 +468,12 @@ def main():
     dom = max(per, key=per.get)
     if dom == "traverse":
         ach = main32["traverse"]["TFLOPs"]
-        roof = {"bound": "alu", "kernel": "k_traverse<float>", "achieved": ach,
+        roof = {"bound": "alu", "kernel": "k_traverse<float, false>", "achieved": ach,
                 "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
                 "traffic": None}
     elif dom == "attract":
         ach = main32["attract"]["GBps"]
-        roof = {"bound": "hbm", "kernel": "k_attract<float,0>", "achieved": ach,
+        roof = {"bound": "hbm", "kernel": "k_attract<float, 0>", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                 "traffic": None}
     elif "tree_build" in main32:
