@@ -732,7 +732,9 @@ template <> __device__ __forceinline__ double stream_load<double>(__amdgpu_buffe
         (long long)__builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kStreamPolicy));
 }
 
-constexpr int kBatches = 8;      // runs of 64 nonzeros per wavefront in flight
+// runs of 64 nonzeros per wavefront in flight: as many as the registers allow
+// without costing occupancy (FP64 values and partial sums take twice the room)
+template <typename T> constexpr int kBatches = sizeof(T) == 4 ? 12 : 8;
 
 // One block per row chunk (grid-stride over the chunks).  Wavefront w takes
 // the runs w, w + 4, ... of the chunk's nonzeros (column order, each run of
@@ -780,12 +782,12 @@ __global__ __launch_bounds__(kBlock) void k_attract(
         __syncthreads();
         const __amdgpu_buffer_rsrc_t rpk = stream_rsrc(pk + e0, e1 - e0);
         const __amdgpu_buffer_rsrc_t rval = stream_rsrc(val + e0, e1 - e0);
-        for (int64_t b = e0 + (int64_t)w * kWave; b < e1; b += (int64_t)kBlock * kBatches) {
-            uint32_t j[kBatches];
-            int r[kBatches];
-            T p[kBatches];
+        for (int64_t b = e0 + (int64_t)w * kWave; b < e1; b += (int64_t)kBlock * kBatches<T>) {
+            uint32_t j[kBatches<T>];
+            int r[kBatches<T>];
+            T p[kBatches<T>];
 #pragma unroll
-            for (int q = 0; q < kBatches; q++) {
+            for (int q = 0; q < kBatches<T>; q++) {
                 const int64_t x = b + q * kBlock + lane;
                 const int off = (int)(x - e0);
                 const uint32_t v = stream_load<uint32_t>(rpk, off);
@@ -793,11 +795,11 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 r[q] = x < e1 ? (int)(v >> kColBits) : kChunkRows;
                 p[q] = stream_load<T>(rval, off);
             }
-            V zj[kBatches];
+            V zj[kBatches<T>];
 #pragma unroll
-            for (int q = 0; q < kBatches; q++) zj[q] = reinterpret_cast<const V*>(z)[j[q]];
+            for (int q = 0; q < kBatches<T>; q++) zj[q] = reinterpret_cast<const V*>(z)[j[q]];
 #pragma unroll
-            for (int q = 0; q < kBatches; q++) {
+            for (int q = 0; q < kBatches<T>; q++) {
                 const V zi = zrow[r[q] < kChunkRows ? r[q] : 0];
                 const T dx = zi.x - zj[q].x, dy = zi.y - zj[q].y;
                 const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
