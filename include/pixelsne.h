@@ -152,16 +152,21 @@ psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter);
 psne_status pixelsne_step_async(pixelsne_ctx* c, int32_t n_iter);
 
 /* Time spent in each pass, summed over the iterations of one call (ms),
- * measured with HIP events recorded on the context's stream between passes. */
+ * measured with HIP events recorded between passes.  The attraction's row sums
+ * run on a second stream of the context, at the same time as sort, tree,
+ * traversal and Z; their time is measured on that stream, so the passes add
+ * up to more than the iteration's wall time. */
 typedef struct {
     double snap_ms;       /* pending screen scaling + pixel + Morton key */
     double sort_ms;       /* radix sort of (key, index) */
     double tree_ms;       /* cell numbering, counts and FP64 sums */
     double traverse_ms;   /* Barnes-Hut repulsion */
     double zsum_ms;       /* Z reduction */
-    double attract_ms;    /* attraction + gains/momentum step */
-    double finalize_ms;   /* screen scaling factors */
-    double reorder_ms;    /* internal renumbering (every params.reorder_every iterations) */
+    double attract_ms;    /* attraction row sums (second stream, overlapping the above) */
+    double finalize_ms;   /* gains/momentum step and screen scaling factors, after the
+                             attraction has finished */
+    double reorder_ms;    /* internal renumbering (on the params.reorder_every /
+                             reorder_growth schedule) */
     int32_t iterations;
 } pixelsne_pass_times;
 

@@ -102,6 +102,15 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &c->u, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->g, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->R, v2)) != hipSuccess) return e;
+    if ((e = dalloc(c, &c->A, v2)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) return e;
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device)) !=
+        hipSuccess)
+        return e;
+    c->side_blocks = 2 * (int64_t)(cus > 0 ? cus : 1);
     c->zpart_n = ceil_div(n, 256);
     if ((e = dalloc(c, &c->zpart, sizeof(double) * c->zpart_n)) != hipSuccess) return e;
     c->mm_n = attract_block_count(n);
@@ -160,6 +169,9 @@ void free_ctx(pixelsne_ctx* c) {
     for (hipGraphExec_t& g : c->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
 }
@@ -399,19 +411,25 @@ psne_status pixelsne_step_profiled(pixelsne_ctx* c, int32_t n_iter, pixelsne_pas
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
     if (n_iter < 0) return invalid("n_iter must be >= 0");
     memset(out, 0, sizeof(*out));
-    std::vector<hipEvent_t> ev((size_t)n_iter * 9);
+    constexpr int kEv = 11;     // pass boundaries of one iteration (see run_iteration_timed)
+    std::vector<hipEvent_t> ev((size_t)n_iter * kEv);
     hipError_t e = hipSuccess;
     size_t made = 0;
     for (; made < ev.size() && e == hipSuccess; made++) e = hipEventCreate(&ev[made]);
     if (e != hipSuccess) made--;
-    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++) e = run_iteration_timed(c, &ev[9 * it]);
+    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
+        e = run_iteration_timed(c, &ev[(size_t)kEv * it]);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     double* acc[8] = {&out->snap_ms, &out->sort_ms, &out->tree_ms, &out->traverse_ms,
                       &out->zsum_ms, &out->attract_ms, &out->finalize_ms, &out->reorder_ms};
+    // (from, to) event of each pass: main-stream passes, the row sums on the
+    // second stream, update + scaling from the join, renumbering
+    const int span[8][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {9, 10}, {6, 7}, {7, 8}};
     for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
         for (int p = 0; p < 8 && e == hipSuccess; p++) {
             float ms = 0.f;
-            e = hipEventElapsedTime(&ms, ev[9 * it + p], ev[9 * it + p + 1]);
+            e = hipEventElapsedTime(&ms, ev[(size_t)kEv * it + span[p][0]],
+                                    ev[(size_t)kEv * it + span[p][1]]);
             *acc[p] += ms;
         }
     for (size_t i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
@@ -515,7 +533,7 @@ psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, v
     if (e == hipSuccess) e = run_tree(c);
     if (e == hipSuccess) e = run_traverse(c, visits, used, Zi);
     if (e == hipSuccess) e = run_zsum(c);
-    if (e == hipSuccess) e = run_attract(c, 1, alpha, A, B);
+    if (e == hipSuccess) e = run_attract(c, alpha, A, B);
     if (e == hipSuccess && R) e = run_to_user_v2(c, c->R, R);
     double hz = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hz, &c->sc->Z, 8, hipMemcpyDeviceToHost, c->stream);

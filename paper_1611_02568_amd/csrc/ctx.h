@@ -88,6 +88,16 @@ struct pixelsne_ctx {
     // one iteration captured as a HIP graph, one per state-buffer parity
     // (renumbering swaps the state buffers with their spares)
     hipStream_t cap_stream = nullptr;
+
+    // The attraction's row sums (A, internal order, state type [n][2]) run on
+    // a second stream, forked after the snap pass and joined before the
+    // update, so that the memory-bound sums share the GPU with the sort, tree
+    // and the ALU-bound traversal.  side_blocks: its persistent grid, sized
+    // to leave most of each CU to the traversal.
+    void* A = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int64_t side_blocks = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int32_t parity = 0;
     bool graph_failed = false;
@@ -110,7 +120,7 @@ hipError_t run_tree(pixelsne_ctx* c);
 hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi);
 hipError_t run_zsum(pixelsne_ctx* c);
 // mode 0: gradient step; mode 1: write A and B only (no update)
-hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B);
+hipError_t run_attract(pixelsne_ctx* c, double alpha, void* A, void* B);
 hipError_t run_finalize(pixelsne_ctx* c, int advance);
 // the passes of one iteration without the renumbering
 hipError_t run_iteration_passes(pixelsne_ctx* c);

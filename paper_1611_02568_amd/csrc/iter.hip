@@ -742,34 +742,25 @@ template <typename T> constexpr int kBatches = sizeof(T) == 4 ? 12 : 8;
 // p_ij w_ij (z_i - z_j) with z_i from LDS, sums each row's terms across the
 // run with a segmented scan, and adds the totals to its own LDS partial sums
 // (one writer per address, no atomics).  Thread t < rows of the chunk then
-// adds the four waves' partials in a fixed order and applies the step to
-// row t.  Sums are therefore reproducible.
+// adds the four waves' partials in a fixed order.  Sums are therefore
+// reproducible.  MODE 0 (the iteration) writes the row sums A_i in the
+// internal order; MODE 1 (the gradient hook) writes A_i and the full
+// gradient B_i = alpha A_i - R_i / Z in the caller's order, after the
+// traversal.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_attract(
     const uint32_t* __restrict__ ch_row, const int64_t* __restrict__ rp_int,
-    const uint32_t* __restrict__ pk, const T* __restrict__ val,
-    const T* __restrict__ z, const T* __restrict__ R, T* __restrict__ u, T* __restrict__ g,
-    T* __restrict__ zh, DevScalars* __restrict__ sc, StepParams prm,
-    const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout,
-    double* __restrict__ mm_part) {
+    const uint32_t* __restrict__ pk, const T* __restrict__ val, const T* __restrict__ z,
+    const T* __restrict__ R, const DevScalars* __restrict__ sc, double alpha,
+    const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout) {
     using V = v2_t<T>;
     __shared__ T acc[4][kChunkRows][2];
     __shared__ V zrow[kChunkRows];
-    __shared__ double red[4][4];
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const double s0 = sc->s[0], s1 = sc->s[1];
     const T b1 = (T)(s0 * s0), b2 = (T)(s1 * s1);
-    const double Z = sc->Z;
-    const int it = sc->t;
-    const double alpha = MODE == 1 ? prm.alpha_override
-                                   : (it < prm.exag_iters ? prm.exaggeration : 1.0);
-    const T mu = (T)(it < prm.mom_switch ? prm.mom0 : prm.mom1);
-    const T us0 = (T)sc->uscale[0], us1 = (T)sc->uscale[1];
-    const T eta = (T)prm.eta, gmin = (T)prm.min_gain;
     const int64_t nch = sc->n_chunks;
     constexpr uint32_t kColMask = (1u << kColBits) - 1u;
-    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
-    bool bad = false;
     for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const int64_t ra = ch_row[ch];
         const int nr = (int)((int64_t)ch_row[ch + 1] - ra);
@@ -822,38 +813,67 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             const T mx = ((acc[0][t][0] + acc[1][t][0]) + acc[2][t][0]) + acc[3][t][0];
             const T my = ((acc[0][t][1] + acc[1][t][1]) + acc[2][t][1]) + acc[3][t][1];
             const int64_t i = ra + t;
-            const V Ri = reinterpret_cast<const V*>(R)[i];
-            const T bx = (T)(alpha * (double)mx - (double)Ri.x / Z);
-            const T by = (T)(alpha * (double)my - (double)Ri.y / Z);
-            if (MODE == 1) {
+            if (MODE == 0) {
+                reinterpret_cast<V*>(Aout)[i] = V{mx, my};
+            } else {
+                const double Z = sc->Z;
+                const V Ri = reinterpret_cast<const V*>(R)[i];
+                const T bx = (T)(alpha * (double)mx - (double)Ri.x / Z);
+                const T by = (T)(alpha * (double)my - (double)Ri.y / Z);
                 if (Aout) reinterpret_cast<V*>(Aout)[orig[i]] = V{mx, my};
                 if (Bout) reinterpret_cast<V*>(Bout)[orig[i]] = V{bx, by};
-            } else {
-                const V zii = zrow[t];
-                V ui = reinterpret_cast<V*>(u)[i];
-                V gi = reinterpret_cast<V*>(g)[i];
-                ui.x *= us0;
-                ui.y *= us1;
-                T gx = sgn(bx) != sgn(ui.x) ? gi.x + T(0.2) : gi.x * T(0.8);
-                T gy = sgn(by) != sgn(ui.y) ? gi.y + T(0.2) : gi.y * T(0.8);
-                gx = gx < gmin ? gmin : gx;
-                gy = gy < gmin ? gmin : gy;
-                ui.x = mu * ui.x - eta * gx * bx;
-                ui.y = mu * ui.y - eta * gy * by;
-                const T hx = zii.x + ui.x, hy = zii.y + ui.y;
-                reinterpret_cast<V*>(u)[i] = ui;
-                reinterpret_cast<V*>(g)[i] = V{gx, gy};
-                reinterpret_cast<V*>(zh)[i] = V{hx, hy};
-                if (!isfinite(hx) || !isfinite(hy)) bad = true;
-                mnx = fmin(mnx, (double)hx);
-                mny = fmin(mny, (double)hy);
-                mxx = fmax(mxx, (double)hx);
-                mxy = fmax(mxy, (double)hy);
             }
         }
         __syncthreads();
     }
-    if (MODE == 1) return;
+}
+
+// The optimiser step for every point (internal order), after the attraction
+// and the traversal: B_i = alpha A_i - R_i / Z, gains and momentum, the new
+// positions zh, and the per-block min/max of zh for the screen scaling.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(
+    const T* __restrict__ A, const T* __restrict__ z, const T* __restrict__ R, T* __restrict__ u,
+    T* __restrict__ g, T* __restrict__ zh, DevScalars* __restrict__ sc, StepParams prm, int64_t n,
+    double* __restrict__ mm_part) {
+    using V = v2_t<T>;
+    __shared__ double red[4][4];
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const double Z = sc->Z;
+    const int it = sc->t;
+    const double alpha = it < prm.exag_iters ? prm.exaggeration : 1.0;
+    const T mu = (T)(it < prm.mom_switch ? prm.mom0 : prm.mom1);
+    const T us0 = (T)sc->uscale[0], us1 = (T)sc->uscale[1];
+    const T eta = (T)prm.eta, gmin = (T)prm.min_gain;
+    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const V a = reinterpret_cast<const V*>(A)[i];
+        const V Ri = reinterpret_cast<const V*>(R)[i];
+        const T bx = (T)(alpha * (double)a.x - (double)Ri.x / Z);
+        const T by = (T)(alpha * (double)a.y - (double)Ri.y / Z);
+        const V zi = reinterpret_cast<const V*>(z)[i];
+        V ui = reinterpret_cast<V*>(u)[i];
+        V gi = reinterpret_cast<V*>(g)[i];
+        ui.x *= us0;
+        ui.y *= us1;
+        T gx = sgn(bx) != sgn(ui.x) ? gi.x + T(0.2) : gi.x * T(0.8);
+        T gy = sgn(by) != sgn(ui.y) ? gi.y + T(0.2) : gi.y * T(0.8);
+        gx = gx < gmin ? gmin : gx;
+        gy = gy < gmin ? gmin : gy;
+        ui.x = mu * ui.x - eta * gx * bx;
+        ui.y = mu * ui.y - eta * gy * by;
+        const T hx = zi.x + ui.x, hy = zi.y + ui.y;
+        reinterpret_cast<V*>(u)[i] = ui;
+        reinterpret_cast<V*>(g)[i] = V{gx, gy};
+        reinterpret_cast<V*>(zh)[i] = V{hx, hy};
+        if (!isfinite(hx) || !isfinite(hy)) bad = true;
+        mnx = fmin(mnx, (double)hx);
+        mny = fmin(mny, (double)hy);
+        mxx = fmax(mxx, (double)hx);
+        mxy = fmax(mxy, (double)hy);
+    }
     if (ballot64(bad) && lane == 0) atomicOr(&sc->nonfinite, 1);
     mnx = wave_min(mnx); mny = wave_min(mny); mxx = wave_max(mxx); mxy = wave_max(mxy);
     if (lane == 0) {
@@ -1250,30 +1270,46 @@ hipError_t run_zsum(pixelsne_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t run_attract(pixelsne_ctx* c, int mode, double alpha, void* A, void* B) {
-    const StepParams p = step_params(c, alpha);
+// The gradient hook: A and B in the caller's order, on the context's stream
+// (after the traversal).
+hipError_t run_attract(pixelsne_ctx* c, double alpha, void* A, void* B) {
     const dim3 grid((unsigned)attract_blocks(c->n));
-    if (fp64(c)) {
-        using T = double;
-        if (mode == 0)
-            k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
-                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
-                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, nullptr, nullptr, c->mm_part);
-        else
-            k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
-                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
-                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, (T*)A, (T*)B, c->mm_part);
-    } else {
-        using T = float;
-        if (mode == 0)
-            k_attract<T, 0><<<grid, kBlock, 0, c->stream>>>(
-                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
-                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, nullptr, nullptr, c->mm_part);
-        else
-            k_attract<T, 1><<<grid, kBlock, 0, c->stream>>>(
-                c->ch_row, c->rp_int, c->pk, (const T*)c->vch, (const T*)c->z, (const T*)c->R,
-                (T*)c->u, (T*)c->g, (T*)c->zh, c->sc, p, c->orig, (T*)A, (T*)B, c->mm_part);
-    }
+    if (fp64(c))
+        k_attract<double, 1><<<grid, kBlock, 0, c->stream>>>(
+            c->ch_row, c->rp_int, c->pk, (const double*)c->vch, (const double*)c->z,
+            (const double*)c->R, c->sc, alpha, c->orig, (double*)A, (double*)B);
+    else
+        k_attract<float, 1><<<grid, kBlock, 0, c->stream>>>(
+            c->ch_row, c->rp_int, c->pk, (const float*)c->vch, (const float*)c->z,
+            (const float*)c->R, c->sc, alpha, c->orig, (float*)A, (float*)B);
+    return hipGetLastError();
+}
+
+// The iteration's attraction row sums into c->A, on the second stream.
+static hipError_t run_attract_sums(pixelsne_ctx* c) {
+    const dim3 grid((unsigned)c->side_blocks);
+    if (fp64(c))
+        k_attract<double, 0><<<grid, kBlock, 0, c->side>>>(
+            c->ch_row, c->rp_int, c->pk, (const double*)c->vch, (const double*)c->z, nullptr,
+            c->sc, 0.0, c->orig, (double*)c->A, nullptr);
+    else
+        k_attract<float, 0><<<grid, kBlock, 0, c->side>>>(
+            c->ch_row, c->rp_int, c->pk, (const float*)c->vch, (const float*)c->z, nullptr,
+            c->sc, 0.0, c->orig, (float*)c->A, nullptr);
+    return hipGetLastError();
+}
+
+static hipError_t run_update(pixelsne_ctx* c) {
+    const StepParams p = step_params(c, 0.0);
+    const dim3 grid((unsigned)attract_blocks(c->n));
+    if (fp64(c))
+        k_update<double><<<grid, kBlock, 0, c->stream>>>(
+            (const double*)c->A, (const double*)c->z, (const double*)c->R, (double*)c->u,
+            (double*)c->g, (double*)c->zh, c->sc, p, c->n, c->mm_part);
+    else
+        k_update<float><<<grid, kBlock, 0, c->stream>>>(
+            (const float*)c->A, (const float*)c->z, (const float*)c->R, (float*)c->u,
+            (float*)c->g, (float*)c->zh, c->sc, p, c->n, c->mm_part);
     return hipGetLastError();
 }
 
@@ -1283,37 +1319,48 @@ hipError_t run_finalize(pixelsne_ctx* c, int advance) {
     return hipGetLastError();
 }
 
-hipError_t run_iteration_passes(pixelsne_ctx* c) {
+// One iteration.  After the snap pass the attraction's row sums are forked
+// onto the second stream (they need only the snapped positions and P) and
+// run while this stream sorts, builds the tree, walks it and reduces Z; the
+// update joins them.  EV, when given, receives the pass boundaries: [0..5]
+// before snap, sort, tree, traverse, Z and after Z on this stream, [6] after
+// the join, [7] after update and scaling, [8] after a scheduled renumbering,
+// [9] and [10] around the row sums on the second stream.
+static hipError_t iteration(pixelsne_ctx* c, hipEvent_t* ev) {
     hipError_t e;
+    auto mark = [&](int k, hipStream_t s) {
+        return ev ? hipEventRecord(ev[k], s) : hipSuccess;
+    };
+    if ((e = mark(0, c->stream)) != hipSuccess) return e;
     if ((e = run_snap(c)) != hipSuccess) return e;
+    if ((e = mark(1, c->stream)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = mark(9, c->side)) != hipSuccess) return e;
+    if ((e = run_attract_sums(c)) != hipSuccess) return e;
+    if ((e = mark(10, c->side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
+    if ((e = mark(2, c->stream)) != hipSuccess) return e;
     if ((e = run_tree(c)) != hipSuccess) return e;
+    if ((e = mark(3, c->stream)) != hipSuccess) return e;
     if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
+    if ((e = mark(4, c->stream)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;
-    if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
-    return run_finalize(c, 1);
+    if ((e = mark(5, c->stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess) return e;
+    if ((e = mark(6, c->stream)) != hipSuccess) return e;
+    if ((e = run_update(c)) != hipSuccess) return e;
+    if ((e = run_finalize(c, 1)) != hipSuccess) return e;
+    if (!ev) return hipSuccess;
+    if ((e = mark(7, c->stream)) != hipSuccess) return e;
+    if ((e = run_scheduled_reorder(c)) != hipSuccess) return e;
+    return mark(8, c->stream);
 }
 
-hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev) {
-    hipError_t e;
-    if ((e = hipEventRecord(ev[0], c->stream)) != hipSuccess) return e;
-    if ((e = run_snap(c)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[1], c->stream)) != hipSuccess) return e;
-    if ((e = run_sort(c)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[2], c->stream)) != hipSuccess) return e;
-    if ((e = run_tree(c)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[3], c->stream)) != hipSuccess) return e;
-    if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[4], c->stream)) != hipSuccess) return e;
-    if ((e = run_zsum(c)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[5], c->stream)) != hipSuccess) return e;
-    if ((e = run_attract(c, 0, 0.0, nullptr, nullptr)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[6], c->stream)) != hipSuccess) return e;
-    if ((e = run_finalize(c, 1)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev[7], c->stream)) != hipSuccess) return e;
-    if ((e = run_scheduled_reorder(c)) != hipSuccess) return e;
-    return hipEventRecord(ev[8], c->stream);
-}
+hipError_t run_iteration_passes(pixelsne_ctx* c) { return iteration(c, nullptr); }
+
+hipError_t run_iteration_timed(pixelsne_ctx* c, hipEvent_t* ev) { return iteration(c, ev); }
 
 hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, double sigma) {
     DevScalars h{};
