@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                               (uint64_t)(uint32_t)__builtin_amdgcn_readlane(st_mlo, sp);
         const uint32_t nsib = info & 0xFFu;
         const int level = (int)(info >> 8);
-        const bool act = (mask >> lane) & 1ull;
+        const bool act = __builtin_amdgcn_inverse_ballot_w64(mask);   // lane in mask
         const double diag2 = ldexp(bsum, 2 * (L - level));
         // the group's records (children are consecutive) in one batch of scalar loads
         Node grp[4];
