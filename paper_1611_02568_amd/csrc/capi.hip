@@ -166,6 +166,9 @@ void free_ctx(pixelsne_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    // the second stream's work is joined into the context's stream, except
+    // after an error between the fork and the join
+    if (c->side) (void)hipStreamSynchronize(c->side);
     for (hipGraphExec_t& g : c->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
