@@ -70,11 +70,11 @@ def tree_bytes(n, n_nodes, sb):
 
 
 def attract_bytes(n, nnz, sb):
-    """Algorithmic HBM bytes of attraction + update for one iteration: CSR
-    column (4 B) and value (sb) per nonzero, row pointer (8 B), z_i once and
-    z_j compulsory once (2 x 2 sb), R (2 sb), u and g read and written
-    (4 x 2 sb), zh written (2 sb)."""
-    return nnz * (4 + sb) + n * (8 + 8 * 2 * sb)
+    """Algorithmic HBM bytes of the attraction's row sums for one iteration:
+    CSR column word (4 B) and value (sb) per nonzero, row offset (8 B), z_i
+    once and z_j compulsory once (2 x 2 sb) and the row sum A_i written
+    (2 sb).  The optimiser step that follows is a kernel of its own."""
+    return nnz * (4 + sb) + n * (8 + 6 * sb)
 
 
 def run_gpu(args):
