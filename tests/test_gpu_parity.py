@@ -359,6 +359,27 @@ def test_reorder_does_not_change_the_trajectory(psne, small_problem):
     assert np.max(np.abs(ya - yb)) <= 1e-8 * np.max(np.abs(yb))
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_profiled_steps_match_plain_steps(psne, small_problem, prec):
+    """The pass-timed iteration (direct launches, events on both streams)
+    gives bit-identical states to the graph-replayed one, across
+    renumberings."""
+    X, P, _ = small_problem
+    y0 = torch.as_tensor(datagen.initial_embedding(2000, seed=9))
+    a = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=2)
+    b = psne.Context.from_P(*P, screen=512, Y_init=y0, precision=prec, reorder_every=2)
+    for k in (3, 5, 9):
+        a.step(k)
+        t = b.step_profiled(k)
+        assert t.iterations == k and t.attract_ms > 0 and t.traverse_ms > 0
+        ya, yb = a.get_Y(psne.FRAME_Y), b.get_Y(psne.FRAME_Y)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, yb), k
+        sa, sb = a.get_state(), b.get_state()
+        assert torch.equal(sa["u"], sb["u"]) and torch.equal(sa["g"], sb["g"])
+    assert a.stats().renumberings == b.stats().renumberings > 0
+
+
 @pytest.mark.parametrize("growth,want", [(2.0, [1, 4, 10, 22]),
                                          (1.0, [1, 4, 7, 10, 13, 16, 19, 22])])
 def test_reorder_schedule(psne, small_problem, growth, want):
