@@ -285,6 +285,44 @@ def time_to_kl(ctx_train, X_train, mix, args):
     return out
 
 
+def r_sweep(args):
+    """The benchmark's FP32 workload (1,000,000 x 128 mixture, perplexity 50)
+    at screen sizes 512 ... 65,536: wall time per iteration over `--steps`
+    iterations after `--warmup`, the exact-Z KL at the end, mean visited cells
+    per point and the number of cells.  At r = 65,536 (16 levels) nearly every
+    point has a leaf of its own, so the same kernels approximate a quadtree
+    split down to single points over the data's bounding box (the screen spans
+    it).  Setup (kNN, P) runs for every r and is not timed."""
+    import torch
+
+    from paper_1611_02568_amd import datagen, pixelsne
+
+    torch.cuda.set_device(0)
+    n = args.n
+    X, _, _ = datagen.zipf_mixture_1m(n=n)
+    y0 = torch.as_tensor(datagen.initial_embedding(n, seed=datagen.seed_for(2, 1)))
+    Xd = torch.from_numpy(X).cuda()
+    out = []
+    for r in (512, 1024, 2048, 4096, 8192, 16384, 65536):
+        ctx = pixelsne.Context.from_data(Xd, 50.0, r, Y_init=y0, precision=pixelsne.FP32)
+        ctx.step(args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.step_async(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        g = ctx.gradient(1.0)
+        row = {"r": r, "levels": ctx.stats().L, "ms_per_iter": ms, "kl": ctx.kl(),
+               "mean_visits": g["visits"].double().mean().item(),
+               "cells": ctx.stats().n_nodes}
+        log(f"[bench] r-sweep {json.dumps(row)}")
+        out.append(row)
+        del ctx, g
+    return out
+
+
 def time_to_kl_large(args):
     """The 5,000,000 x 100 workload with 1% outliers (perplexity 30, k 90, screen
     4096): a 100-1024-1024-2 network is trained on the converged plain run of a
@@ -439,11 +477,23 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="run only the 5M time-to-KL experiment and print its own JSON line")
     ap.add_argument("--large-n", type=int, default=5_000_000)
+    ap.add_argument("--r-sweep", action="store_true",
+                    help="run only the screen-size sweep (r = 512 ... 65,536) on the FP32 "
+                         "workload and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
                                    "note only (DESIGN.md), so --gpus must be 1"}))
         sys.exit(2)
+
+    if args.r_sweep:
+        res = r_sweep(args)
+        print(json.dumps({"metric": "ms per iteration and exact-Z KL after 1,000 iterations "
+                                    "against screen size r",
+                          "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+                          "data": "synthetic", "dtype": "f32", "steps": args.steps,
+                          "warmup": args.warmup, "result": res}), flush=True)
+        return
 
     if args.large:
         import torch

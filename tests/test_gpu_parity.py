@@ -82,7 +82,8 @@ def _tree_check(ctx, z64, r, exact_ties=True):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("gen,n,r", [("uniform", 20037, 512), ("clustered", 30011, 1024),
-                                     ("clustered", 777, 64), ("uniform", 2, 2)])
+                                     ("clustered", 777, 64), ("uniform", 2, 2),
+                                     ("clustered", 5003, 65536)])
 def test_tree_bit_exact(psne, prec, gen, n, r):
     dt = _state_dtype(prec)
     z = (datagen.uniform_pixels(n, r, seed=n, dtype=dt) if gen == "uniform"
@@ -163,6 +164,15 @@ def test_gradient_degenerate_single_pixel(psne, prec):
     X, _ = datagen.small_mixture(n=n, D=10, seed=10)
     P = oracle.build_P(X, 10.0)
     _grad_check(psne, P, z, np.array([0.02, 0.02]), r, prec, 0.5, alpha=1.0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_parity_largest_screen(psne, small_problem, prec):
+    """Screen 65,536 (16 levels, the deepest tree): nearly every point has a
+    leaf of its own."""
+    X, P, st = small_problem
+    z = st.z * (65536.0 / 512.0)
+    _grad_check(psne, P, z, st.s * (512.0 / 65536.0), 65536, prec, 0.5, alpha=1.0)
 
 
 def _skewed_P(n, seed):
