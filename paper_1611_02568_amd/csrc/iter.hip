@@ -72,17 +72,26 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t* __restrict__
 }
 
 // Exclusive scan of each row of a [rows][len] uint32 array in place (one block
-// per row, coalesced chunks of 256); the row totals go to tot[row].
+// per row; each thread takes 4 consecutive entries of a 1,024-entry piece, so
+// long rows need few barrier rounds); the row totals go to tot[row].
+constexpr int kScanItems = 4;
+
 __global__ __launch_bounds__(kBlock) void k_rows_scan(uint32_t* __restrict__ a, int64_t len,
                                                       uint32_t* __restrict__ tot) {
     __shared__ uint32_t ws[4];
     const int t = threadIdx.x, w = t >> 6, lane = lane_id();
     uint32_t* row = a + (int64_t)blockIdx.x * len;
     uint32_t carry = 0;
-    for (int64_t c0 = 0; c0 < len; c0 += kBlock) {
-        const int64_t i = c0 + t;
-        const uint32_t v = i < len ? row[i] : 0u;
-        uint32_t x = v;
+    for (int64_t c0 = 0; c0 < len; c0 += (int64_t)kScanItems * kBlock) {
+        const int64_t i0 = c0 + (int64_t)kScanItems * t;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            v[k] = i0 + k < len ? row[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t x = sum;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, kWave);
@@ -90,9 +99,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_scan(uint32_t* __restrict__ a, 
         }
         if (lane == kWave - 1) ws[w] = x;
         __syncthreads();
-        uint32_t pre = carry;
-        for (int q = 0; q < w; q++) pre += ws[q];
-        if (i < len) row[i] = pre + x - v;
+        uint32_t run = carry + x - sum;
+        for (int q = 0; q < w; q++) run += ws[q];
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            if (i0 + k < len) row[i0 + k] = run;
+            run += v[k];
+        }
         carry += ws[0] + ws[1] + ws[2] + ws[3];
         __syncthreads();
     }
