@@ -745,9 +745,9 @@ template <> __device__ __forceinline__ double stream_load<double>(__amdgpu_buffe
         (long long)__builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kStreamPolicy));
 }
 
-// runs of 64 nonzeros per wavefront in flight: as many as the registers allow
-// without costing occupancy (FP64 values and partial sums take twice the room)
-template <typename T> constexpr int kBatches = sizeof(T) == 4 ? 12 : 8;
+// runs of 64 nonzeros per wavefront in flight (measured with the sums on the
+// second stream beside the traversal: 8 beats 10, 12, 16, 20 and 24)
+template <typename T> constexpr int kBatches = 8;
 
 // One block per row chunk (grid-stride over the chunks).  Wavefront w takes
 // the runs w, w + 4, ... of the chunk's nonzeros (column order, each run of
