@@ -302,7 +302,9 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
     c->k = (int32_t)k;
     int32_t* idx = nullptr;
     double *d2 = nullptr, *Pc = nullptr, *val64 = nullptr;
-    auto cleanup = [&]() { hipFree(idx); hipFree(d2); hipFree(Pc); hipFree(val64); };
+    auto cleanup = [&]() {
+        (void)hipFree(idx); (void)hipFree(d2); (void)hipFree(Pc); (void)hipFree(val64);
+    };
     hipError_t e = hipMalloc(&idx, sizeof(int32_t) * n * k);
     if (e == hipSuccess) e = hipMalloc(&d2, sizeof(double) * n * k);
     if (e == hipSuccess) e = hipMalloc(&Pc, sizeof(double) * n * k);

@@ -164,7 +164,7 @@ psne_status pixelsne_neighborhood_precision(const pixelsne_ctx* c, const int32_t
         e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    hipFree(lo); hipFree(kd); hipFree(part);
+    (void)hipFree(lo); (void)hipFree(kd); (void)hipFree(part);
     if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "neighborhood_precision");
     for (int q = 0; q < nk; q++) {
         unsigned long long s = 0;

@@ -508,19 +508,18 @@ __device__ __forceinline__ double add_nc(double a, double b) {
 
 // Write a stack entry (four wave-uniform words, in scalar registers) into
 // lane `sel` of the four per-lane stack registers.  With one scalar operand
-// per vector instruction the lane select goes through m0, written here by a
-// scalar move; the s_nop adds two wait states before it is read.
+// per vector instruction the lane select goes through m0 (an input operand:
+// the compiler writes it with a scalar move); the s_nop adds two wait states
+// before it is read.
 __device__ __forceinline__ void push_entry(int& a, int& b, int& c, int& d, int va, int vb,
                                            int vc, int vd, int sel) {
-    asm("s_mov_b32 m0, %8\n\t"
-        "s_nop 1\n\t"
+    asm("s_nop 1\n\t"
         "v_writelane_b32 %0, %4, m0\n\t"
         "v_writelane_b32 %1, %5, m0\n\t"
         "v_writelane_b32 %2, %6, m0\n\t"
         "v_writelane_b32 %3, %7, m0"
         : "+v"(a), "+v"(b), "+v"(c), "+v"(d)
-        : "s"(va), "s"(vb), "s"(vc), "s"(vd), "s"(sel)
-        : "m0");
+        : "s"(va), "s"(vb), "s"(vc), "s"(vd), "{m0}"(sel));
 }
 
 template <typename T, bool COUNT>

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates_i8(const uint8_t* __rest
 // the first k.  flag[i] = 1 when the error bound of the FP32 pre-selection
 // does not prove that the k best are among the candidates.
 template <typename X>
-__global__ __launch_bounds__(256) void k_knn_rerank(const X* __restrict__ Xm, int64_t n, int D,
+__global__ __launch_bounds__(256) void k_knn_rerank(const X* __restrict__ Xm, int D,
                                                     int k, const uint64_t* __restrict__ cand,
                                                     const uint32_t* __restrict__ cand_cnt,
                                                     const uint32_t* __restrict__ cand_thr,
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(256) void k_sym_row(const int64_t* __restrict__ off
 }
 
 __global__ __launch_bounds__(256) void k_sym_write(const int64_t* __restrict__ off,
-                                                   const int64_t* __restrict__ rp, int64_t n,
+                                                   const int64_t* __restrict__ rp,
                                                    const uint32_t* __restrict__ tcol,
                                                    const double* __restrict__ tval,
                                                    uint32_t* __restrict__ col,
@@ -726,7 +726,8 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
     int32_t* nrm_i = nullptr;
     hipError_t e = hipSuccess;
     auto fail = [&](hipError_t x) {
-        hipFree(nrm); hipFree(cand); hipFree(ccnt); hipFree(flag); hipFree(cthr); hipFree(nrm_i);
+        (void)hipFree(nrm); (void)hipFree(cand); (void)hipFree(ccnt); (void)hipFree(flag);
+        (void)hipFree(cthr); (void)hipFree(nrm_i);
         return x;
     };
     if ((e = hipMalloc(&nrm, sizeof(float) * n)) != hipSuccess) return fail(e);
@@ -760,7 +761,7 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
         k_knn_candidates<X><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(Xm, n, D, nrm, kp,
                                                                              cand, ccnt, cthr);
     }
-    k_knn_rerank<X><<<dim3((unsigned)n), 256, 0, s>>>(Xm, n, D, k, cand, ccnt, cthr, nrm, nmax,
+    k_knn_rerank<X><<<dim3((unsigned)n), 256, 0, s>>>(Xm, D, k, cand, ccnt, cthr, nrm, nmax,
                                                       kExact ? 1 : 0, idx, d2, flag);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     std::vector<uint32_t> hf(n);
@@ -896,8 +897,8 @@ hipError_t projection_keys(const void* X, int64_t n, int32_t D, int32_t x_dtype,
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(proj);
-    hipFree(part);
+    (void)hipFree(proj);
+    (void)hipFree(part);
     return e;
 }
 
@@ -935,12 +936,13 @@ hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k
     double* val = nullptr;
     hipError_t e = hipSuccess;
     auto cleanup = [&]() {
-        hipFree(indeg); hipFree(fill); hipFree(tcol); hipFree(scol); hipFree(cap);
-        hipFree(off); hipFree(tmp); hipFree(ucnt); hipFree(tval); hipFree(sval);
+        for (void* q : {(void*)indeg, (void*)fill, (void*)tcol, (void*)scol, (void*)cap,
+                        (void*)off, (void*)tmp, (void*)ucnt, (void*)tval, (void*)sval})
+            (void)hipFree(q);
     };
     auto fail = [&](hipError_t x) {
         cleanup();
-        hipFree(rp); hipFree(col); hipFree(val);
+        (void)hipFree(rp); (void)hipFree(col); (void)hipFree(val);
         return x;
     };
     const int64_t nb = ceil_div(n + 1, 1024);
@@ -955,21 +957,21 @@ hipError_t symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t k
     if ((e = hipMalloc(&tval, 8 * 2 * m)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&scol, 4 * 2 * m)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&sval, 8 * 2 * m)) != hipSuccess) return fail(e);
-    hipMemsetAsync(indeg, 0, 4 * n, s);
-    hipMemsetAsync(fill, 0, 4 * n, s);
+    if ((e = hipMemsetAsync(indeg, 0, 4 * n, s)) != hipSuccess) return fail(e);
+    if ((e = hipMemsetAsync(fill, 0, 4 * n, s)) != hipSuccess) return fail(e);
     k_indeg<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, m, indeg);
     k_row_caps<<<dim3((unsigned)ceil_div(n + 1, 256)), 256, 0, s>>>(indeg, n, k, cap);
     if ((e = scan_i64_local(cap, n + 1, off, tmp, s)) != hipSuccess) return fail(e);
     k_sym_fill<<<dim3((unsigned)ceil_div(m, 256)), 256, 0, s>>>(idx, Pc, n, k, off, fill, tcol, tval);
     k_sym_row<<<dim3((unsigned)n), 256, 0, s>>>(off, tcol, tval, scol, sval, ucnt);
-    hipMemsetAsync(ucnt + n, 0, 8, s);
+    if ((e = hipMemsetAsync(ucnt + n, 0, 8, s)) != hipSuccess) return fail(e);
     if ((e = scan_i64_local(ucnt, n + 1, rp, tmp, s)) != hipSuccess) return fail(e);
     int64_t nnz = 0;
     if ((e = hipMemcpyAsync(&nnz, rp + n, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) return fail(e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&col, 4 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&val, 8 * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e);
-    k_sym_write<<<dim3((unsigned)n), 256, 0, s>>>(off, rp, n, tcol, tval, col, val,
+    k_sym_write<<<dim3((unsigned)n), 256, 0, s>>>(off, rp, tcol, tval, col, val,
                                                   1.0 / (2.0 * (double)n));
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
