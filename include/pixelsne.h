@@ -145,6 +145,10 @@ pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_pt
  * repulsion and Z (Eq. 5, 11, 12), sparse attraction (Eq. 5), gains/momentum
  * step, screen-driven scaling (Section 3.2).  Enqueues the work and then
  * synchronises once to check for non-finite values (PSNE_E_NUMERIC).
+ * The work is ordered on the context's stream (params.stream).  Inside an
+ * iteration the attraction's row sums run on a second, non-blocking stream
+ * that the context owns: it waits for the snap pass on the context's stream
+ * and the update waits for it, so callers see one stream-ordered iteration.
  */
 psne_status pixelsne_step(pixelsne_ctx* c, int32_t n_iter);
 
