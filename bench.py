@@ -9,8 +9,9 @@ Barnes-Hut repulsion, Z, sparse attraction + gains/momentum step, screen
 scaling) over all points; the one-time setup (kNN, perplexity, P) is timed
 separately.  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  See the design doc for the byte / flop counts used by the
-roofline numbers.
+Prints one JSON line.  The roofline figures use algorithmic counts: bytes
+the method must move (`attract_bytes`, `tree_bytes`) and flops per visited
+and per used cell for the traversal, over the measured pass times.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ if ROOT not in sys.path:
 METRIC = "points×iters/sec at n=1M (fp32 vs fp64) + time-to-KL within 1%, MLP init vs plain"
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the rate of FP64 and of
-# non-packed FP32 vector arithmetic (packed FP32 is disabled in this build)
+# non-packed FP32 vector arithmetic (the library is compiled without packed FP32)
 VALU_PEAK_TFLOPS = 78.6
 
 
@@ -482,8 +483,8 @@ def main():
                          "workload and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design "
-                                   "note only (DESIGN.md), so --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is "
+                                   "described, not implemented, so --gpus must be 1"}))
         sys.exit(2)
 
     if args.r_sweep:

@@ -47,7 +47,7 @@ typedef enum {
     PSNE_E_DEVICE = -3,       /* HIP runtime error; the context is unusable */
     PSNE_E_NUMERIC = -4,      /* a non-finite value appeared */
     PSNE_E_STATE = -5,        /* context unusable after an earlier device error */
-    PSNE_E_UNSUPPORTED = -6   /* valid request outside what this build supports */
+    PSNE_E_UNSUPPORTED = -6   /* valid request outside what the library supports */
 } psne_status;
 
 enum { PSNE_FP32 = 0, PSNE_FP64 = 1 };

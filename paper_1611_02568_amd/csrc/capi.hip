@@ -124,7 +124,7 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     }
     tb.max_nodes = mx;
     if (mx >= (int64_t)1 << 30) {
-        set_error("too many tree cells for this build");
+        set_error("too many tree cells: cell indices are limited to 2^30");
         return hipErrorNotSupported;
     }
     tb.sort_blocks = ceil_div(n, 2048);
