@@ -177,7 +177,9 @@ class Context:
     # --- construction -----------------------------------------------------
     @classmethod
     def from_data(cls, X: torch.Tensor, perplexity: float, screen: int, Y_init=None, **kw):
-        """pixelsne_init_ex on a device matrix X [n, D] (float32/float64/uint8)."""
+        """pixelsne_init_ex on a device matrix X [n, D] (float32/float64/uint8).
+        Keyword arguments set fields of pixelsne_params (include/pixelsne.h),
+        e.g. precision, theta, reorder_every, reorder_growth, graphs."""
         n, D = X.shape
         p = default_params(**kw)
         p.x_dtype = _X_TYPES[X.dtype]
@@ -191,7 +193,8 @@ class Context:
 
     @classmethod
     def from_P(cls, row_ptr, col, val, screen: int, Y_init=None, **kw):
-        """pixelsne_init_with_P on a device CSR P (int64 / int32 / float64)."""
+        """pixelsne_init_with_P on a device CSR P (int64 / int32 / float64).
+        Keyword arguments set fields of pixelsne_params as for from_data."""
         dev = torch.device("cuda")
         row_ptr = torch.as_tensor(row_ptr, dtype=torch.int64).to(dev).contiguous()
         col = torch.as_tensor(col, dtype=torch.int32).to(dev).contiguous()
