@@ -2,10 +2,10 @@
  * pixelsne.h -- C ABI of the MI355X (gfx950) PixelSNE library.
  *
  * PixelSNE (Kim et al., arXiv:1611.02568) is Barnes-Hut t-SNE whose quadtree
- * is aligned to the pixels of the output screen (Section 3.1): positions are
+ * is aligned to the pixels of the output screen (Section 4.1): positions are
  * kept in the pixel frame z with 0 <= z < r (Eq. 1-2), the tree has a fixed
  * depth L = log2 r with unit-pixel leaves, and after every gradient step the
- * positions are rescaled to fill the screen (Section 3.2) while a per-axis
+ * positions are rescaled to fill the screen (Section 4.2) while a per-axis
  * scale factor keeps q identical to the unscaled embedding (Eq. 12-13).
  *
  * Conventions for every function below
@@ -26,7 +26,7 @@
  *   PSNE_FP32: positions, velocities, gains, P values and the force
  *              arithmetic are FP32; the Z normaliser, the centre-of-mass sums
  *              and the Barnes-Hut opening test are FP64.
- *   PSNE_FP64: everything FP64 (the paper keeps z in double, Section 3.1).
+ *   PSNE_FP64: everything FP64 (the paper keeps z in double, Section 4.1).
  */
 #ifndef PIXELSNE_H
 #define PIXELSNE_H
@@ -52,7 +52,7 @@ typedef enum {
 
 enum { PSNE_FP32 = 0, PSNE_FP64 = 1 };
 /* Representative point of a cell: centre of mass of its members (Eq. 8), or
- * the geometric centre of the cell (Section 3.1, iteration-independent). */
+ * the geometric centre of the cell (Section 4.1, iteration-independent). */
 enum { PSNE_COM_MASS = 0, PSNE_COM_CELL_CENTER = 1 };
 /* Element type of the input matrix X. */
 enum { PSNE_X_F32 = 0, PSNE_X_F64 = 1, PSNE_X_U8 = 2 };
@@ -73,7 +73,7 @@ typedef struct {
     double mom0, mom1;        /* momentum before / after mom_switch [0.5, 0.8] */
     int32_t mom_switch;       /* [250] */
     double min_gain;          /* gain floor [0.01] */
-    double eps;               /* screen-scaling epsilon of Section 3.2 [1e-6] */
+    double eps;               /* screen-scaling epsilon of Section 4.2 [1e-6] */
     double init_sigma;        /* std of the generated initial embedding [1e-4] */
     uint64_t seed;            /* seed of the generated initial embedding [0] */
     int32_t precision;        /* PSNE_FP32 | PSNE_FP64 [PSNE_FP32] */
@@ -112,9 +112,9 @@ void pixelsne_default_params(pixelsne_params* p);
 /*
  * Create a context: brute-force kNN of the rows of X (k = floor(3u) nearest by
  * squared Euclidean distance, self excluded, ties to the smaller index),
- * per-row Gaussian calibration to perplexity u (Section 2.2), the symmetric
- * sparse P = (P_cond + P_cond^T) / 2n in CSR (Section 2.3), an initial
- * embedding and its first screen scaling (Section 3.2).
+ * per-row Gaussian calibration to perplexity u (Section 3.2), the symmetric
+ * sparse P = (P_cond + P_cond^T) / 2n in CSR (Section 3.3), an initial
+ * embedding and its first screen scaling (Section 4.2).
  *   X          device, [n][D], float32 (pixelsne_init) or params.x_dtype
  *   n          number of points, 2 <= n < 2^27, k <= n - 1
  *   D          input dimension >= 1
@@ -128,7 +128,7 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
                                int32_t screen_w, int32_t screen_h, const pixelsne_params* p);
 
 /*
- * Create a context from a caller-built P instead of X (Section 2.3 CSR):
+ * Create a context from a caller-built P instead of X (Section 3.3 CSR):
  *   row_ptr device int64 [n+1], col device int32 [nnz] (each row ascending,
  *   no diagonal), val device float64 [nnz] (sums to 1).  Copied into the
  *   context; offsets and column ranges are checked on the device (NULL with
@@ -141,9 +141,9 @@ pixelsne_ctx* pixelsne_init_with_P(int64_t n, int64_t nnz, const int64_t* row_pt
 
 /*
  * Run n_iter >= 0 optimisation iterations.  Each iteration: snap to pixels and
- * Morton keys (Eq. 1-2), sort, build the P-Quadtree (Section 3.1), Barnes-Hut
+ * Morton keys (Eq. 1-2), sort, build the P-Quadtree (Section 4.1), Barnes-Hut
  * repulsion and Z (Eq. 5, 11, 12), sparse attraction (Eq. 5), gains/momentum
- * step, screen-driven scaling (Section 3.2).  Enqueues the work and then
+ * step, screen-driven scaling (Section 4.2).  Enqueues the work and then
  * synchronises once to check for non-finite values (PSNE_E_NUMERIC).
  * The work is ordered on the context's stream (params.stream).  Inside an
  * iteration the attraction's row sums run on a second, non-blocking stream
@@ -291,7 +291,7 @@ psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, i
                          int32_t* idx, double* d2, void* stream);
 
 /*
- * Per-row Gaussian calibration (Section 2.2): for each row find b_i with
+ * Per-row Gaussian calibration (Section 3.2): for each row find b_i with
  * entropy of p_{j|i} = exp(-b_i (d2_ij - min_j d2_ij)) / sum equal to ln(u)
  * (|H - ln u| < 1e-5, at most 200 evaluations, start b = 1, double/halve
  * until bracketed, then bisect).

@@ -9,11 +9,11 @@ independent NumPy O(n^2) t-SNE used to pin it, and ``mlp.py`` is the FP64
 reference of the learned placement network.
 
 Functions follow the paper's sections:
-  knn / perplexity / symmetrize ......... Section 2.2-2.3 (sparse P)
-  morton / sorted_order / Tree .......... Eq. 1-2, Section 3.1 (P-Quadtree)
-  repulsion ............................. Eq. 5, 11, 12; Section 3.1 leaf stop
+  knn / perplexity / symmetrize ......... Section 3.2-3.3 (sparse P)
+  morton / sorted_order / Tree .......... Eq. 1-2, Section 4.1 (P-Quadtree)
+  repulsion ............................. Eq. 5, 11, 12; Section 4.1 leaf stop
   attraction ............................ Eq. 5, 12
-  normalize ............................. Section 3.2 (screen-driven scaling)
+  normalize ............................. Section 4.2 (screen-driven scaling)
   gradient / iterate .................... Eq. 5 in the pixel frame, Eq. 13
   kl .................................... Eq. 4 with exact Z
   neighborhood_precision ................ Eq. 14
@@ -103,7 +103,7 @@ def _f64(a, shape=None):
 
 
 # --------------------------------------------------------------------------
-# Section 2.2-2.3: sparse P
+# Section 3.2-3.3: sparse P
 # --------------------------------------------------------------------------
 def knn(X, k: int, rows=None):
     """k nearest neighbours (squared Euclidean, FP64, self excluded, ties to
@@ -166,7 +166,7 @@ def build_P(X, u: float, k: int | None = None):
 
 
 # --------------------------------------------------------------------------
-# Eq. 1-2 and Section 3.1: pixels, Morton order, P-Quadtree
+# Eq. 1-2 and Section 4.1: pixels, Morton order, P-Quadtree
 # --------------------------------------------------------------------------
 def morton(z, r: int):
     z = _f64(z)
@@ -238,7 +238,7 @@ def csum(v) -> float:
 
 
 # --------------------------------------------------------------------------
-# Eq. 5 / 12: attraction, gradient; Section 3.2: scaling; Eq. 4: KL
+# Eq. 5 / 12: attraction, gradient; Section 4.2: scaling; Eq. 4: KL
 # --------------------------------------------------------------------------
 def _csr(P):
     rp, col, val = P

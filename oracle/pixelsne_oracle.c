@@ -10,16 +10,16 @@
  *
  * Every step follows the paper's order and notation:
  *   - high-dimensional affinities P from a Gaussian kernel at a perplexity
- *     (Section 2.2) over k nearest neighbours (Section 2.3);
+ *     (Section 3.2) over k nearest neighbours (Section 3.3);
  *   - pixel coordinates z with 0 <= z < r (Eq. 1-2);
- *   - the pixel-aligned quadtree (P-Quadtree, Section 3.1): the root is the
+ *   - the pixel-aligned quadtree (P-Quadtree, Section 4.1): the root is the
  *     fixed screen, cells split down to unit pixels, each cell holds its
  *     boundary (Eq. 6), member count and centre of mass (Eq. 7-8);
  *   - Barnes-Hut repulsion by depth-first traversal with the opening
- *     criterion (Eq. 11), leaf stop (Section 3.1, "Bounded tree depth");
+ *     criterion (Eq. 11), leaf stop (Section 4.1, "Bounded tree depth");
  *   - q in terms of z with the scale factors beta (Eq. 12-13) and the
  *     gradient of Eq. 5 in the pixel frame;
- *   - screen-driven scaling (Section 3.2).
+ *   - screen-driven scaling (Section 4.2).
  *
  * Readings where the paper is silent or garbled (each one is listed in the
  * design notes): the opening test compares the cell diagonal with the
@@ -76,7 +76,7 @@ static inline double cs_get(const csum* a) { return a->s + a->c; }
 
 /* ------------------------------------------------------------------ */
 /* k nearest neighbours, brute force (replaces the VP / RP trees of     */
-/* Section 2.3 and 3.3).  Squared Euclidean distance in FP64; the       */
+/* Section 3.3 and 4.3).  Squared Euclidean distance in FP64; the       */
 /* point itself is excluded; ties go to the smaller index.              */
 /* ------------------------------------------------------------------ */
 static inline int knn_less(double da, int32_t ja, double db, int32_t jb) {
@@ -140,7 +140,7 @@ int orc_knn(const double* X, int64_t n, int32_t D, int32_t k, const int64_t* row
 }
 
 /* ------------------------------------------------------------------ */
-/* Perplexity calibration (Section 2.2): for each row find the          */
+/* Perplexity calibration (Section 3.2): for each row find the          */
 /* Gaussian precision b_i with entropy H(P_i) = ln(u) (natural log),   */
 /* p_{j|i} = exp(-b_i * delta_j) / sum, delta_j = d2_ij - min_j d2_ij   */
 /* (the shift cancels in the normalisation).  Bisection that doubles / */
@@ -246,7 +246,7 @@ int64_t orc_symmetrize(const int32_t* idx, const double* Pc, int64_t n, int32_t 
 }
 
 /* ------------------------------------------------------------------ */
-/* Pixel assignment and Morton keys (Eq. 1-2, Section 3.1).             */
+/* Pixel assignment and Morton keys (Eq. 1-2, Section 4.1).             */
 /* pixel = clamp(floor(z), 0, r - 1); key interleaves x in even bits    */
 /* and y in odd bits, so the child index is 2*ybit + xbit (NW, NE, SW,  */
 /* SE with y pointing down the screen).                                 */
@@ -283,7 +283,7 @@ int orc_morton(const double* z, int64_t n, int32_t r, uint32_t* key) {
 }
 
 /* ------------------------------------------------------------------ */
-/* P-Quadtree (Section 3.1).  Built by assigning each point, in index   */
+/* P-Quadtree (Section 4.1).  Built by assigning each point, in index   */
 /* order, from the root down to its unit pixel; every cell on the way   */
 /* counts the point and accumulates its coordinates for the centre of  */
 /* mass (Eq. 8).                                                        */
@@ -435,7 +435,7 @@ int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted
 /* of the other points (the cell centre in CELL_CENTER mode); skipped   */
 /* when m = 0.                                                          */
 /* com_mode 0: centre of mass (Eq. 8); 1: geometric cell centre         */
-/* (Section 3.1 "simply approximate the center of mass").               */
+/* (Section 4.1, which uses it in place of the centre of mass).        */
 /* visits counts every cell reached by the traversal.                    */
 /* ------------------------------------------------------------------ */
 /* rows == NULL: every point, outputs indexed by point; otherwise outputs are
@@ -526,7 +526,7 @@ double orc_sum(const double* v, int64_t n) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Attraction (Eq. 5 first term over the sparse P of Section 2.3):      */
+/* Attraction (Eq. 5 first term over the sparse P of Section 3.3):      */
 /* A_i = sum_{j in row i} p_ij w_ij (z_i - z_j), w from Eq. 12.         */
 /* ------------------------------------------------------------------ */
 int orc_attraction_rows(const double* z, int64_t n, const double* beta, const int64_t* row_ptr,
@@ -558,7 +558,7 @@ int orc_attraction(const double* z, int64_t n, const double* beta, const int64_t
 }
 
 /* ------------------------------------------------------------------ */
-/* Screen-driven scaling (Section 3.2): per axis                        */
+/* Screen-driven scaling (Section 4.2): per axis                        */
 /*   gamma_d = max_i zh_d - min_i zh_d + eps,                            */
 /*   z_d = r (zh_d - min_i zh_d) / gamma_d.                              */
 /* Writes z, gamma[2], zmin[2].                                          */

@@ -1,16 +1,18 @@
 // Per-iteration passes of PixelSNE on gfx950 (wave64).
 //
-//   snap        pending screen scaling (Section 3.2) + pixel (Eq. 1-2) + Morton key
+//   snap        pending screen scaling (Section 4.2) + pixel (Eq. 1-2) + Morton key
 //   sort        stable LSD radix sort of (key, index), 8-bit digits, LDS ranking
-//   tree        P-Quadtree (Section 3.1) as a linear tree: one node per occupied
+//   tree        P-Quadtree (Section 4.1) as a linear tree: one node per occupied
 //               (level, Morton prefix); counts and FP64 coordinate sums (Eq. 8)
 //               reduced bottom-up in one pass
 //   traverse    Barnes-Hut repulsion (Eq. 5, 11, 12): one wavefront walks the
 //               union of the interaction lists of 64 Morton-consecutive points,
 //               each stack entry carrying the mask of lanes still descending
 //   zsum        Z = sum_i Z_i in FP64, fixed order
-//   attract     sparse attraction over CSR P (Eq. 5) fused with the
-//               gains/momentum step and per-block min/max of the new positions
+//   attract     row sums of the sparse attraction over CSR P (Eq. 5), on a
+//               second stream beside sort, tree, traversal and Z
+//   update      B = alpha A - R / Z, gains/momentum step, new positions and
+//               per-block min/max of them
 //   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
 #include <math.h>
 
@@ -924,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const T* __restrict__ zh, int
     }
 }
 
-// screen-driven scaling: gamma = max - min + eps per axis (Section 3.2)
+// screen-driven scaling: gamma = max - min + eps per axis (Section 4.2)
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ mm_part,
                                                      int64_t m, DevScalars* __restrict__ sc,
                                                      int r, double eps, int advance) {

@@ -1,4 +1,4 @@
-// One-time setup on gfx950: the sparse affinity matrix P (paper Section 2.2-2.3).
+// One-time setup on gfx950: the sparse affinity matrix P (paper Section 3.2-3.3).
 //
 //   knn          brute-force k nearest neighbours.  Distance tiles come from
 //                FP32 MFMA (v_mfma_f32_32x32x2f32): d = |x|^2 + |y|^2 - 2 x.y,

@@ -6,7 +6,7 @@ path and the CPU oracle can both consume identical arrays while sharing no
 code that computes anything PixelSNE defines.
 
 The paper evaluates on MNIST, a facial-expression CNN feature set, two
-word2vec-averaged news corpora and Yelp (Section 4.1.1).  None of those are
+word2vec-averaged news corpora and Yelp (Section 5.1.1).  None of those are
 available here, so each workload below is a Gaussian-mixture stand-in with
 the shape (n, D), value type and cluster structure of the workload it
 replaces.  Random numbers the method itself draws (the initial embedding) are
