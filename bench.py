@@ -78,6 +78,68 @@ def attract_bytes(n, nnz, sb):
     return nnz * (4 + sb) + n * (8 + 6 * sb)
 
 
+def update_bytes(n, sb):
+    """Algorithmic HBM bytes of the optimiser step (its own kernel): read the
+    row sums A, z, R, u and g, write u, g and the new positions (8 x 2 sb per
+    point)."""
+    return n * 16 * sb
+
+
+def traverse_bytes(n, n_nodes, sb):
+    """Compulsory HBM bytes of the Barnes-Hut walk: sorted positions (2 sb),
+    the permutation and own-leaf index (8 B), R written (2 sb) and Z_i partials,
+    and each cell record read once (32 B + 16 B of sums)."""
+    return n * (4 * sb + 8) + n_nodes * 48
+
+
+def pass_metrics(n, nnz, sb, K, ms, pt, vis, used, n_nodes):
+    """Per-pass times and their roofline figures for one timed window."""
+    per = {k[:-3]: v / K for k, v in pt.items() if k.endswith("_ms")}
+    tree_ms = per["snap"] + per["sort"] + per["tree"]
+    tb = tree_bytes(n, n_nodes, sb)
+    ab = attract_bytes(n, nnz, sb)
+    ub = update_bytes(n, sb)
+    vb = traverse_bytes(n, n_nodes, sb)
+    flops = n * (8.0 * vis + 9.0 * used)
+    it_bytes = tb + ab + ub + vb
+    return {
+        "value": n * K / (ms / 1e3),
+        "ms_per_step": ms / K,
+        "pass_ms": per,
+        "mean_visits": vis,
+        "mean_used_cells": used,
+        "cells": n_nodes,
+        "tree_build": {"ms": tree_ms, "bytes": tb, "GBps": tb / (tree_ms * 1e6),
+                       "frac_hbm": tb / (tree_ms * 1e6) / HBM_PEAK_GBS},
+        "attract": {"ms": per["attract"], "bytes": ab, "GBps": ab / (per["attract"] * 1e6),
+                    "frac_hbm": ab / (per["attract"] * 1e6) / HBM_PEAK_GBS},
+        "traverse": {"ms": per["traverse"], "flops": flops,
+                     "TFLOPs": flops / (per["traverse"] * 1e9),
+                     "frac_valu": flops / (per["traverse"] * 1e9) / VALU_PEAK_TFLOPS},
+        # the whole iteration's algorithmic bytes over its wall time
+        "iteration": {"bytes": it_bytes, "GBps": it_bytes / (ms / K * 1e6),
+                      "frac_hbm": it_bytes / (ms / K * 1e6) / HBM_PEAK_GBS},
+    }
+
+
+def timed_window(ctx, K, profiled=True):
+    """K iterations between two events on the caller's stream; with
+    `profiled`, the library also records events between the passes."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    if profiled:
+        pt = ctx.step_profiled(K).as_dict()
+    else:
+        ctx.step_async(K)
+        pt = None
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), pt
+
+
 def run_gpu(args):
     import numpy as np
     import torch
@@ -115,58 +177,55 @@ def run_gpu(args):
     log(f"[bench] setup {setup_s:.2f} s, nnz {nnz} ({nnz / n:.1f} per row)")
 
     out = {}
+    K = args.steps
     for name, ctx, sb in (("fp32", ctx32, 4), ("fp64", ctx64, 8)):
         if name == "fp64" and args.no_fp64:
             continue
         ctx.step(args.warmup)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        # the timed region: K iterations, with HIP events recorded by the library
-        # on its stream (the caller's) between the passes of every iteration
-        e0.record()
+        saved = ctx.get_state() if args.reps > 1 else None
+        # the timed region: K iterations after the warm-up, with HIP events
+        # recorded by the library on its streams between the passes
+        ms, pt = timed_window(ctx, K, profiled=not args.plain_timing)
+        log(f"[bench] {name}: {K} iterations in {ms:.1f} ms")
         if args.plain_timing:
-            ctx.step_async(args.steps)
-        else:
-            pt = ctx.step_profiled(args.steps).as_dict()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        st = ctx.stats()
-        log(f"[bench] {name}: {args.steps} iterations in {ms:.1f} ms")
-        if args.plain_timing:
-            out[name] = {"value": n * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps}
+            out[name] = {"value": n * K / (ms / 1e3), "ms_per_step": ms / K}
             continue
-        g = ctx.gradient(1.0)
-        vis = g["visits"].double().mean().item()
-        used = g["used"].double().mean().item()
-        n_nodes = ctx.stats().n_nodes
-        K = args.steps
-        per = {k[:-3]: v / K for k, v in pt.items() if k.endswith("_ms")}
-        tree_ms = per["snap"] + per["sort"] + per["tree"]
-        att_ms = per["attract"]
-        tb = tree_bytes(n, n_nodes, sb)
-        ab = attract_bytes(n, nnz, sb)
-        flops = n * (8.0 * vis + 9.0 * used)
-        out[name] = {
-            "value": n * K / (ms / 1e3),
-            "ms_per_step": ms / K,
-            "pass_ms": per,
-            "iteration": st.iteration,
-            "mean_visits": vis,
-            "mean_used_cells": used,
-            "cells": n_nodes,
-            "tree_build": {"ms": tree_ms, "bytes": tb, "GBps": tb / (tree_ms * 1e6),
-                           "frac_hbm": tb / (tree_ms * 1e6) / HBM_PEAK_GBS},
-            "attract": {"ms": att_ms, "bytes": ab, "GBps": ab / (att_ms * 1e6),
-                        "frac_hbm": ab / (att_ms * 1e6) / HBM_PEAK_GBS},
-            "traverse": {"ms": per["traverse"], "flops": flops,
-                         "TFLOPs": flops / (per["traverse"] * 1e9)},
-        }
-        log(f"[bench] {name}: passes {json.dumps({k: round(v, 4) for k, v in per.items()})}")
+        # the statistics of the window's last tree
+        gr = ctx.gradient(1.0)
+        vis = gr["visits"].double().mean().item()
+        used = gr["used"].double().mean().item()
+        del gr
+        res = pass_metrics(n, nnz, sb, K, ms, pt, vis, used, ctx.stats().n_nodes)
+        res["iterations"] = [args.warmup + 1, args.warmup + K]
+        log(f"[bench] {name}: passes {json.dumps({k: round(v, 4) for k, v in res['pass_ms'].items()})}")
+        # repetitions: the same K iterations again from the saved state
+        reps = [ms / K]
+        for _ in range(args.reps - 1):
+            ctx.set_state(saved["z"], saved["s"], u=saved["u"], g=saved["g"],
+                          iteration=saved["iteration"])
+            ms_r, _ = timed_window(ctx, K)
+            reps.append(ms_r / K)
+        res["reps_ms_per_step"] = reps
+        res["ms_per_step_mean"] = float(np.mean(reps))
+        res["ms_per_step_sd"] = float(np.std(reps, ddof=1)) if len(reps) > 1 else 0.0
+        del saved
+        # steady state: iterations 981-1000 of the run (untimed iterations up to 980)
+        it = ctx.stats().iteration
+        if it < 980:
+            ctx.step(980 - it)
+        it0 = ctx.stats().iteration
+        ms_s, pt_s = timed_window(ctx, 20)
+        gr = ctx.gradient(1.0)
+        st = pass_metrics(n, nnz, sb, 20, ms_s, pt_s, gr["visits"].double().mean().item(),
+                          gr["used"].double().mean().item(), ctx.stats().n_nodes)
+        del gr
+        st["iterations"] = [it0 + 1, it0 + 20]
+        res["steady_state"] = st
+        log(f"[bench] {name}: steady state (iterations {it0 + 1}-{it0 + 20}) "
+            f"{st['ms_per_step']:.4f} ms/iteration")
+        out[name] = res
         if name == "fp32" and args.ttkl:
-            # the FP32 run has now done 1,020 iterations: a converged embedding
+            # the network learns from the converged run (>= 1,000 iterations)
             out["time_to_kl"] = time_to_kl(ctx, X, mix, args)
     if "fp64" in out:
         out["fp32_vs_fp64"] = compare_precisions(ctx32, ctx64)
@@ -198,29 +257,16 @@ def compare_precisions(ctx32, ctx64):
     return res
 
 
-def _refine_until(ctx, target, max_iters, t_start, sync):
-    """Step in chunks of 10 until KL <= target (KL evaluations not timed)."""
-    t_iter, it, ks = 0.0, 0, []
-    while it < max_iters:
-        t0 = time.perf_counter()
-        ctx.step(10)
-        sync()
-        t_iter += time.perf_counter() - t0
-        it += 10
-        k = ctx.kl()
-        ks.append(k)
-        if k <= target:
-            return {"iters": it, "seconds": t_start + t_iter, "kl": k}
-    return {"iters": None, "seconds": None, "kl": ks[-1] if ks else None}
-
-
 def time_to_kl(ctx_train, X_train, mix, args):
     """Learned placement: a 128-512-512-2 network trained (BF16 MFMA) on the
-    converged 1M run places 200,000 held-out draws of the same mixture; the
-    placed embedding is refined by ordinary iterations (no exaggeration,
-    momentum 0.8, fresh gains) until its KL is within 1% of 1,000 plain
-    iterations from a random start.  Times exclude the shared P setup and the
-    untimed KL checks; network training is reported separately."""
+    converged 1M run (>= 1,000 iterations) places 200,000 held-out draws of the
+    same mixture; the placed embedding is refined by ordinary iterations (no
+    exaggeration, momentum 0.8, fresh gains; pixelsne_refine) until its exact
+    KL is within 1% of 1,000 plain iterations from a random start, the plain
+    method continuing past the 100-iteration refinement budget (fallback).
+    Times are GPU times of the iterations (HIP events) plus the placement;
+    the shared P setup, the KL checks and the network training (reported on
+    its own) are excluded."""
     import torch
 
     from paper_1611_02568_amd import datagen, pixelsne
@@ -229,6 +275,8 @@ def time_to_kl(ctx_train, X_train, mix, args):
         torch.cuda.synchronize()
 
     r = 2048
+    tr = ctx_train.stats()
+    assert tr.iteration >= 1000, "the network must learn from a converged run"
     st = ctx_train.get_state()
     s_train = st["s"]
     Y01 = (st["z"] / r).float().contiguous()
@@ -245,19 +293,17 @@ def time_to_kl(ctx_train, X_train, mix, args):
     nh = Xh.shape[0]
     yh0 = torch.as_tensor(datagen.initial_embedding(nh, seed=datagen.seed_for(3, 1)))
     hi, _ = pixelsne.knn(Xhd, 30)                  # high-dimensional neighbours for Eq. (14)
-    out = {"heldout": nh, "train_points": X_train.shape[0], "mlp": "128-512-512-2 GELU, BF16 MFMA",
+    out = {"heldout": nh, "train_points": X_train.shape[0],
+           "train_run": {"iteration": tr.iteration, "kl": ctx_train.kl()},
+           "mlp": "128-512-512-2 GELU, BF16 MFMA",
            "mlp_epochs": args.mlp_epochs, "mlp_train_s": t_train, "mlp_last_epoch_loss": loss}
     for label, eta in (("eta200", 200.0), ("eta_n_over_12", nh / 12.0)):
         plain = pixelsne.Context.from_data(Xhd, 50.0, r, Y_init=yh0, precision=pixelsne.FP32, eta=eta)
-        sync()
-        t0 = time.perf_counter()
-        plain.step(1000)
-        sync()
-        t_plain = time.perf_counter() - t0
+        ms_plain, _ = timed_window(plain, 1000, profiled=False)
         kl_plain = plain.kl()
         prec_plain = plain.neighborhood_precision(hi, [1, 10, 30])
         del plain
-        res = {"plain_1000_s": t_plain, "plain_kl": kl_plain, "target_kl": 1.01 * kl_plain,
+        res = {"plain_1000_s": ms_plain / 1e3, "plain_kl": kl_plain, "target_kl": 1.01 * kl_plain,
                "plain_precision_k1_10_30": prec_plain}
         # placed scale: the training run's s, and s times sqrt(n_heldout / n_train)
         # (the embedding's extent grows with the number of points)
@@ -266,17 +312,17 @@ def time_to_kl(ctx_train, X_train, mix, args):
                                  ("refine_eta200_s_sqrt_n_ratio", 200.0, fsq),
                                  ("refine_eta_n_over_12", nh / 12.0, 1.0),
                                  ("refine_eta_n_over_12_s_sqrt_n_ratio", nh / 12.0, fsq)):
-            t0 = time.perf_counter()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             Yp = net.place(Xhd, r, (s_train[0] * fs, s_train[1] * fs))
+            e1.record()
             sync()
-            t_place = time.perf_counter() - t0
+            t_place = e0.elapsed_time(e1) / 1e3
             placed = pixelsne.Context.from_data(Xhd, 50.0, r, Y_init=Yp, precision=pixelsne.FP32,
                                                 exag_iters=0, mom_switch=0, eta=reta)
-            sync()
-            k0 = placed.kl()
-            rr = _refine_until(placed, 1.01 * kl_plain, 1000, t_place, sync)
-            rr["kl_placed"] = k0
-            rr["speedup"] = (t_plain / rr["seconds"]) if rr["seconds"] else None
+            rr = placed.refine(1.01 * kl_plain, check_every=10, refine_iters=100, max_iters=1000)
+            rr["seconds"] = t_place + rr["iter_ms"] / 1e3 if rr["reached"] else None
+            rr["speedup"] = (ms_plain / 1e3 / rr["seconds"]) if rr["seconds"] else None
             rr["precision_k1_10_30"] = placed.neighborhood_precision(hi, [1, 10, 30])
             rr["place_s"] = t_place
             res[rlabel] = rr
@@ -426,32 +472,77 @@ def time_to_kl_large(args):
     return out
 
 
-def cpu_baseline(sample_n: int, min_seconds: float):
-    """The oracle as it stands on this host's cores, on the first sample_n
-    points of the same mixture (rows are shuffled, so a random sample)."""
+def _oracle_rate(oracle, st, p, P, n, min_seconds, max_iters, chunk):
+    """points x iterations / s of oracle.iterate over at least min_seconds
+    (or max_iters iterations), in chunks."""
+    iters, t = 0, 0.0
+    while (t < min_seconds or iters == 0) and iters < max_iters:
+        k = min(chunk, max_iters - iters)
+        t0 = time.perf_counter()
+        oracle.iterate(st, p, P, k)
+        t += time.perf_counter() - t0
+        iters += k
+    return {"value": n * iters / t, "iterations": iters, "seconds": t}
+
+
+def cpu_baseline(args):
+    """The oracle as it stands (FP64, OpenMP over points) on this host's cores,
+    on bounded samples of the workloads:
+      * the benchmark's shape: 1,000,000 points, screen 2048, theta 0.5, a P of
+        the benchmark's row length (258 nonzeros per row; synthetic, from the
+        input generators, since the oracle cannot build P from a million
+        128-dimensional rows in minutes), the benchmark's initial embedding:
+        the first iterations on all cores (the headline figure) and on one
+        thread (the paper's own timings are single-threaded);
+      * the 2,000 x 50 mixture (its own P, perplexity 30, screen 512), all
+        cores and one thread;
+      * 70,000 points at the uint8 workload's row length (136, synthetic P),
+        screen 1024, all cores and one thread.
+    Setup is not timed."""
     import numpy as np
 
     import oracle
     from paper_1611_02568_amd import datagen
 
-    X, _, _ = datagen.zipf_mixture_1m(n=1_000_000)
-    Xs = X[:sample_n].astype(np.float64)
-    del X
-    P = oracle.build_P(Xs, 50.0, k=150)
-    st = oracle.State(datagen.initial_embedding(sample_n, seed=7), 2048)
+    cores = oracle.num_threads()
+    res = {}
+    # the benchmark's shape
+    n = 1_000_000
+    P = datagen.circulant_affinities(n, 129, seed=datagen.seed_for(2, 5))
+    y0 = datagen.initial_embedding(n, seed=datagen.seed_for(2, 1))
     p = oracle.params(2048)
-    oracle.iterate(st, p, P, 2)
-    iters, t = 0, 0.0
-    while t < min_seconds and iters < 1000:
-        t0 = time.perf_counter()
-        oracle.iterate(st, p, P, 10)
-        t += time.perf_counter() - t0
-        iters += 10
-    return {"value": sample_n * iters / t, "unit": "points*iters/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{sample_n} points of the same 1M x 128 mixture (its own brute-force "
-                      f"P, perplexity 50, k 150), screen 2048, theta 0.5, {iters} iterations "
-                      f"after 2 warm-up iterations, FP64, OpenMP; setup not timed"}
+    st = oracle.State(y0, 2048)
+    res["1m_all"] = _oracle_rate(oracle, st, p, P, n, args.cpu_seconds, 50, 2)
+    oracle.set_num_threads(1)
+    res["1m_single"] = _oracle_rate(oracle, oracle.State(y0, 2048), p, P, n, 0.0, 1, 1)
+    oracle.set_num_threads(cores)
+    del P, st
+    # the 2,000-point workload
+    X, _ = datagen.small_mixture(n=2000)
+    P = oracle.build_P(X, 30.0)
+    y0 = datagen.initial_embedding(2000, seed=datagen.seed_for(0, 1))
+    p = oracle.params(512)
+    res["2k_all"] = _oracle_rate(oracle, oracle.State(y0, 512), p, P, 2000, 2.0, 1000, 50)
+    oracle.set_num_threads(1)
+    res["2k_single"] = _oracle_rate(oracle, oracle.State(y0, 512), p, P, 2000, 2.0, 1000, 50)
+    oracle.set_num_threads(cores)
+    # 70,000 points, synthetic P of the uint8 workload's row length
+    P = datagen.circulant_affinities(70000, 68, seed=datagen.seed_for(1, 5))
+    y0 = datagen.initial_embedding(70000, seed=datagen.seed_for(1, 1))
+    p = oracle.params(1024)
+    res["70k_all"] = _oracle_rate(oracle, oracle.State(y0, 1024), p, P, 70000, 3.0, 200, 5)
+    oracle.set_num_threads(1)
+    res["70k_single"] = _oracle_rate(oracle, oracle.State(y0, 1024), p, P, 70000, 3.0, 20, 1)
+    oracle.set_num_threads(cores)
+    head = res["1m_all"]
+    return {"value": head["value"], "unit": "points*iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"iterations 1-{head['iterations']} of the 1,000,000-point workload from "
+                      "its initial embedding (screen 2048, theta 0.5), with a synthetic P of the "
+                      "benchmark's row length (258 per row) in place of the kNN P; FP64, "
+                      "OpenMP; setup not timed",
+            "single_thread": {"value": res["1m_single"]["value"], "cores": 1,
+                              "sample": "iteration 1 of the same"},
+            "workloads": res}
 
 
 def main():
@@ -462,8 +553,10 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="minimum all-core oracle time on the 1,000,000-point workload")
+    ap.add_argument("--reps", type=int, default=3,
+                    help="timed windows of the same iterations (from a saved state)")
     ap.add_argument("--no-ttkl", dest="ttkl", action="store_false",
                     help="skip the learned-placement time-to-KL comparison")
     ap.add_argument("--mlp-epochs", type=int, default=20)
@@ -539,7 +632,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline(args.cpu_sample, args.cpu_seconds)
+        cpu = cpu_baseline(args)
 
     line = {
         "metric": METRIC,
@@ -561,6 +654,14 @@ def main():
                    "theta": 0.5, "nnz": nnz},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "iteration_roofline": main32.get("iteration"),
+        "ms_per_step_reps": main32.get("reps_ms_per_step"),
+        "ms_per_step_sd": main32.get("ms_per_step_sd"),
+        "steady_state": main32.get("steady_state") and {
+            "iterations": main32["steady_state"]["iterations"],
+            "value": main32["steady_state"]["value"],
+            "ms_per_step": main32["steady_state"]["ms_per_step"],
+            "iteration_frac_hbm": main32["steady_state"]["iteration"]["frac_hbm"]},
         "fp64": res.get("fp64") and {"value": res["fp64"]["value"],
                                      "ms_per_step": res["fp64"]["ms_per_step"]},
         "setup_s": setup_s,

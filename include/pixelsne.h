@@ -255,6 +255,36 @@ psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_
 psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl);
 
 /*
+ * Refinement of a warm-started embedding with the plain method as fallback
+ * (the learned placement's last stage; an addition to the method).  Runs
+ * ordinary iterations (pixelsne_step) of the context in chunks of check_every
+ * and evaluates the exact-Z KL of Eq. (4) (pixelsne_kl) after each chunk;
+ * stops as soon as KL <= kl_target or after max_iters iterations.
+ * refine_iters is the refinement budget: when the target is not met within
+ * it, the iterations simply continue as the plain method's (fallback = 1).
+ * The context is typically created with Y_init from pixelsne_mlp_place,
+ * exag_iters = 0 and mom_switch = 0.
+ *   kl_target    finite; check_every >= 1; 0 <= refine_iters <= max_iters.
+ *   out          host; iterations run, whether the target was reached,
+ *                whether the fallback was taken, KL before and after, and the
+ *                GPU time of the iterations alone (HIP events; the KL checks
+ *                are not included).
+ * Synchronises after every chunk.  PSNE_E_NUMERIC on non-finite positions.
+ */
+typedef struct {
+    int32_t iterations;
+    int32_t reached;          /* 1: KL <= kl_target at return */
+    int32_t fallback;         /* 1: more than refine_iters iterations were needed, or the
+                                 target was not reached */
+    double kl_start, kl;      /* exact-Z KL before the first and after the last chunk */
+    double iter_ms;           /* GPU time of the iterations (ms) */
+} pixelsne_refine_result;
+
+psne_status pixelsne_refine(pixelsne_ctx* c, double kl_target, int32_t check_every,
+                            int32_t refine_iters, int32_t max_iters,
+                            pixelsne_refine_result* out);
+
+/*
  * The 32 nearest neighbours of every point in the current 2-D embedding
  * y = s * z (distance b1 dz1^2 + b2 dz2^2 with b = s^2, FP64, self excluded,
  * ties to the smaller index), by brute force on the GPU.
@@ -341,6 +371,11 @@ psne_status pixelsne_mlp_train(pixelsne_mlp* m, const float* X, const float* Y01
                                int32_t epochs, int32_t batch, float lr, double* last_epoch_loss);
 /* Y01_out device float32 [n][2] */
 psne_status pixelsne_mlp_forward(pixelsne_mlp* m, const float* X, int64_t n, float* Y01_out);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected with the
+ * network's own step count, which pixelsne_mlp_train advances too) with a
+ * caller-supplied gradient: device float32 [num_params] in the flat layout
+ * above, e.g. a gradient averaged over several devices. */
+psne_status pixelsne_mlp_adam_step(pixelsne_mlp* m, const float* grad, float lr);
 /* Initial embedding for pixelsne_init_ex's Y_init: y = clamp(MLP(x), 0,
  * 1 - 2^-24) * screen * s per axis, s = y units per pixel of the run the
  * network was trained on (host double[2]).  Y_out device float64 [n][2]. */

@@ -99,3 +99,28 @@ def standardize_stats(X):
     sd = X.std(0)
     sd[sd == 0] = 1.0
     return mu, sd
+
+
+def adam_step(theta, m1, m2, grad, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, 2015, Algorithm 1), step number t >= 1:
+    biased first and second moment estimates, their bias corrections by
+    1 - b^t, and theta - lr * m_hat / (sqrt(v_hat) + eps).  FP64.
+    Returns (theta, m1, m2)."""
+    g = np.asarray(grad, dtype=np.float64)
+    m1 = b1 * np.asarray(m1, dtype=np.float64) + (1.0 - b1) * g
+    m2 = b2 * np.asarray(m2, dtype=np.float64) + (1.0 - b2) * g * g
+    m_hat = m1 / (1.0 - b1 ** t)
+    v_hat = m2 / (1.0 - b2 ** t)
+    return np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m1, m2
+
+
+def place(theta, X, d, h1, h2, mean, inv_std, screen, s, bf=False):
+    """Initial embedding of new points from the network: the standardised
+    input (x - mean) * inv_std through the MLP, each output clamped to
+    [0, 1 - 2^-24] (the screen's half-open range), then scaled to the pixel
+    frame (times screen) and to y units (times s per axis).  FP64 [n, 2]."""
+    Xs = (np.asarray(X, dtype=np.float64) - np.asarray(mean, dtype=np.float64)) * \
+        np.asarray(inv_std, dtype=np.float64)
+    out, _ = forward(theta, Xs, d, h1, h2, bf)
+    top = 1.0 - 2.0 ** -24
+    return np.clip(out, 0.0, top) * float(screen) * np.asarray(s, dtype=np.float64)[None, :]

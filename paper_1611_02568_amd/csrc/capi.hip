@@ -587,6 +587,62 @@ psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl) {
     return PSNE_OK;
 }
 
+psne_status pixelsne_refine(pixelsne_ctx* c, double kl_target, int32_t check_every,
+                            int32_t refine_iters, int32_t max_iters,
+                            pixelsne_refine_result* out) {
+    if (!c || !out) return invalid("null argument");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (!isfinite(kl_target)) return invalid("kl_target must be finite");
+    if (check_every < 1) return invalid("check_every must be >= 1");
+    if (refine_iters < 0 || max_iters < refine_iters)
+        return invalid("0 <= refine_iters <= max_iters required");
+    memset(out, 0, sizeof(*out));
+    hipError_t e = run_kl(c, &out->kl_start);
+    if (e != hipSuccess) return device_error(c, e, "refine");
+    out->kl = out->kl_start;
+    out->reached = out->kl <= kl_target ? 1 : 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    int32_t done = 0;
+    double ms_total = 0.0;
+    psne_status st = PSNE_OK;
+    while (e == hipSuccess && !out->reached && done < max_iters) {
+        const int32_t chunk = check_every < max_iters - done ? check_every : max_iters - done;
+        e = hipEventRecord(ev[0], c->stream);
+        if (e != hipSuccess) break;
+        st = pixelsne_step_async(c, chunk);
+        if (st != PSNE_OK) break;
+        e = hipEventRecord(ev[1], c->stream);
+        int32_t bad = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad, &c->sc->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) break;
+        ms_total += ms;
+        done += chunk;
+        if (bad) {
+            set_error("non-finite positions");
+            st = PSNE_E_NUMERIC;
+            break;
+        }
+        e = run_kl(c, &out->kl);
+        out->reached = e == hipSuccess && out->kl <= kl_target ? 1 : 0;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    out->iterations = done;
+    out->iter_ms = ms_total;
+    // the refinement budget did not reach the target: the iterations past it
+    // (or all of max_iters) were the plain method's
+    out->fallback = (done > refine_iters || !out->reached) ? 1 : 0;
+    if (e != hipSuccess) return device_error(c, e, "refine");
+    return st;
+}
+
 psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
                          int32_t* idx, double* d2, void* stream) {
     if (n < 2 || n >= ((int64_t)1 << 31)) return invalid("n must be in [2, 2^31)");

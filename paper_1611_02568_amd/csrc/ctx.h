@@ -135,6 +135,7 @@ hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
 // exact-Z KL of the current state (synchronises)
 hipError_t run_kl(const pixelsne_ctx* c, double* kl);
+int64_t kl_scratch_doubles(int64_t n);
 // renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_scheduled_reorder(pixelsne_ctx* c);

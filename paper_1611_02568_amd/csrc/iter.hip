@@ -1164,6 +1164,30 @@ __global__ __launch_bounds__(kBlock) void k_kl_p(const int64_t* __restrict__ rp,
     }
 }
 
+// The KL's three sums from the block partials, in a fixed order: Z over the
+// nz partials of k_kl_z, then sum p (ln p - ln w) and sum p over the np pairs
+// of k_kl_p.  Writes out[0..2] = {Z, sum p (ln p - ln w), sum p}.
+__global__ __launch_bounds__(kBlock) void k_kl_final(const double* __restrict__ part, int64_t nz,
+                                                     int64_t np, double* __restrict__ out) {
+    __shared__ double red[3][kBlock];
+    double z = 0.0, a = 0.0, ps = 0.0;
+    for (int64_t i = threadIdx.x; i < nz; i += kBlock) z += part[i];
+    for (int64_t i = threadIdx.x; i < np; i += kBlock) {
+        a += part[nz + 2 * i];
+        ps += part[nz + 2 * i + 1];
+    }
+    red[0][threadIdx.x] = z;
+    red[1][threadIdx.x] = a;
+    red[2][threadIdx.x] = ps;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int q = 0; q < 3; q++) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
 inline int64_t attract_blocks(int64_t n) {
@@ -1447,12 +1471,17 @@ hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm
     return hipGetLastError();
 }
 
-hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
-    const int64_t nbz = ceil_div(c->n, kBlock);
-    const int64_t nbp = c->n / 4 < 4096 ? (c->n + 3) / 4 : 4096;
-    double* part = nullptr;
-    hipError_t e = hipMalloc((void**)&part, 8 * (size_t)(nbz + 2 * nbp));
-    if (e != hipSuccess) return e;
+// Blocks of the KL's two passes: one per 256 rows for the pair sums, at most
+// 4,096 (one wavefront per row, grid-stride) for the sums over P.
+static int64_t kl_blocks_z(int64_t n) { return ceil_div(n, kBlock); }
+static int64_t kl_blocks_p(int64_t n) { return n / 4 < 4096 ? (n + 3) / 4 : 4096; }
+
+int64_t kl_scratch_doubles(int64_t n) { return kl_blocks_z(n) + 2 * kl_blocks_p(n) + 3; }
+
+// The KL passes with their partial sums in `part` (kl_scratch_doubles(n)
+// doubles of device memory); synchronises the context's stream.
+static hipError_t run_kl_with(const pixelsne_ctx* c, double* part, double* kl) {
+    const int64_t nbz = kl_blocks_z(c->n), nbp = kl_blocks_p(c->n);
     if (fp64(c)) {
         k_kl_z<double><<<dim3((unsigned)nbz), kBlock, 0, c->stream>>>((const double*)c->zh, c->sc,
                                                                      c->n, c->r, part);
@@ -1466,21 +1495,24 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
             c->row_ptr, c->col, (const float*)c->val, c->inv, (const float*)c->zh, c->sc, c->n, c->r,
             part + nbz);
     }
-    std::vector<double> h(nbz + 2 * nbp);
-    e = hipGetLastError();
+    k_kl_final<<<1, kBlock, 0, c->stream>>>(part, nbz, nbp, part + nbz + 2 * nbp);
+    double h[3] = {0.0, 0.0, 0.0};
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h.data(), part, 8 * h.size(), hipMemcpyDeviceToHost, c->stream);
+        e = hipMemcpyAsync(h, part + nbz + 2 * nbp, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(part);
     if (e != hipSuccess) return e;
-    double Z = 0.0, a = 0.0, ps = 0.0;
-    for (int64_t b = 0; b < nbz; b++) Z += h[b];
-    for (int64_t b = 0; b < nbp; b++) {
-        a += h[nbz + 2 * b];
-        ps += h[nbz + 2 * b + 1];
-    }
-    *kl = a + ps * log(Z);
+    *kl = h[1] + h[2] * log(h[0]);
     return hipSuccess;
+}
+
+hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
+    double* part = nullptr;
+    hipError_t e = hipMalloc((void**)&part, 8 * (size_t)kl_scratch_doubles(c->n));
+    if (e != hipSuccess) return e;
+    e = run_kl_with(c, part, kl);
+    (void)hipFree(part);
+    return e;
 }
 
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64) {

@@ -538,6 +538,18 @@ hipError_t refresh_bf16(pixelsne_mlp* m) {
     return hipGetLastError();
 }
 
+// One Adam step (Kingma & Ba, 2015; beta 0.9 / 0.999, eps 1e-8, bias-corrected)
+// on the master weights with gradient g, then the bfloat16 weight copies.
+hipError_t adam_update(pixelsne_mlp* m, const float* g, float lr) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    m->step++;
+    const float c1 = 1.f - powf(b1, (float)m->step), c2 = 1.f - powf(b2, (float)m->step);
+    k_adam<<<g1(m->n_params), kT, 0, m->stream>>>(m->theta, g, m->m1, m->m2, m->n_params, lr, b1,
+                                                 b2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? refresh_bf16(m) : e;
+}
+
 psne_status mlp_error(hipError_t e, const char* where) {
     set_error(std::string(where) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? PSNE_E_NOMEM : PSNE_E_DEVICE;
@@ -704,7 +716,6 @@ psne_status pixelsne_mlp_train(pixelsne_mlp* m, const float* X, const float* Y01
     std::vector<uint32_t> ord(n);
     for (int64_t i = 0; i < n; i++) ord[i] = (uint32_t)i;
     std::mt19937_64 rng(m->seed ^ 0x5DEECE66DULL);
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     double epoch_loss = 0.0;
     for (int32_t ep = 0; ep < epochs; ep++) {
         std::shuffle(ord.begin(), ord.end(), rng);
@@ -719,13 +730,7 @@ psne_status pixelsne_mlp_train(pixelsne_mlp* m, const float* X, const float* Y01
                                                           m->mean, m->inv_std, m->xb, Y01, m->yb);
             e = forward_batch(m, (int)B, true);
             if (e == hipSuccess) e = backward_batch(m, (int)B);
-            if (e == hipSuccess) {
-                m->step++;
-                const float c1 = 1.f - powf(b1, (float)m->step), c2 = 1.f - powf(b2, (float)m->step);
-                k_adam<<<g1(m->n_params), kT, 0, m->stream>>>(m->theta, m->grad, m->m1, m->m2,
-                                                             m->n_params, lr, b1, b2, eps, c1, c2);
-                e = refresh_bf16(m);
-            }
+            if (e == hipSuccess) e = adam_update(m, m->grad, lr);
             if (e == hipSuccess && ep == epochs - 1) {
                 e = hipMemcpyAsync(lp.data(), m->lossbuf, 8 * ceil_div(B, 4), hipMemcpyDeviceToHost,
                                    m->stream);
@@ -739,6 +744,16 @@ psne_status pixelsne_mlp_train(pixelsne_mlp* m, const float* X, const float* Y01
     if (e != hipSuccess) return mlp_error(e, "mlp_train");
     if (last_epoch_loss) *last_epoch_loss = epoch_loss;
     return PSNE_OK;
+}
+
+psne_status pixelsne_mlp_adam_step(pixelsne_mlp* m, const float* grad, float lr) {
+    if (!m || !dev_ptr(grad) || !(lr > 0.f)) {
+        set_error("mlp_adam_step: bad arguments");
+        return PSNE_E_INVAL;
+    }
+    hipError_t e = adam_update(m, grad, lr);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    return e == hipSuccess ? PSNE_OK : mlp_error(e, "mlp_adam_step");
 }
 
 psne_status pixelsne_mlp_place(pixelsne_mlp* m, const float* X, int64_t n, int32_t screen,

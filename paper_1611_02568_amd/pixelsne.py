@@ -67,6 +67,14 @@ class PassTimes(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class RefineResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("reached", C.c_int32), ("fallback", C.c_int32),
+                ("kl_start", C.c_double), ("kl", C.c_double), ("iter_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # exported symbol -> (restype, argtypes)
 _vp, _i64, _i32, _d, _u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_uint64
 SIGNATURES = {
@@ -103,6 +111,8 @@ SIGNATURES = {
     "pixelsne_mlp_forward": (C.c_int, [_vp, _vp, _i64, _vp]),
     "pixelsne_mlp_place": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(C.c_double), _vp]),
     "pixelsne_kl": (C.c_int, [_vp, C.POINTER(C.c_double)]),
+    "pixelsne_refine": (C.c_int, [_vp, _d, _i32, _i32, _i32, C.POINTER(RefineResult)]),
+    "pixelsne_mlp_adam_step": (C.c_int, [_vp, _vp, C.c_float]),
     "pixelsne_knn2d": (C.c_int, [_vp, _vp]),
     "pixelsne_neighborhood_precision": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32,
                                                   C.POINTER(C.c_double)]),
@@ -292,6 +302,15 @@ class Context:
         _check(load().pixelsne_kl(self._h, C.byref(v)))
         return v.value
 
+    def refine(self, kl_target: float, check_every: int = 10, refine_iters: int = 100,
+               max_iters: int = 1000) -> dict:
+        """pixelsne_refine: iterate until the exact KL <= kl_target; the plain
+        method continues past refine_iters (fallback)."""
+        res = RefineResult()
+        _check(load().pixelsne_refine(self._h, float(kl_target), int(check_every),
+                                      int(refine_iters), int(max_iters), C.byref(res)))
+        return res.as_dict()
+
     def knn2d(self) -> torch.Tensor:
         """The 32 nearest neighbours of each point in the embedding, int32 [n, 32]."""
         idx = torch.empty((self.n, 32), dtype=torch.int32, device="cuda")
@@ -397,6 +416,11 @@ class MLP:
         _check(load().pixelsne_mlp_train(self._h, _ptr(X), _ptr(Y01), X.shape[0], int(epochs),
                                          int(batch), float(lr), C.byref(loss)))
         return loss.value
+
+    def adam_step(self, grad, lr: float = 1e-3):
+        """One Adam step with a caller-supplied flat FP32 gradient."""
+        g = torch.as_tensor(grad, dtype=torch.float32).cuda().contiguous()
+        _check(load().pixelsne_mlp_adam_step(self._h, _ptr(g), float(lr)))
 
     def forward(self, X: torch.Tensor) -> torch.Tensor:
         X = X.contiguous()

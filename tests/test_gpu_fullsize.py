@@ -3,7 +3,7 @@
 The oracle cannot build P for a million points in test time, so at full size
 the checks are sampled or take a synthetic P of the same size and row length:
 
-* 1,000,000 x 128 mixture: kNN of sampled rows exact; P of sampled rows
+* 1,000,000 x 128 mixture: kNN of 1,000 sampled rows exact; P of 4 rows
   against the oracle's conditional probabilities of those rows and of their
   neighbours (FP64 context, rel 1e-9), symmetric pairs equal; P sums to 1.
 * 1,000,000 points, 258 nonzeros per row, screen 2048 (the benchmark's P
@@ -40,9 +40,17 @@ def test_knn_and_P_sampled_1m(psne):
                                  Y_init=torch.as_tensor(datagen.initial_embedding(n, seed=3)))
     rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
     del ctx
+    ctx_knn = tuple(t.cpu().numpy() for t in psne.knn(torch.from_numpy(X).cuda(), k))
     assert rp[-1] == col.size and abs(val.sum() - 1.0) < 1e-9
-    rows = np.random.default_rng(12).choice(n, 4, replace=False)
-    oi, od = oracle.knn(X, k, rows=rows)
+    # kNN of 1,000 sampled rows exact; P checked on 4 of them (each needs the
+    # oracle's neighbour lists of all its columns as well)
+    rows_knn = np.random.default_rng(12).choice(n, 1000, replace=False)
+    ki, kd = oracle.knn(X, k, rows=rows_knn)
+    nbr = ctx_knn[0][rows_knn]
+    assert np.array_equal(nbr, ki)
+    np.testing.assert_allclose(ctx_knn[1][rows_knn], kd, rtol=1e-13, atol=0)
+    rows = rows_knn[:4]
+    oi, od = ki[:4], kd[:4]
     # the oracle's conditional rows for the sampled points and all their columns
     cols = np.unique(np.concatenate([col[rp[i]:rp[i + 1]] for i in rows]))
     ci, cd = oracle.knn(X, k, rows=cols)

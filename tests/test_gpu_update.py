@@ -1,0 +1,122 @@
+"""The optimiser step against the oracle, element by element (Eq. 12-13 and
+Section 4.2; the step rule itself is the Barnes-Hut-SNE convention the paper
+leaves unprinted: gains +0.2 / x0.8 floored at 0.01, momentum 0.5 -> 0.8 and
+exaggeration 12 until iteration 250).
+
+The same state (z, u, g, s, t) goes into both sides, k iterations run, and the
+new state is compared: t = 247 with k = 5 crosses the end of the early
+exaggeration and the momentum switch at 250.  Internal renumbering (every 2
+iterations) and graph replay change only the GPU's memory order.
+
+Bars.  FP64 path: positions and velocities to 1e-9 relative to their ranges,
+gains bit-exact, scale s to 1e-12.  FP32 path (z, u, g stored in FP32, B to
+1e-4 relative): a gain decision differs only where sign(B_i) is inside B's
+FP32 error, allowed for at most 0.5% of the entries (equal decisions agree to
+FP32 rounding); elsewhere u within 1e-4 relative
+(norm-wise, times the steps taken), z within 2^-20 r per step plus the u
+difference, s within 1e-6.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1611_02568_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+R = 512
+
+
+@pytest.fixture(scope="module")
+def psne():
+    from paper_1611_02568_amd import pixelsne
+    pixelsne.load()
+    assert torch.cuda.is_available()
+    return pixelsne
+
+
+@pytest.fixture(scope="module")
+def near_switch():
+    X, _ = datagen.small_mixture(n=2000)
+    P = oracle.build_P(X, 30.0)
+    st = oracle.State(datagen.initial_embedding(2000, seed=datagen.seed_for(0, 1)), R)
+    oracle.iterate(st, oracle.params(R), P, 247)
+    return P, st
+
+
+def _rounded_state(st, dt):
+    """The oracle state rounded to the GPU's state type (z kept below r)."""
+    o = copy.deepcopy(st)
+    o.z = np.minimum(st.z.astype(dt), np.nextafter(dt(R), dt(0))).astype(np.float64)
+    o.u = st.u.astype(dt).astype(np.float64)
+    o.g = st.g.astype(dt).astype(np.float64)
+    return o
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 5])
+@pytest.mark.parametrize("graphs,reorder", [(1, 0), (0, 2), (1, 2)])
+def test_update_step_parity(psne, near_switch, prec, k, graphs, reorder):
+    P, st = near_switch
+    dt = np.float64 if prec == 1 else np.float32
+    o = _rounded_state(st, dt)
+    assert o.t == 247
+    ctx = psne.Context.from_P(*P, screen=R, precision=prec, graphs=graphs,
+                              reorder_every=reorder, reorder_growth=1.0,
+                              Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=5)))
+    ctx.set_state(o.z.astype(dt), o.s, u=o.u.astype(dt), g=o.g.astype(dt), iteration=o.t)
+    ctx.step(k)
+    got = ctx.get_state()
+    oracle.iterate(o, oracle.params(R), P, k)
+    assert got["iteration"] == o.t == 247 + k
+    z = got["z"].double().cpu().numpy()
+    u = got["u"].double().cpu().numpy()
+    g = got["g"].double().cpu().numpy()
+    s = np.array(got["s"])
+    if prec == 1:
+        assert np.array_equal(g, o.g)
+        assert np.max(np.abs(z - o.z)) <= 1e-9 * R
+        assert np.max(np.abs(u - o.u)) <= 1e-9 * np.max(np.abs(o.u))
+        np.testing.assert_allclose(s, o.s, rtol=1e-12)
+    else:
+        # a different gain decision moves g by at least 0.2 g_min; equal
+        # decisions leave FP32 rounding of a few operations
+        same = np.abs(g - o.g) <= k * 2.0 ** -21 * o.g
+        assert same.mean() >= 0.995, same.mean()
+        assert np.all(same | (np.abs(g - o.g) >= 0.002))
+        rows = same.all(axis=1)
+        du = np.linalg.norm(u[rows] - o.u[rows]) / np.linalg.norm(o.u[rows])
+        assert du <= 1e-4 * k, du
+        dz = np.abs(z[rows] - o.z[rows])
+        assert np.max(dz) <= k * 2.0 ** -20 * R + np.max(np.abs(u[rows] - o.u[rows])), np.max(dz)
+        np.testing.assert_allclose(s, o.s, rtol=1e-6)
+    # the normalisation holds on both sides: min 0 and the top pixel r - 1
+    assert np.all(z.min(0) == 0.0) and np.all(np.floor(z.max(0)) == R - 1)
+    assert np.all(np.floor(o.z.max(0)) == R - 1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update_from_zero_velocity(psne, near_switch, prec):
+    """With u = 0 (sign 0) every gain grows by 0.2 in the first step and the
+    step is -eta g B exactly as the oracle takes it (t = 0: exaggeration 12,
+    momentum 0.5)."""
+    P, st = near_switch
+    dt = np.float64 if prec == 1 else np.float32
+    o = _rounded_state(st, dt)
+    o.u[:] = 0.0
+    o.g[:] = 1.0
+    o.t = 0
+    ctx = psne.Context.from_P(*P, screen=R, precision=prec,
+                              Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=5)))
+    ctx.set_state(o.z.astype(dt), o.s, iteration=0)
+    ctx.step(1)
+    got = ctx.get_state()
+    oracle.iterate(o, oracle.params(R), P, 1)
+    g = got["g"].double().cpu().numpy()
+    assert np.all(g == dt(1.2)) and np.all(o.g == 1.2)
+    u = got["u"].double().cpu().numpy()
+    tol = 1e-9 if prec == 1 else 1e-4
+    assert np.linalg.norm(u - o.u) <= tol * np.linalg.norm(o.u)
