@@ -255,6 +255,19 @@ psne_status pixelsne_export_P(const pixelsne_ctx* c, int64_t* nnz, int64_t* row_
 psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl);
 
 /*
+ * pixelsne_kl for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid hipMalloc between steps): the same kernels and the
+ * same result, with the per-block partial sums in a fixed array of the library
+ * (73,731 doubles, 576 KiB, one copy per device, held until the process ends)
+ * instead of a buffer allocated for the call.  No device or host allocation.
+ * Supports n <= 2^24 (PSNE_E_UNSUPPORTED above).  The context's device must be
+ * current.  All calls on one device share the array, so calls that overlap on
+ * a device (several host threads, or several streams) race; calls in
+ * sequence do not.  *kl host double.  Synchronises the context's stream.
+ */
+psne_status pixelsne_kl_noalloc(const pixelsne_ctx* c, double* kl);
+
+/*
  * Refinement of a warm-started embedding with the plain method as fallback
  * (the learned placement's last stage; an addition to the method).  Runs
  * ordinary iterations (pixelsne_step) of the context in chunks of check_every

@@ -239,6 +239,11 @@ psne_status finish_init(pixelsne_ctx* c) {
     if (c->prm.Y_init && !is_device_ptr(c->prm.Y_init)) return invalid("Y_init must be a device pointer");
     // the initial state resets the device scalars; the chunked P (whose chunk
     // count lives there) is built after it
+    // the device address of the library's fixed KL array on this device
+    // (pixelsne_kl_noalloc), resolved once per device while it is current
+    double* kl_fixed = nullptr;
+    e = kl_scratch_address(c->device, &kl_fixed);
+    if (e != hipSuccess) return device_error(c, e, "resolving the fixed KL buffer");
     e = run_init_state(c, c->prm.Y_init, c->prm.seed, c->prm.init_sigma);
     if (e == hipSuccess) e = run_identity_order(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -584,6 +589,22 @@ psne_status pixelsne_kl(const pixelsne_ctx* c, double* kl) {
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
     hipError_t e = run_kl(c, kl);
     if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "kl");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_kl_noalloc(const pixelsne_ctx* c, double* kl) {
+    if (!c || !kl) return invalid("null argument");
+    if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
+    if (kl_scratch_doubles(c->n) > kKlScratchDoubles) {
+        set_error("pixelsne_kl_noalloc supports n <= 2^24 (its fixed buffer holds " +
+                  std::to_string(kKlScratchDoubles) + " partial sums); use pixelsne_kl");
+        return PSNE_E_UNSUPPORTED;
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != c->device) return invalid("the context's device must be current");
+    if (e == hipSuccess) e = run_kl_static(c, kl);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "kl_noalloc");
     return PSNE_OK;
 }
 

@@ -133,9 +133,17 @@ hipError_t run_get_state(const pixelsne_ctx* c, void* z, void* u, void* g);
 hipError_t run_export_tree(const pixelsne_ctx* c, uint32_t* keys, uint32_t* perm,
                            uint32_t* prefix, uint32_t* count, double* sum);
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64);
-// exact-Z KL of the current state (synchronises)
+// exact-Z KL of the current state (synchronises); partial sums in a
+// hipMalloc'd buffer, or (run_kl_static) in the library's fixed per-device
+// array of kKlScratchDoubles doubles, for n up to kKlStaticMaxN
 hipError_t run_kl(const pixelsne_ctx* c, double* kl);
+hipError_t run_kl_static(const pixelsne_ctx* c, double* kl);
+constexpr int64_t kKlStaticMaxN = (int64_t)1 << 24;
+constexpr int64_t kKlScratchDoubles = kKlStaticMaxN / 256 + 2 * 4096 + 3;
 int64_t kl_scratch_doubles(int64_t n);
+// device address of the fixed KL array on `device` (which must be current the
+// first time; resolved once per device)
+hipError_t kl_scratch_address(int device, double** out);
 // renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_scheduled_reorder(pixelsne_ctx* c);

@@ -16,6 +16,7 @@
 //   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
 #include <math.h>
 
+#include <mutex>
 #include <vector>
 
 #include "ctx.h"
@@ -1513,6 +1514,44 @@ hipError_t run_kl(const pixelsne_ctx* c, double* kl) {
     e = run_kl_with(c, part, kl);
     (void)hipFree(part);
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// The KL without device allocation: its partial sums live in a fixed array
+// of the library, one copy per device, held until the process ends.  Host
+// code must never pass the array's name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol): kl_scratch_address() resolves the
+// device address once per device and every use goes through it.  Calls that
+// overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kKlScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t kl_scratch_address(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // resolve with the device current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t run_kl_static(const pixelsne_ctx* c, double* kl) {
+    if (kl_scratch_doubles(c->n) > kKlScratchDoubles) return hipErrorInvalidValue;
+    double* part = nullptr;
+    hipError_t e = kl_scratch_address(c->device, &part);
+    if (e != hipSuccess) return e;
+    return run_kl_with(c, part, kl);
 }
 
 hipError_t run_convert_val(pixelsne_ctx* c, const double* val64) {

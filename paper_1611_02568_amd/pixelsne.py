@@ -112,6 +112,7 @@ SIGNATURES = {
     "pixelsne_mlp_place": (C.c_int, [_vp, _vp, _i64, _i32, C.POINTER(C.c_double), _vp]),
     "pixelsne_kl": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "pixelsne_refine": (C.c_int, [_vp, _d, _i32, _i32, _i32, C.POINTER(RefineResult)]),
+    "pixelsne_kl_noalloc": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "pixelsne_mlp_adam_step": (C.c_int, [_vp, _vp, C.c_float]),
     "pixelsne_knn2d": (C.c_int, [_vp, _vp]),
     "pixelsne_neighborhood_precision": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32,
@@ -300,6 +301,12 @@ class Context:
         """KL(P || Q) with the exact normaliser (O(n^2) on the GPU)."""
         v = C.c_double()
         _check(load().pixelsne_kl(self._h, C.byref(v)))
+        return v.value
+
+    def kl_noalloc(self) -> float:
+        """pixelsne_kl_noalloc: the same KL with no device allocation."""
+        v = C.c_double()
+        _check(load().pixelsne_kl_noalloc(self._h, C.byref(v)))
         return v.value
 
     def refine(self, kl_target: float, check_every: int = 10, refine_iters: int = 100,
