@@ -160,14 +160,14 @@ def run_gpu(args):
         log("[bench] setup (kNN, perplexity, P) for the FP32 path")
         ctx64 = None
         ctx32 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP32,
-                                           graphs=g)
+                                           graphs=g, opening_fp64=args.opening_fp64)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
     else:
         # the same setup for each path (identical P and initial numbering)
         log("[bench] setup (kNN, perplexity, P), FP32 and FP64 paths")
         ctx32 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP32,
-                                           graphs=g)
+                                           graphs=g, opening_fp64=args.opening_fp64)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         ctx64 = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0, precision=pixelsne.FP64,
@@ -563,6 +563,8 @@ def main():
     ap.add_argument("--heldout", type=int, default=200_000)
     ap.add_argument("--plain-timing", action="store_true",
                     help="time the region without per-pass events (for counter runs)")
+    ap.add_argument("--opening-fp64", type=int, default=0, choices=(0, 1),
+                    help="FP32 path: run the opening test and distances in FP64")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch kernels one by one outside the timed region too")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -649,7 +651,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.n:,} x 128 fp32 Zipf(1.1) 100-component Gaussian mixture, "
                                "perplexity 50, k 150, screen 2048x2048, theta 0.5, FP32 path "
-                               "(FP64 Z, cell sums and opening test)",
+                               + ("(FP64 Z, cell sums and opening test)" if args.opening_fp64
+                                  else "(FP32 opening test and forces, FP64 Z and cell sums)"),
                    "n": args.n, "D": 128, "perplexity": 50, "k": 150, "screen": 2048,
                    "theta": 0.5, "nnz": nnz},
         "roofline": roof,

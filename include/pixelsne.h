@@ -23,9 +23,10 @@
  *   - A context must be used from one host thread at a time.
  *
  * Precision paths (params.precision)
- *   PSNE_FP32: positions, velocities, gains, P values and the force
- *              arithmetic are FP32; the Z normaliser, the centre-of-mass sums
- *              and the Barnes-Hut opening test are FP64.
+ *   PSNE_FP32: positions, velocities, gains, P values, the force
+ *              arithmetic and the Barnes-Hut opening test are FP32 (the test
+ *              optionally FP64, params.opening_fp64); the Z normaliser and
+ *              the centre-of-mass sums are FP64.
  *   PSNE_FP64: everything FP64 (the paper keeps z in double, Section 4.1).
  */
 #ifndef PIXELSNE_H
@@ -104,6 +105,12 @@ typedef struct {
                                  moves less and less per iteration as the embedding
                                  settles, so the locality a renumbering restores decays
                                  more slowly the later it is made. */
+    int32_t opening_fp64;     /* PSNE_FP32 path only.  0: the Barnes-Hut opening test of
+                                 Eq. 11 and the distances run in FP32, operands rounded to
+                                 FP32 and each operation rounded in the order
+                                 (w*w)*(b1+b2) < th2*((b1*dx)*dx + (b2*dy)*dy), no fused
+                                 multiply-add [0].  1: the test and the distances in FP64
+                                 (the FP64 path always does this). */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -205,7 +212,10 @@ psne_status pixelsne_get_stats(const pixelsne_ctx* c, pixelsne_stats* out);
  * Replace the optimiser state.  z, u, g: device [n][2] of the state type
  * (float32 for PSNE_FP32, float64 for PSNE_FP64), z in the pixel frame
  * (0 <= z < r), u the velocity in that frame, g the gains; u or g NULL =>
- * zeros / ones.  s: host double[2].  Asynchronous copies.
+ * zeros / ones.  s: host double[2].  The iteration counter becomes
+ * `iteration`, which sets the schedule (exaggeration, momentum) and the
+ * internal renumbering schedule as they stand after that many iterations.
+ * Synchronises.
  */
 psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, const void* g,
                                const double* s, int32_t iteration);

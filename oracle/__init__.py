@@ -64,8 +64,8 @@ def _load():
     lib.orc_tree_level.argtypes = [vp, C.c_int32, _u32p, _i64p, _dp]
     lib.orc_sorted_order.argtypes = [_dp, C.c_int64, C.c_int32, _u32p, _i64p]
     lib.orc_repulsion.argtypes = [vp, _dp, _dp, C.c_double, C.c_int32, _dp, _dp, _i64p]
-    lib.orc_repulsion_rows.argtypes = [vp, _dp, _dp, C.c_double, C.c_int32, vp, C.c_int64,
-                                       _dp, _dp, _i64p]
+    lib.orc_repulsion_rows.argtypes = [vp, _dp, _dp, C.c_double, C.c_int32, C.c_int32, vp,
+                                       C.c_int64, _dp, _dp, _i64p]
     lib.orc_attraction_rows.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp, vp, C.c_int64,
                                         _dp]
     lib.orc_sum.restype = C.c_double
@@ -73,7 +73,8 @@ def _load():
     lib.orc_attraction.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp, _dp]
     lib.orc_normalize.argtypes = [_dp, C.c_int64, C.c_int32, C.c_double, _dp, _dp, _dp]
     lib.orc_gradient.argtypes = [_dp, C.c_int64, C.c_int32, _dp, C.c_double, C.c_int32,
-                                 C.c_double, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
+                                 C.c_int32, C.c_double, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp,
+                                 _i64p, _dp]
     lib.orc_iterate.argtypes = [C.c_void_p, C.c_int64, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp,
                                 C.c_int32, C.c_int32, vp]
     lib.orc_kl.restype = C.c_double
@@ -217,8 +218,10 @@ class Tree:
         _check(self._lib.orc_tree_level(self.h, l, pre, cnt, sm), "tree level")
         return pre, cnt, sm
 
-    def repulsion(self, beta, theta: float, com_mode: int = 0, rows=None):
-        """(R, Z_i, visits) for every point, or for the points in rows."""
+    def repulsion(self, beta, theta: float, com_mode: int = 0, rows=None, predicate: int = 0):
+        """(R, Z_i, visits) for every point, or for the points in rows.
+        predicate 0: the opening test in FP64; 1: in FP32 (operands rounded to
+        FP32, each operation rounded in the written order)."""
         if rows is None:
             m, rp = self.z.shape[0], None
         else:
@@ -228,7 +231,8 @@ class Tree:
         Zi = np.empty(m, np.float64)
         vis = np.empty(m, np.int64)
         _check(self._lib.orc_repulsion_rows(self.h, self.z, _f64(beta), float(theta),
-                                            int(com_mode), rp, m, R, Zi, vis), "repulsion")
+                                            int(com_mode), int(predicate), rp, m, R, Zi, vis),
+               "repulsion")
         return R, Zi, vis
 
 
@@ -270,8 +274,10 @@ def normalize(zh, r: int, eps: float = 1e-6):
     return z, g, m
 
 
-def gradient(z, r: int, s, P, theta: float = 0.5, com_mode: int = 0, alpha: float = 1.0):
-    """Pixel-frame bracket B = alpha*A - R/Z and its parts (dict)."""
+def gradient(z, r: int, s, P, theta: float = 0.5, com_mode: int = 0, alpha: float = 1.0,
+             predicate: int = 0):
+    """Pixel-frame bracket B = alpha*A - R/Z and its parts (dict); predicate
+    selects the FP64 (0) or FP32 (1) opening test, forces FP64 either way."""
     z = _f64(z)
     n = z.shape[0]
     rp, col, val = _csr(P)
@@ -281,8 +287,8 @@ def gradient(z, r: int, s, P, theta: float = 0.5, com_mode: int = 0, alpha: floa
     Zi = np.empty(n)
     vis = np.empty(n, np.int64)
     Z = np.empty(1)
-    _check(_load().orc_gradient(z, n, r, _f64(s), float(theta), int(com_mode), float(alpha),
-                                rp, col, val, B, A, R, Zi, vis, Z), "gradient")
+    _check(_load().orc_gradient(z, n, r, _f64(s), float(theta), int(com_mode), int(predicate),
+                                float(alpha), rp, col, val, B, A, R, Zi, vis, Z), "gradient")
     return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": float(Z[0])}
 
 
@@ -290,14 +296,16 @@ class Params(C.Structure):
     _fields_ = [("r", C.c_int32), ("theta", C.c_double), ("com_mode", C.c_int32),
                 ("eta", C.c_double), ("mom0", C.c_double), ("mom1", C.c_double),
                 ("mom_switch", C.c_int32), ("exaggeration", C.c_double),
-                ("exag_iters", C.c_int32), ("min_gain", C.c_double), ("eps", C.c_double)]
+                ("exag_iters", C.c_int32), ("min_gain", C.c_double), ("eps", C.c_double),
+                ("predicate", C.c_int32)]
 
 
 def params(r: int, theta: float = 0.5, com_mode: int = 0, eta: float = 200.0, mom0: float = 0.5,
            mom1: float = 0.8, mom_switch: int = 250, exaggeration: float = 12.0,
-           exag_iters: int = 250, min_gain: float = 0.01, eps: float = 1e-6) -> Params:
+           exag_iters: int = 250, min_gain: float = 0.01, eps: float = 1e-6,
+           predicate: int = 0) -> Params:
     return Params(r, theta, com_mode, eta, mom0, mom1, mom_switch, exaggeration, exag_iters,
-                  min_gain, eps)
+                  min_gain, eps, predicate)
 
 
 class State:

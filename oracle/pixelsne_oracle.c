@@ -430,6 +430,12 @@ int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted
 /*   diag2 = w^2 (beta1 + beta2)                      (cell diagonal^2)  */
 /*   a leaf is always used; an inner cell is used iff                    */
 /*   diag2 < theta^2 * d2  (diagonal / distance < theta), else recurse.  */
+/* predicate 0 evaluates that test in FP64; predicate 1 in FP32: z_i, c, */
+/* w, beta and theta^2 rounded to FP32, then                             */
+/*   (w*w)*(b1+b2) < th2*((b1*dx)*dx + (b2*dy)*dy),  dx = z_i - c,       */
+/* each operation rounded to FP32 in that order (no fused multiply-add;  */
+/* the library's FP32 path takes the same decision).  The forces of a    */
+/* used cell are FP64 either way.                                        */
 /* A used cell adds m*w_ic to Z_i and m*w_ic^2*dz to R_i, w = 1/(1+d2).  */
 /* m = N_c, except in the leaf holding i: m = N_c - 1 and c is the mean */
 /* of the other points (the cell centre in CELL_CENTER mode); skipped   */
@@ -441,12 +447,15 @@ int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted
 /* rows == NULL: every point, outputs indexed by point; otherwise outputs are
  * indexed by position in rows[0..nrows). */
 int orc_repulsion_rows(const void* h, const double* z, const double* beta, double theta,
-                       int32_t com_mode, const int64_t* rows, int64_t nrows, double* R,
-                       double* Zi, int64_t* visits) {
+                       int32_t com_mode, int32_t predicate, const int64_t* rows, int64_t nrows,
+                       double* R, double* Zi, int64_t* visits) {
     const otree* t = (const otree*)h;
     if (!t || !z || !beta || !(theta >= 0.0) || theta >= 1.0) return ORC_EINVAL;
+    if (predicate != 0 && predicate != 1) return ORC_EINVAL;
     const int L = t->L;
     const double b1 = beta[0], b2 = beta[1], th2 = theta * theta;
+    /* single-precision operands of the FP32 opening test */
+    const float b1f = (float)b1, b2f = (float)b2, th2f = (float)th2, bsf = b1f + b2f;
     if (!rows) nrows = t->n;
     int64_t q;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -488,11 +497,19 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
                         cy = (cs_get(&nd->sy) - zy) / m;
                     }
                 }
-            } else {
+            } else if (predicate == 0) {
                 double dx = zx - cx, dy = zy - cy;
                 double d2 = b1 * dx * dx + b2 * dy * dy;
                 double diag2 = w * w * (b1 + b2);
                 use = diag2 < th2 * d2;
+            } else {
+                /* the same test in single precision: operands rounded to
+                 * FP32, every operation rounded to FP32 in this order */
+                float dxf = (float)zx - (float)cx, dyf = (float)zy - (float)cy;
+                float wf = (float)w;
+                float d2f = (b1f * dxf) * dxf + (b2f * dyf) * dyf;
+                float diag2f = (wf * wf) * bsf;
+                use = diag2f < th2f * d2f;
             }
             if (use) {
                 double dx = zx - cx, dy = zy - cy;
@@ -514,8 +531,8 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
 }
 
 int orc_repulsion(const void* h, const double* z, const double* beta, double theta,
-                  int32_t com_mode, double* R, double* Zi, int64_t* visits) {
-    return orc_repulsion_rows(h, z, beta, theta, com_mode, NULL, 0, R, Zi, visits);
+                  int32_t com_mode, int32_t predicate, double* R, double* Zi, int64_t* visits) {
+    return orc_repulsion_rows(h, z, beta, theta, com_mode, predicate, NULL, 0, R, Zi, visits);
 }
 
 /* Z = sum_i Z_i, compensated, in index order */
@@ -589,7 +606,8 @@ int orc_normalize(const double* zh, int64_t n, int32_t r, double eps, double* z,
 /* Outputs B (and optionally A, R, Z_i, visits, Z).                      */
 /* ------------------------------------------------------------------ */
 int orc_gradient(const double* z, int64_t n, int32_t r, const double* s, double theta,
-                 int32_t com_mode, double alpha, const int64_t* row_ptr, const int32_t* col,
+                 int32_t com_mode, int32_t predicate, double alpha, const int64_t* row_ptr,
+                 const int32_t* col,
                  const double* val, double* B, double* A_out, double* R_out, double* Zi_out,
                  int64_t* visits, double* Z_out) {
     double beta[2] = {s[0] * s[0], s[1] * s[1]};
@@ -600,7 +618,7 @@ int orc_gradient(const double* z, int64_t n, int32_t r, const double* s, double 
     double* Zi = Zi_out ? Zi_out : (double*)malloc(sizeof(double) * (size_t)n);
     int rc = ORC_ENOMEM;
     if (A && R && Zi) {
-        rc = orc_repulsion(h, z, beta, theta, com_mode, R, Zi, visits);
+        rc = orc_repulsion(h, z, beta, theta, com_mode, predicate, R, Zi, visits);
         if (rc == ORC_OK) rc = orc_attraction(z, n, beta, row_ptr, col, val, A);
         if (rc == ORC_OK) {
             double Z = orc_sum(Zi, n);
@@ -633,6 +651,7 @@ typedef struct {
     double exaggeration;
     int32_t exag_iters;
     double min_gain, eps;
+    int32_t predicate;   /* opening test: 0 FP64, 1 FP32 (see orc_repulsion_rows) */
 } orc_params;
 
 static inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
@@ -650,7 +669,8 @@ int orc_iterate(const orc_params* p, int64_t n, const int64_t* row_ptr, const in
         double alpha = t < p->exag_iters ? p->exaggeration : 1.0;
         double mu = t < p->mom_switch ? p->mom0 : p->mom1;
         double Z;
-        rc = orc_gradient(z, n, p->r, s, p->theta, p->com_mode, alpha, row_ptr, col, val, B,
+        rc = orc_gradient(z, n, p->r, s, p->theta, p->com_mode, p->predicate, alpha, row_ptr,
+                          col, val, B,
                           NULL, NULL, NULL, NULL, &Z);
         if (rc != ORC_OK) break;
         if (Z_hist) Z_hist[it] = Z;

@@ -64,6 +64,7 @@ psne_status check_params(const pixelsne_params* p) {
         return invalid("reorder_growth must be in [1, 1e6]");
     if (p->graphs != 0 && p->graphs != 1) return invalid("graphs must be 0 or 1");
     if (p->data_order != 0 && p->data_order != 1) return invalid("data_order must be 0 or 1");
+    if (p->opening_fp64 != 0 && p->opening_fp64 != 1) return invalid("opening_fp64 must be 0 or 1");
     return PSNE_OK;
 }
 
@@ -143,6 +144,9 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     // + 3: the traversal loads a sibling group as four records at once
     if ((e = dalloc(c, &tb.nodes, sizeof(Node) * (size_t)(mx + 3))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;
+    if (c->prm.precision == PSNE_FP32 && !c->prm.opening_fp64 &&
+        (e = dalloc(c, &tb.cells32, sizeof(CellF) * (size_t)(mx + 3))) != hipSuccess)
+        return e;
     if ((e = dalloc(c, &tb.leaf_of, 4 * (size_t)n)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.zs, v2)) != hipSuccess) return e;
     // renumbering: spare copies of the state, index maps, the chunked copy of P
@@ -285,6 +289,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->data_order = 1;
     p->graphs = 1;
     p->reorder_growth = 2.0;
+    p->opening_fp64 = 0;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -510,6 +515,9 @@ psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, co
     h.nonfinite = 0;
     e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = run_set_state(c, z, u, g);
+    // the renumbering schedule as it stands after `iteration` iterations (the
+    // points keep their current internal numbering)
+    reset_reorder_schedule(c, iteration);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_error(c, e, "set_state");
     return PSNE_OK;

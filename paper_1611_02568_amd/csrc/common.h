@@ -44,6 +44,14 @@ struct alignas(32) Node {
     uint32_t level;
 };
 
+// The traversal's copy of a cell for the FP32 path (16 bytes): the
+// representative point rounded to FP32, and count and child as in Node.
+struct alignas(16) CellF {
+    float cx, cy;
+    uint32_t count;
+    uint32_t child;
+};
+
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
 template <> struct V2<double> { using type = double2; };

@@ -25,6 +25,7 @@ struct TreeBufs {
     double2* wlast = nullptr;
     uint32_t* first_child = nullptr;         // [max_nodes]
     Node* nodes = nullptr;                   // [max_nodes]
+    CellF* cells32 = nullptr;                // [max_nodes] FP32 copy (FP32 opening test)
     double2* nsum = nullptr;                 // [max_nodes] coordinate sums (FP64)
     uint32_t* leaf_of = nullptr;             // [n] leaf cell of each sorted position
     void* zs = nullptr;                      // [n][2] positions in sorted order (state type)
@@ -75,6 +76,7 @@ struct pixelsne_ctx {
     int32_t since_reorder = 0;               // iterations since the last renumbering
     int64_t reorder_interval = 0;            // ... at which the next one is due
     int32_t scheduled_reorders = 0;
+    int32_t since_reorder0 = 0;              // since_reorder at iteration 0 (schedule origin)
 
     // P for the attraction pass: internal rows cut into chunks of at most
     // kChunkRows consecutive rows; within a chunk the nonzeros are ordered by
@@ -147,6 +149,8 @@ hipError_t kl_scratch_address(int device, double** out);
 // renumbering and the chunked copy of P (reorder.hip)
 hipError_t run_reorder(pixelsne_ctx* c);
 hipError_t run_scheduled_reorder(pixelsne_ctx* c);
+// put the renumbering schedule where it stands after t iterations from the start
+void reset_reorder_schedule(pixelsne_ctx* c, int32_t t);
 hipError_t run_identity_order(pixelsne_ctx* c);
 // renumber by a Morton code of three random projections of X (rows of D
 // elements of x_dtype) and delay the first renumbering by the embedding to the

@@ -261,7 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     }
 }
 
-__device__ __forceinline__ void write_node(Node* __restrict__ nodes, double2* __restrict__ nsum,
+__device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __restrict__ c32,
+                                           double2* __restrict__ nsum,
                                            uint32_t g, int level, int L, double sx, double sy,
                                            uint32_t count, uint32_t child, uint32_t key0,
                                            int com_mode) {
@@ -281,6 +282,7 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, double2* __
     nodes[g].count = count;
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
+    if (c32) c32[g] = CellF{(float)cx, (float)cy, count, child};
 }
 
 // Leaf sums, part 1 (one thread per sorted position): gather the position
@@ -343,8 +345,9 @@ constexpr uint32_t kLeafSerial = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tree_leaves(
     const uint32_t* __restrict__ keys, int64_t n, int L, int com_mode,
-    const DevScalars* __restrict__ sc, Node* __restrict__ nodes, double2* __restrict__ nsum,
-    const double2* __restrict__ wfirst, const double2* __restrict__ wlast) {
+    const DevScalars* __restrict__ sc, Node* __restrict__ nodes, CellF* __restrict__ c32,
+    double2* __restrict__ nsum, const double2* __restrict__ wfirst,
+    const double2* __restrict__ wlast) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = lane_id();
     const uint32_t nleaf = sc->level_size[L];
@@ -392,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
         sx = (wlast[wa].x + sx) + wfirst[wb].x;
         sy = (wlast[wa].y + sy) + wfirst[wb].y;
     }
-    write_node(nodes, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
+    write_node(nodes, c32, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
 }
 
 // One inner cell: count and sums of its children (consecutive in the next
@@ -400,8 +403,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
 __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, int l, int L,
                                            int com_mode, const DevScalars* __restrict__ sc,
                                            const uint32_t* __restrict__ first_child,
-                                           Node* __restrict__ nodes, double2* __restrict__ nsum,
-                                           uint32_t t, uint32_t m) {
+                                           Node* __restrict__ nodes, CellF* __restrict__ c32,
+                                           double2* __restrict__ nsum, uint32_t t, uint32_t m) {
     const uint32_t g = sc->level_base[l] + t;
     const uint32_t fc = first_child[g];
     const uint32_t lc = (t + 1 < m) ? first_child[g + 1] : sc->level_base[l + 1] + sc->level_size[l + 1];
@@ -413,8 +416,8 @@ __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, in
         ay += v.y;
         c += nodes[q].count;
     }
-    write_node(nodes, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30), keys[nodes[g].start],
-               com_mode);
+    write_node(nodes, c32, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30),
+               keys[nodes[g].start], com_mode);
 }
 
 // One level of inner cells, one thread per cell.
@@ -423,11 +426,12 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restric
                                                        const DevScalars* __restrict__ sc,
                                                        const uint32_t* __restrict__ first_child,
                                                        Node* __restrict__ nodes,
+                                                       CellF* __restrict__ c32,
                                                        double2* __restrict__ nsum) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t m = sc->level_size[l];
     if (t >= m) return;
-    inner_cell(keys, l, L, com_mode, sc, first_child, nodes, nsum, (uint32_t)t, m);
+    inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, (uint32_t)t, m);
 }
 
 // Levels top..0 in one block (a level l holds at most 4^l cells, so at most
@@ -441,11 +445,12 @@ __global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __rest
                                                           const DevScalars* __restrict__ sc,
                                                           const uint32_t* __restrict__ first_child,
                                                           Node* __restrict__ nodes,
+                                                          CellF* __restrict__ c32,
                                                           double2* __restrict__ nsum) {
     for (int l = top; l >= 0; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t t = threadIdx.x; t < m; t += kTopThreads)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, nsum, t, m);
+            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, t, m);
         __syncthreads();
     }
 }
@@ -509,6 +514,29 @@ __device__ __forceinline__ double add_nc(double a, double b) {
     return a + b;
 }
 
+// the same distance and product in FP32, each operation rounded separately
+__device__ __forceinline__ float dist2f(float b1, float b2, float dx, float dy) {
+#pragma clang fp contract(off)
+    const float a = (b1 * dx) * dx;
+    const float b = (b2 * dy) * dy;
+    return a + b;
+}
+__device__ __forceinline__ float mulf_nc(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// one used cell in the FP32 path: q = 1 / (1 + d^2) in FP32, Z_i summed in FP64
+__device__ __forceinline__ void bh_term32(float d2, float dx, float dy, float m, double& zacc,
+                                          float& rx, float& ry) {
+    const float q = __builtin_amdgcn_rcpf(1.0f + d2);
+    const float mq = m * q;
+    zacc += (double)mq;
+    const float f = mq * q;
+    rx += f * dx;
+    ry += f * dy;
+}
+
 // Write a stack entry (four wave-uniform words, in scalar registers) into
 // lane `sel` of the four per-lane stack registers.  With one scalar operand
 // per vector instruction the lane select goes through m0 (an input operand:
@@ -525,15 +553,20 @@ __device__ __forceinline__ void push_entry(int& a, int& b, int& c, int& d, int v
         : "s"(va), "s"(vb), "s"(vc), "s"(vd), "{m0}"(sel));
 }
 
-template <typename T, bool COUNT>
+// F32T (FP32 path only): the opening test and the distances in FP32 on the
+// cells' FP32 copies (cells32), operands and operations rounded as the FP64
+// test's expression written in single precision; otherwise in FP64 on nodes.
+template <typename T, bool COUNT, bool F32T>
 __global__ __launch_bounds__(kBlock) void k_traverse(
-    const Node* __restrict__ nodes, const double2* __restrict__ nsum, const T* __restrict__ zs,
+    const Node* __restrict__ nodes, const CellF* __restrict__ cells32,
+    const double2* __restrict__ nsum, const T* __restrict__ zs,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
     const DevScalars* __restrict__ sc, int64_t n, int L, double th2, int com_mode,
     T* __restrict__ R, double* __restrict__ zpart, const uint32_t* __restrict__ orig,
     double* __restrict__ Zi_out, uint32_t* __restrict__ visits_out,
     uint32_t* __restrict__ used_out) {
     using V = v2_t<T>;
+    static_assert(!F32T || sizeof(T) == 4, "the FP32 opening test belongs to the FP32 path");
     __shared__ double wz[4];
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -543,6 +576,10 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     const uint32_t own = valid ? leaf_of[s] : 0xFFFFFFFFu;
     const double s0 = sc->s[0], s1 = sc->s[1];
     const double b1 = mul_nc(s0, s0), b2 = mul_nc(s1, s1), bsum = add_nc(b1, b2);
+    // single-precision operands of the FP32 test: beta and theta^2 rounded
+    const float b1f = (float)b1, b2f = (float)b2, th2f = (float)th2;
+    const float bsumf = b1f + b2f;
+    const float zxf = (float)zp.x, zyf = (float)zp.y;
 
     double zacc = 0.0;
     T rx = T(0), ry = T(0);
@@ -567,6 +604,58 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
         const uint32_t nsib = info & 0xFFu;
         const int level = (int)(info >> 8);
         const bool act = __builtin_amdgcn_inverse_ballot_w64(mask);   // lane in mask
+        if constexpr (F32T) {
+            // (w w)(b1 + b2) with w = 2^(L - level): a power-of-two scaling, exact in FP32
+            const float diag2f = ldexpf(bsumf, 2 * (L - level));
+            CellF grp[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) grp[q] = cells32[first + q];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                if (q >= nsib) break;
+                const uint32_t c = first + q;
+                const CellF nd = grp[q];
+                uint64_t om = 0;
+                if (level < L) {
+                    const float dx = zxf - nd.cx, dy = zyf - nd.cy;
+                    const float d2 = dist2f(b1f, b2f, dx, dy);
+                    const bool near = !(diag2f < mulf_nc(th2f, d2));
+                    om = ballot64(near) & mask;
+                    const bool use = act && !near;
+                    bh_term32(d2, dx, dy, use ? (float)nd.count : 0.f, zacc, rx, ry);
+                    if (COUNT) {
+                        nuse += use ? 1u : 0u;
+                        nvis += act ? 1u : 0u;
+                    }
+                } else {
+                    float cx = nd.cx, cy = nd.cy;
+                    float m = (float)nd.count;
+                    bool use = act;
+                    if (c == own) {
+                        const uint32_t others = nd.count - 1u;
+                        m = (float)others;
+                        if (others > 0u && com_mode != PSNE_COM_CELL_CENTER) {
+                            const double2 sm = nsum[c];
+                            cx = (float)((sm.x - zx) / (double)others);
+                            cy = (float)((sm.y - zy) / (double)others);
+                        }
+                        use = act && others > 0u;
+                    }
+                    const float dx = zxf - cx, dy = zyf - cy;
+                    bh_term32(dist2f(b1f, b2f, dx, dy), dx, dy, use ? m : 0.f, zacc, rx, ry);
+                    if (COUNT) {
+                        nuse += use ? 1u : 0u;
+                        nvis += act ? 1u : 0u;
+                    }
+                }
+                if (om) {
+                    push_entry(st_first, st_info, st_mlo, st_mhi, (int)(nd.child & 0x3FFFFFFFu),
+                               (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
+                               (int)(uint32_t)om, (int)(uint32_t)(om >> 32), sp);
+                    sp++;
+                }
+            }
+        } else {
         const double diag2 = ldexp(bsum, 2 * (L - level));
         // the group's records (children are consecutive) in one batch of scalar loads
         Node grp[4];
@@ -623,6 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                            (int)(uint32_t)om, (int)(uint32_t)(om >> 32), sp);
                 sp++;
             }
+        }
         }
     }
     if (valid) {
@@ -1262,44 +1352,50 @@ hipError_t run_tree(pixelsne_ctx* c) {
             perm, tb.leaf_of, (const double*)c->z, c->n, tb.nsum, (double*)tb.zs, tb.wfirst,
             tb.wlast);
         k_tree_leaves<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
+            tb.wlast);
     } else {
         k_leaf_scan<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             perm, tb.leaf_of, (const float*)c->z, c->n, tb.nsum, (float*)tb.zs, tb.wfirst,
             tb.wlast);
         k_tree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.nsum, tb.wfirst, tb.wlast);
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
+            tb.wlast);
     }
     const int top = c->L - 1 < kTopLevel ? c->L - 1 : kTopLevel;
     for (int l = c->L - 1; l > top; l--) {
         const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;
         k_tree_level<<<grid_for(cap < c->n ? cap : c->n), kBlock, 0, c->stream>>>(
-            keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.nsum);
+            keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.cells32, tb.nsum);
     }
     if (top >= 0)
         k_tree_top<<<1, kTopThreads, 0, c->stream>>>(keys, top, c->L, c->prm.com_mode, c->sc,
-                                                     tb.first_child, tb.nodes, tb.nsum);
+                                                     tb.first_child, tb.nodes, tb.cells32, tb.nsum);
     return hipGetLastError();
 }
 
-template <typename T, bool COUNT>
+template <typename T, bool COUNT, bool F32T>
 void launch_traverse(pixelsne_ctx* c, double th2, uint32_t* visits, uint32_t* used, double* Zi) {
     TreeBufs& tb = c->tb;
-    k_traverse<T, COUNT><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-        tb.nodes, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc, c->n, c->L, th2,
-        c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
+    k_traverse<T, COUNT, F32T><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+        tb.nodes, tb.cells32, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc,
+        c->n, c->L, th2, c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
 }
 
 hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi) {
     const double th2 = c->prm.theta * c->prm.theta;
     // per-point counters only when they are asked for
     const bool count = visits || used;
+    const bool f32t = !fp64(c) && !c->prm.opening_fp64;
     if (fp64(c)) {
-        if (count) launch_traverse<double, true>(c, th2, visits, used, Zi);
-        else launch_traverse<double, false>(c, th2, visits, used, Zi);
+        if (count) launch_traverse<double, true, false>(c, th2, visits, used, Zi);
+        else launch_traverse<double, false, false>(c, th2, visits, used, Zi);
+    } else if (f32t) {
+        if (count) launch_traverse<float, true, true>(c, th2, visits, used, Zi);
+        else launch_traverse<float, false, true>(c, th2, visits, used, Zi);
     } else {
-        if (count) launch_traverse<float, true>(c, th2, visits, used, Zi);
-        else launch_traverse<float, false>(c, th2, visits, used, Zi);
+        if (count) launch_traverse<float, true, false>(c, th2, visits, used, Zi);
+        else launch_traverse<float, false, false>(c, th2, visits, used, Zi);
     }
     return hipGetLastError();
 }

@@ -294,6 +294,7 @@ hipError_t run_identity_order(pixelsne_ctx* c) {
     // the first renumbering follows the first iteration
     c->reorder_interval = c->prm.reorder_every;
     c->since_reorder = c->prm.reorder_every > 0 ? c->prm.reorder_every - 1 : 0;
+    c->since_reorder0 = c->since_reorder;
     return build_chunks(c);
 }
 
@@ -309,7 +310,23 @@ hipError_t run_data_order(pixelsne_ctx* c, const void* X, int32_t D, int32_t x_d
         const int32_t first = c->prm.exag_iters > 1 ? c->prm.exag_iters : 1;
         c->since_reorder = c->prm.reorder_every - first;
     }
+    c->since_reorder0 = c->since_reorder;
     return hipSuccess;
+}
+
+void reset_reorder_schedule(pixelsne_ctx* c, int32_t t) {
+    c->reorder_interval = c->prm.reorder_every;
+    c->since_reorder = c->since_reorder0;
+    c->scheduled_reorders = 0;
+    if (c->prm.reorder_every <= 0) return;
+    for (int32_t it = 0; it < t; it++) {
+        if (++c->since_reorder < c->reorder_interval) continue;
+        c->since_reorder = 0;
+        if (c->scheduled_reorders++ > 0) {
+            const double next = std::ceil((double)c->reorder_interval * c->prm.reorder_growth);
+            c->reorder_interval = next < 2147483647.0 ? (int64_t)next : 2147483647;
+        }
+    }
 }
 
 // After an iteration: renumber when the schedule says so.  The interval after

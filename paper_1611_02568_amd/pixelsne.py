@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("data_order", C.c_int32),
         ("graphs", C.c_int32),
         ("reorder_growth", C.c_double),
+        ("opening_fp64", C.c_int32),
     ]
 
 

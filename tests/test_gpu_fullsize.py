@@ -89,7 +89,8 @@ def test_gradient_full_1m(psne, big_P, prec):
                               Y_init=torch.as_tensor(datagen.initial_embedding(n, seed=4)))
     ctx.set_state(z, s)
     g = ctx.gradient(12.0)
-    og = oracle.gradient(z.astype(np.float64), r, np.array(s), big_P, theta=0.5, alpha=12.0)
+    og = oracle.gradient(z.astype(np.float64), r, np.array(s), big_P, theta=0.5, alpha=12.0,
+                         predicate=1 - prec)
     assert np.array_equal(g["visits"].cpu().numpy(), og["visits"])
     assert abs(g["Z"] - og["Z"]) <= TOL_Z[prec] * og["Z"]
     for key in ("A", "R", "B"):
@@ -110,7 +111,7 @@ def test_gradient_sampled_5m(psne):
     z64 = z.astype(np.float32).astype(np.float64)
     rows = np.random.default_rng(13).choice(n, 512, replace=False)
     beta = s * s
-    R, Zi, vis = oracle.Tree(z64, r).repulsion(beta, 0.5, rows=rows)
+    R, Zi, vis = oracle.Tree(z64, r).repulsion(beta, 0.5, rows=rows, predicate=1)
     A = oracle.attraction(z64, beta, P, rows=rows)
     assert np.array_equal(g["visits"].cpu().numpy()[rows], vis)
     np.testing.assert_allclose(g["Zi"].cpu().numpy()[rows], Zi, rtol=1e-5)

@@ -70,7 +70,7 @@ def test_update_step_parity(psne, near_switch, prec, k, graphs, reorder):
     ctx.set_state(o.z.astype(dt), o.s, u=o.u.astype(dt), g=o.g.astype(dt), iteration=o.t)
     ctx.step(k)
     got = ctx.get_state()
-    oracle.iterate(o, oracle.params(R), P, k)
+    oracle.iterate(o, oracle.params(R, predicate=1 - prec), P, k)
     assert got["iteration"] == o.t == 247 + k
     z = got["z"].double().cpu().numpy()
     u = got["u"].double().cpu().numpy()
@@ -114,7 +114,7 @@ def test_update_from_zero_velocity(psne, near_switch, prec):
     ctx.set_state(o.z.astype(dt), o.s, iteration=0)
     ctx.step(1)
     got = ctx.get_state()
-    oracle.iterate(o, oracle.params(R), P, 1)
+    oracle.iterate(o, oracle.params(R, predicate=1 - prec), P, 1)
     g = got["g"].double().cpu().numpy()
     assert np.all(g == dt(1.2)) and np.all(o.g == 1.2)
     u = got["u"].double().cpu().numpy()
