@@ -33,6 +33,7 @@ _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
 def _load():
@@ -55,6 +56,9 @@ def _load():
     lib.orc_morton.argtypes = [_dp, C.c_int64, C.c_int32, _u32p]
     lib.orc_tree_build.restype = vp
     lib.orc_tree_build.argtypes = [_dp, C.c_int64, C.c_int32]
+    lib.orc_dtree_build.restype = vp
+    lib.orc_dtree_build.argtypes = [_dp, C.c_int64, C.c_int32]
+    lib.orc_tree_level64.argtypes = [vp, C.c_int32, _u64p, _i64p, _dp]
     lib.orc_tree_free.argtypes = [vp]
     lib.orc_tree_depth.restype = C.c_int32
     lib.orc_tree_depth.argtypes = [vp]
@@ -73,8 +77,8 @@ def _load():
     lib.orc_attraction.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp, _dp]
     lib.orc_normalize.argtypes = [_dp, C.c_int64, C.c_int32, C.c_double, _dp, _dp, _dp]
     lib.orc_gradient.argtypes = [_dp, C.c_int64, C.c_int32, _dp, C.c_double, C.c_int32,
-                                 C.c_int32, C.c_double, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp,
-                                 _i64p, _dp]
+                                 C.c_int32, C.c_int32, C.c_double, _i64p, _i32p, _dp, _dp, _dp,
+                                 _dp, _dp, _i64p, _dp]
     lib.orc_iterate.argtypes = [C.c_void_p, C.c_int64, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp,
                                 C.c_int32, C.c_int32, vp]
     lib.orc_kl.restype = C.c_double
@@ -187,13 +191,17 @@ def sorted_order(z, r: int):
 
 
 class Tree:
-    """P-Quadtree of pixel positions z (n x 2) on an r x r screen."""
+    """P-Quadtree (kind 0) of pixel positions z (n x 2) on an r x r screen, or
+    the D-Quadtree of Barnes-Hut-SNE (kind 1) over the same frame: split until
+    each leaf holds one point (or one cell of the 2^32 grid), levels 0..32."""
 
-    def __init__(self, z, r: int):
+    def __init__(self, z, r: int, kind: int = 0):
         self._lib = _load()
         self.z = _f64(z)
         self.r = r
-        self.h = self._lib.orc_tree_build(self.z, self.z.shape[0], r)
+        self.kind = kind
+        build = self._lib.orc_dtree_build if kind == 1 else self._lib.orc_tree_build
+        self.h = build(self.z, self.z.shape[0], r)
         if not self.h:
             raise RuntimeError("oracle tree build failed")
         self.L = self._lib.orc_tree_depth(self.h)
@@ -210,12 +218,17 @@ class Tree:
         return s
 
     def level(self, l: int):
-        """(prefix uint32, count int64, sums float64 [m,2]) ascending by prefix."""
+        """(prefix, count int64, sums float64 [m,2]) ascending by prefix; the
+        prefix is uint32 (P-Quadtree) or uint64 on the 2^32 grid (D-Quadtree)."""
         m = int(self.level_sizes()[l])
-        pre = np.empty(m, np.uint32)
         cnt = np.empty(m, np.int64)
         sm = np.empty((m, 2), np.float64)
-        _check(self._lib.orc_tree_level(self.h, l, pre, cnt, sm), "tree level")
+        if self.kind == 1:
+            pre = np.empty(m, np.uint64)
+            _check(self._lib.orc_tree_level64(self.h, l, pre, cnt, sm), "tree level")
+        else:
+            pre = np.empty(m, np.uint32)
+            _check(self._lib.orc_tree_level(self.h, l, pre, cnt, sm), "tree level")
         return pre, cnt, sm
 
     def repulsion(self, beta, theta: float, com_mode: int = 0, rows=None, predicate: int = 0):
@@ -275,9 +288,10 @@ def normalize(zh, r: int, eps: float = 1e-6):
 
 
 def gradient(z, r: int, s, P, theta: float = 0.5, com_mode: int = 0, alpha: float = 1.0,
-             predicate: int = 0):
+             predicate: int = 0, tree: int = 0):
     """Pixel-frame bracket B = alpha*A - R/Z and its parts (dict); predicate
-    selects the FP64 (0) or FP32 (1) opening test, forces FP64 either way."""
+    selects the FP64 (0) or FP32 (1) opening test, forces FP64 either way;
+    tree selects the P-Quadtree (0) or the D-Quadtree (1)."""
     z = _f64(z)
     n = z.shape[0]
     rp, col, val = _csr(P)
@@ -288,7 +302,8 @@ def gradient(z, r: int, s, P, theta: float = 0.5, com_mode: int = 0, alpha: floa
     vis = np.empty(n, np.int64)
     Z = np.empty(1)
     _check(_load().orc_gradient(z, n, r, _f64(s), float(theta), int(com_mode), int(predicate),
-                                float(alpha), rp, col, val, B, A, R, Zi, vis, Z), "gradient")
+                                int(tree), float(alpha), rp, col, val, B, A, R, Zi, vis, Z),
+           "gradient")
     return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": float(Z[0])}
 
 
@@ -297,15 +312,15 @@ class Params(C.Structure):
                 ("eta", C.c_double), ("mom0", C.c_double), ("mom1", C.c_double),
                 ("mom_switch", C.c_int32), ("exaggeration", C.c_double),
                 ("exag_iters", C.c_int32), ("min_gain", C.c_double), ("eps", C.c_double),
-                ("predicate", C.c_int32)]
+                ("predicate", C.c_int32), ("tree", C.c_int32)]
 
 
 def params(r: int, theta: float = 0.5, com_mode: int = 0, eta: float = 200.0, mom0: float = 0.5,
            mom1: float = 0.8, mom_switch: int = 250, exaggeration: float = 12.0,
            exag_iters: int = 250, min_gain: float = 0.01, eps: float = 1e-6,
-           predicate: int = 0) -> Params:
+           predicate: int = 0, tree: int = 0) -> Params:
     return Params(r, theta, com_mode, eta, mom0, mom1, mom_switch, exaggeration, exag_iters,
-                  min_gain, eps, predicate)
+                  min_gain, eps, predicate, tree)
 
 
 class State:

@@ -291,17 +291,26 @@ int orc_morton(const double* z, int64_t n, int32_t r, uint32_t* key) {
 typedef struct {
     int32_t child[4];
     int32_t level;
-    uint32_t prefix;
+    uint32_t prefix;        /* P-Quadtree: Morton prefix of the cell */
+    uint64_t prefix64;      /* D-Quadtree: Morton prefix on the 2^32 grid */
     int64_t count;
     csum sx, sy;
+    int64_t first;          /* D-Quadtree leaf: first member point (-1: none) */
 } onode;
 
 typedef struct {
     int32_t r, L;
+    int32_t kind;           /* 0: P-Quadtree (pixel leaves), 1: D-Quadtree */
+    int32_t Lmax;           /* deepest level: L, or 32 for the D-Quadtree */
     int64_t n, nnodes, cap;
     onode* nodes;
-    int32_t* leaf_of;       /* node id of each point's pixel */
+    int32_t* leaf_of;       /* node id of each point's leaf */
+    int64_t* next;          /* D-Quadtree: next member of the same leaf (-1: last) */
 } otree;
+
+static inline int is_leaf(const onode* nd) {
+    return nd->child[0] < 0 && nd->child[1] < 0 && nd->child[2] < 0 && nd->child[3] < 0;
+}
 
 static int32_t tree_new_node(otree* t, int32_t level, uint32_t prefix) {
     if (t->nnodes == t->cap) {
@@ -314,13 +323,14 @@ static int32_t tree_new_node(otree* t, int32_t level, uint32_t prefix) {
     memset(c, 0, sizeof(*c));
     c->child[0] = c->child[1] = c->child[2] = c->child[3] = -1;
     c->level = level; c->prefix = prefix;
+    c->first = -1;
     return (int32_t)t->nnodes++;
 }
 
 void orc_tree_free(void* h) {
     otree* t = (otree*)h;
     if (!t) return;
-    free(t->nodes); free(t->leaf_of); free(t);
+    free(t->nodes); free(t->leaf_of); free(t->next); free(t);
 }
 
 void* orc_tree_build(const double* z, int64_t n, int32_t r) {
@@ -329,6 +339,7 @@ void* orc_tree_build(const double* z, int64_t n, int32_t r) {
     otree* t = (otree*)calloc(1, sizeof(otree));
     if (!t) return NULL;
     t->r = r; t->L = L; t->n = n;
+    t->kind = 0; t->Lmax = L;
     t->leaf_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     if (!t->leaf_of || tree_new_node(t, 0, 0) != 0) { orc_tree_free(t); return NULL; }
     for (int64_t i = 0; i < n; i++) {
@@ -357,13 +368,109 @@ void* orc_tree_build(const double* z, int64_t n, int32_t r) {
     return t;
 }
 
-int32_t orc_tree_depth(const void* h) { return ((const otree*)h)->L; }
+/* ------------------------------------------------------------------ */
+/* D-Quadtree of Barnes-Hut-SNE (Section 3.3): the root spans the data, */
+/* [min y_d, max y_d + eps) per axis (Eq. 9-10), and cells split into  */
+/* four equal quadrants as points are assigned one by one, until every  */
+/* leaf holds at most one point.  The root is the screen's frame: the   */
+/* scaling of Section 4.2 maps [min, max + eps) onto [0, r), so in the  */
+/* pixel frame the root is [0, r)^2.  Cell boundaries are kept exact on */
+/* a 2^32 x 2^32 grid over the root (q = floor(z 2^(32 - L)); child     */
+/* index 2 ybit + xbit as for the P-Quadtree); points that fall in one  */
+/* grid cell cannot be told apart there and share a leaf at level 32.   */
+/* Each cell counts its points and sums their coordinates (Eq. 7-8).    */
+/* ------------------------------------------------------------------ */
+static inline uint32_t grid32(double z, int L) {
+    double f = floor(ldexp(z, 32 - L));
+    if (!(f >= 0.0)) return 0;
+    if (f > 4294967295.0) return 4294967295u;
+    return (uint32_t)f;
+}
+
+static inline int quadrant(uint32_t qx, uint32_t qy, int level) {
+    int sh = 31 - level;                  /* bit that splits a cell of this level */
+    return (int)(((qy >> sh) & 1u) << 1 | ((qx >> sh) & 1u));
+}
+
+void* orc_dtree_build(const double* z, int64_t n, int32_t r) {
+    int L = log2_exact(r);
+    if (!z || n < 1 || L < 0 || L > 16) return NULL;
+    otree* t = (otree*)calloc(1, sizeof(otree));
+    if (!t) return NULL;
+    t->r = r; t->L = L; t->n = n;
+    t->kind = 1; t->Lmax = 32;
+    t->leaf_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    t->next = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!t->leaf_of || !t->next || tree_new_node(t, 0, 0) != 0) { orc_tree_free(t); return NULL; }
+    for (int64_t i = 0; i < n; i++) {
+        const double zx = z[2 * i], zy = z[2 * i + 1];
+        const uint32_t qx = grid32(zx, L), qy = grid32(zy, L);
+        int32_t c = 0;
+        for (;;) {
+            onode* nd = &t->nodes[c];
+            nd->count++;
+            cs_add(&nd->sx, zx);
+            cs_add(&nd->sy, zy);
+            if (is_leaf(nd)) {
+                if (nd->first < 0) {                       /* empty leaf */
+                    nd->first = i; t->next[i] = -1;
+                    break;
+                }
+                const int64_t f = nd->first;
+                const uint32_t fx = grid32(z[2 * f], L), fy = grid32(z[2 * f + 1], L);
+                if (nd->level == 32 || (fx == qx && fy == qy)) {
+                    /* same grid cell: the leaf keeps both (members in order) */
+                    int64_t j = f;
+                    while (t->next[j] >= 0) j = t->next[j];
+                    t->next[j] = i; t->next[i] = -1;
+                    break;
+                }
+                /* split: the leaf's members (one grid position) move to
+                 * their quadrant child; then i continues below */
+                const int level = nd->level;
+                const uint64_t pre = nd->prefix64;
+                const int qf = quadrant(fx, fy, level);
+                int32_t ch = tree_new_node(t, level + 1, 0);
+                if (ch < 0) { orc_tree_free(t); return NULL; }
+                nd = &t->nodes[c];                           /* nodes may have moved */
+                onode* cn = &t->nodes[ch];
+                cn->prefix64 = (pre << 2) | (uint64_t)qf;
+                cn->first = f;
+                for (int64_t j = f; j >= 0; j = t->next[j]) {
+                    cn->count++;
+                    cs_add(&cn->sx, z[2 * j]);
+                    cs_add(&cn->sy, z[2 * j + 1]);
+                }
+                nd->first = -1;
+                nd->child[qf] = ch;
+            }
+            const int q = quadrant(qx, qy, nd->level);
+            int32_t ch = nd->child[q];
+            if (ch < 0) {
+                const uint64_t pre = (nd->prefix64 << 2) | (uint64_t)q;
+                const int level = nd->level;
+                ch = tree_new_node(t, level + 1, 0);
+                if (ch < 0) { orc_tree_free(t); return NULL; }
+                t->nodes[ch].prefix64 = pre;
+                t->nodes[c].child[q] = ch;
+            }
+            c = ch;
+        }
+    }
+    /* each point's leaf, after all the splits */
+    for (int64_t c = 0; c < t->nnodes; c++)
+        if (is_leaf(&t->nodes[c]))
+            for (int64_t j = t->nodes[c].first; j >= 0; j = t->next[j]) t->leaf_of[j] = (int32_t)c;
+    return t;
+}
+
+int32_t orc_tree_depth(const void* h) { return ((const otree*)h)->Lmax; }
 int64_t orc_tree_num_nodes(const void* h) { return ((const otree*)h)->nnodes; }
 
-/* number of occupied cells at each level 0..L */
+/* number of occupied cells at each level 0..Lmax */
 int orc_tree_level_sizes(const void* h, int64_t* sizes) {
     const otree* t = (const otree*)h;
-    for (int l = 0; l <= t->L; l++) sizes[l] = 0;
+    for (int l = 0; l <= t->Lmax; l++) sizes[l] = 0;
     for (int64_t c = 0; c < t->nnodes; c++) sizes[t->nodes[c].level]++;
     return ORC_OK;
 }
@@ -374,10 +481,39 @@ static int pref_cmp(const void* a, const void* b) {
     return x->prefix < y->prefix ? -1 : (x->prefix > y->prefix ? 1 : 0);
 }
 
+/* cells of one level of a D-Quadtree ascending by prefix: prefix on the
+ * 2^32 grid, count, sums */
+typedef struct { uint64_t prefix; int64_t id; } pref64_t;
+static int pref64_cmp(const void* a, const void* b) {
+    const pref64_t* x = (const pref64_t*)a; const pref64_t* y = (const pref64_t*)b;
+    return x->prefix < y->prefix ? -1 : (x->prefix > y->prefix ? 1 : 0);
+}
+
+int orc_tree_level64(const void* h, int32_t level, uint64_t* prefix, int64_t* count, double* sum) {
+    const otree* t = (const otree*)h;
+    if (level < 0 || level > t->Lmax) return ORC_EINVAL;
+    int64_t m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++) if (t->nodes[c].level == level) m++;
+    pref64_t* v = (pref64_t*)malloc(sizeof(pref64_t) * (size_t)(m ? m : 1));
+    if (!v) return ORC_ENOMEM;
+    m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++)
+        if (t->nodes[c].level == level) { v[m].prefix = t->nodes[c].prefix64; v[m].id = c; m++; }
+    qsort(v, (size_t)m, sizeof(pref64_t), pref64_cmp);
+    for (int64_t a = 0; a < m; a++) {
+        const onode* nd = &t->nodes[v[a].id];
+        if (prefix) prefix[a] = nd->prefix64;
+        if (count) count[a] = nd->count;
+        if (sum) { sum[2 * a] = cs_get(&nd->sx); sum[2 * a + 1] = cs_get(&nd->sy); }
+    }
+    free(v);
+    return ORC_OK;
+}
+
 /* cells of one level ascending by Morton prefix: prefix, count, sums */
 int orc_tree_level(const void* h, int32_t level, uint32_t* prefix, int64_t* count, double* sum) {
     const otree* t = (const otree*)h;
-    if (level < 0 || level > t->L) return ORC_EINVAL;
+    if (level < 0 || level > t->L || t->kind != 0) return ORC_EINVAL;
     int64_t m = 0;
     for (int64_t c = 0; c < t->nnodes; c++) if (t->nodes[c].level == level) m++;
     pref_t* v = (pref_t*)malloc(sizeof(pref_t) * (size_t)(m ? m : 1));
@@ -452,6 +588,7 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
     const otree* t = (const otree*)h;
     if (!t || !z || !beta || !(theta >= 0.0) || theta >= 1.0) return ORC_EINVAL;
     if (predicate != 0 && predicate != 1) return ORC_EINVAL;
+    if (t->kind == 1 && com_mode == 1) return ORC_EINVAL;   /* D-Quadtree: centres of mass only */
     const int L = t->L;
     const double b1 = beta[0], b2 = beta[1], th2 = theta * theta;
     /* single-precision operands of the FP32 opening test */
@@ -465,14 +602,14 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
         const int32_t own = t->leaf_of[i];
         double rx = 0.0, ry = 0.0, zsum = 0.0;
         int64_t nv = 0;
-        int32_t stack[4 * 20];
+        int32_t stack[4 * 36];          /* 3 per level below the root, 33 levels at most */
         int sp = 0;
         stack[sp++] = 0;
         while (sp > 0) {
             const int32_t c = stack[--sp];
             const onode* nd = &t->nodes[c];
             nv++;
-            const double w = (double)(1u << (L - nd->level));
+            const double w = ldexp(1.0, L - nd->level);   /* side in pixels */
             double m = (double)nd->count, cx, cy;
             if (com_mode == 1) {
                 uint32_t x0 = 0, y0 = 0;
@@ -487,7 +624,7 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
                 cy = cs_get(&nd->sy) / m;
             }
             int use;
-            if (nd->level == L) {
+            if (is_leaf(nd)) {
                 use = 1;
                 if (c == own) {
                     m -= 1.0;
@@ -606,12 +743,12 @@ int orc_normalize(const double* zh, int64_t n, int32_t r, double eps, double* z,
 /* Outputs B (and optionally A, R, Z_i, visits, Z).                      */
 /* ------------------------------------------------------------------ */
 int orc_gradient(const double* z, int64_t n, int32_t r, const double* s, double theta,
-                 int32_t com_mode, int32_t predicate, double alpha, const int64_t* row_ptr,
-                 const int32_t* col,
+                 int32_t com_mode, int32_t predicate, int32_t tree, double alpha,
+                 const int64_t* row_ptr, const int32_t* col,
                  const double* val, double* B, double* A_out, double* R_out, double* Zi_out,
                  int64_t* visits, double* Z_out) {
     double beta[2] = {s[0] * s[0], s[1] * s[1]};
-    void* h = orc_tree_build(z, n, r);
+    void* h = tree == 1 ? orc_dtree_build(z, n, r) : orc_tree_build(z, n, r);
     if (!h) return ORC_ENOMEM;
     double* A = A_out ? A_out : (double*)malloc(sizeof(double) * 2 * (size_t)n);
     double* R = R_out ? R_out : (double*)malloc(sizeof(double) * 2 * (size_t)n);
@@ -652,6 +789,7 @@ typedef struct {
     int32_t exag_iters;
     double min_gain, eps;
     int32_t predicate;   /* opening test: 0 FP64, 1 FP32 (see orc_repulsion_rows) */
+    int32_t tree;        /* 0: P-Quadtree, 1: D-Quadtree (orc_dtree_build) */
 } orc_params;
 
 static inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
@@ -669,8 +807,8 @@ int orc_iterate(const orc_params* p, int64_t n, const int64_t* row_ptr, const in
         double alpha = t < p->exag_iters ? p->exaggeration : 1.0;
         double mu = t < p->mom_switch ? p->mom0 : p->mom1;
         double Z;
-        rc = orc_gradient(z, n, p->r, s, p->theta, p->com_mode, p->predicate, alpha, row_ptr,
-                          col, val, B,
+        rc = orc_gradient(z, n, p->r, s, p->theta, p->com_mode, p->predicate, p->tree, alpha,
+                          row_ptr, col, val, B,
                           NULL, NULL, NULL, NULL, &Z);
         if (rc != ORC_OK) break;
         if (Z_hist) Z_hist[it] = Z;

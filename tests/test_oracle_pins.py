@@ -451,3 +451,156 @@ def test_neighborhood_precision_invariants(orc):
         lo = np.stack([rng.permutation(np.delete(np.arange(n), i))[:30] for i in range(n)])
         vals.append(orc.neighborhood_precision(hi, lo, [30])[0])
     assert abs(np.mean(vals) - 30 / 399) < 0.006
+
+
+# --------------------------------------------------------------------------
+# D-Quadtree (Barnes-Hut-SNE's data-driven tree, Section 3.3, Eq. 9-10)
+# --------------------------------------------------------------------------
+def _grid64(z, r):
+    """Morton keys on the 2^32 grid over the root [0, r)^2 (x even bits)."""
+    L = int(round(math.log2(r)))
+    q = np.clip(np.floor(np.ldexp(z, 32 - L)), 0, 2.0 ** 32 - 1).astype(np.uint64)
+    key = np.zeros(len(z), np.uint64)
+    for b in range(32):
+        key |= ((q[:, 0] >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+        key |= ((q[:, 1] >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b + 1)
+    return q, key
+
+
+def _dtree_cells(z, r):
+    """Brute force: the cells of level l are the distinct level-l prefixes of
+    the points whose level-(l-1) cell holds two or more distinct grid
+    positions (a cell splits only then); {level: (prefix, count, sums)}."""
+    _, key = _grid64(z, r)
+    out = {}
+    for l in range(33):
+        pre = key >> np.uint64(2 * (32 - l))
+        if l == 0:
+            keep = np.ones(len(z), bool)
+        else:
+            par = key >> np.uint64(2 * (33 - l))
+            distinct = {}
+            for p, k in zip(par.tolist(), key.tolist()):
+                distinct.setdefault(p, set()).add(k)
+            keep = np.array([len(distinct[p]) >= 2 for p in par.tolist()])
+        if not keep.any():
+            break
+        up, inv = np.unique(pre[keep], return_inverse=True)
+        sm = np.array([[math.fsum(z[keep][inv == c, 0]), math.fsum(z[keep][inv == c, 1])]
+                       for c in range(up.size)])
+        out[l] = (up, np.bincount(inv), sm)
+    return out
+
+
+@pytest.mark.parametrize("gen", ["clustered", "duplicates"])
+def test_dtree_matches_bruteforce(orc, gen):
+    r, n = 64, 300
+    z = datagen.clustered_pixels(n, r, seed=41, n_clusters=3, spread=0.002)
+    if gen == "duplicates":
+        z[10:20] = z[10]                    # exact duplicates share one leaf
+        z[30:33] = z[30] + 1e-12            # closer than the 2^32 grid: likewise
+    tree = orc.Tree(z, r, kind=1)
+    ref = _dtree_cells(z, r)
+    sizes = tree.level_sizes()
+    assert len(sizes) == 33
+    for l in range(33):
+        if l not in ref:
+            assert sizes[l] == 0
+            continue
+        pre, cnt, sm = tree.level(l)
+        up, rc, rs = ref[l]
+        assert np.array_equal(pre, up), l
+        assert np.array_equal(cnt, rc), l
+        np.testing.assert_allclose(sm, rs, rtol=1e-15, atol=0)
+    # tight clusters split below the pixel level: deeper than the screen's L = 6
+    assert max(ref) > 12
+
+
+def test_dtree_theta0_is_exact_repulsion(orc):
+    """At theta = 0 every point's walk reaches single-point leaves (any
+    positions, no pixel alignment needed): the repulsion and Z_i equal the
+    exact O(n^2) sums of the textbook gradient."""
+    r, n = 256, 150
+    z = datagen.clustered_pixels(n, r, seed=43, n_clusters=4, spread=0.01)
+    beta = np.array([0.03, 0.05]) ** 2
+    R, Zi, _ = orc.Tree(z, r, kind=1).repulsion(beta, 0.0)
+    d = z[:, None, :] - z[None, :, :]
+    w = 1.0 / (1.0 + beta[0] * d[..., 0] ** 2 + beta[1] * d[..., 1] ** 2)
+    np.fill_diagonal(w, 0.0)
+    np.testing.assert_allclose(Zi, w.sum(1), rtol=1e-12)
+    Rx = (w * w * d[..., 0]).sum(1)
+    Ry = (w * w * d[..., 1]).sum(1)
+    np.testing.assert_allclose(R, np.stack([Rx, Ry], 1), rtol=1e-10, atol=1e-14 * np.abs(Rx).max())
+
+
+def _bh_python_dtree(z, r, beta, theta):
+    """Depth-first Barnes-Hut over the D-Quadtree written from its definition:
+    a cell of level l spans 2^(32-l) grid units (2^(L-l) pixels); it is a
+    leaf when its points occupy one grid position, else it opens into its
+    occupied quadrants (children 2 ybit + xbit, in order)."""
+    L = int(round(math.log2(r)))
+    n = len(z)
+    q, _ = _grid64(z, r)
+    q = q.astype(object)
+    b1, b2 = beta
+    R = np.zeros((n, 2)); Zi = np.zeros(n); vis = np.zeros(n, int)
+
+    def visit(i, level, x0, y0, mem):
+        if not mem:
+            return
+        vis[i] += 1
+        span = 2 ** (32 - level)
+        w = 2.0 ** (L - level)
+        if len({(q[j, 0], q[j, 1]) for j in mem}) == 1:
+            use = [j for j in mem if j != i]
+            if not use:
+                return
+            m = len(use)
+            c = np.array([math.fsum(z[use, 0]), math.fsum(z[use, 1])]) / m
+        else:
+            m = len(mem)
+            c = np.array([math.fsum(z[mem, 0]), math.fsum(z[mem, 1])]) / m
+            dz = z[i] - c
+            d2 = b1 * dz[0] ** 2 + b2 * dz[1] ** 2
+            if not (w * w * (b1 + b2) < theta * theta * d2):
+                h = span // 2
+                for k in range(4):
+                    cx, cy = x0 + (k & 1) * h, y0 + (k >> 1) * h
+                    sub = [j for j in mem if cx <= q[j, 0] < cx + h and cy <= q[j, 1] < cy + h]
+                    visit(i, level + 1, cx, cy, sub)
+                return
+        dz = z[i] - c
+        qq = 1.0 / (1.0 + b1 * dz[0] ** 2 + b2 * dz[1] ** 2)
+        Zi[i] += m * qq
+        R[i] += m * qq * qq * dz
+
+    for i in range(n):
+        visit(i, 0, 0, 0, list(range(n)))
+    return R, Zi, vis
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.9])
+def test_dtree_traversal_bruteforce(orc, theta):
+    r, n = 32, 90
+    z = datagen.clustered_pixels(n, r, seed=45, n_clusters=3, spread=0.004)
+    z[5:8] = z[5]                                          # a shared leaf
+    beta = np.array([0.37, 0.22])
+    R, Zi, vis = orc.Tree(z, r, kind=1).repulsion(beta, theta)
+    Rp, Zp, vp = _bh_python_dtree(z, r, beta, theta)
+    assert np.array_equal(vis, vp)
+    np.testing.assert_allclose(Zi, Zp, rtol=1e-13)
+    np.testing.assert_allclose(R, Rp, rtol=1e-11, atol=1e-13 * np.abs(Rp).max())
+
+
+def test_dtree_visits_more_cells_than_ptree(orc):
+    """The paper's point (Section 4.1): the pixel tree stops at pixels, the
+    data tree keeps splitting inside dense regions, so at the same theta a
+    walk on the data tree reaches more cells, while the two forces stay close
+    (both approximate the same exact sum)."""
+    r, n = 256, 3000
+    z = datagen.clustered_pixels(n, r, seed=47, n_clusters=6, spread=0.02)
+    beta = np.array([0.02, 0.02]) ** 2
+    Rp, Zp, vp = orc.Tree(z, r).repulsion(beta, 0.5)
+    Rd, Zd, vd = orc.Tree(z, r, kind=1).repulsion(beta, 0.5)
+    assert vd.mean() > vp.mean()
+    assert np.linalg.norm(Rd - Rp) <= 0.05 * np.linalg.norm(Rd)
