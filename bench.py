@@ -333,13 +333,16 @@ def time_to_kl(ctx_train, X_train, mix, args):
 
 
 def r_sweep(args):
-    """The benchmark's FP32 workload (1,000,000 x 128 mixture, perplexity 50)
-    at screen sizes 512 ... 65,536: wall time per iteration over `--steps`
-    iterations after `--warmup`, the exact-Z KL at the end, mean visited cells
-    per point and the number of cells.  At r = 65,536 (16 levels) nearly every
-    point has a leaf of its own, so the same kernels approximate a quadtree
-    split down to single points over the data's bounding box (the screen spans
-    it).  Setup (kNN, P) runs for every r and is not timed."""
+    """The paper's central comparison (Section 4.1, Fig. 3, Table 5) on the
+    benchmark's FP32 workload (1,000,000 x 128 mixture, perplexity 50): the
+    pixel-aligned P-Quadtree at screen sizes r = 512 ... 8,192 against the
+    data-driven D-Quadtree of Barnes-Hut-SNE (root on the data, cells split
+    until each leaf holds one point, rebuilt every iteration), both walked by
+    the same traversal.  Per configuration: wall time per iteration over
+    `--steps` iterations after `--warmup` (graph replay), the pass times of
+    20 further iterations, mean visited cells per point, the number of cells
+    and the exact-Z KL at the end.  Setup (kNN, P) runs for each
+    configuration and is not timed."""
     import torch
 
     from paper_1611_02568_amd import datagen, pixelsne
@@ -350,21 +353,23 @@ def r_sweep(args):
     y0 = torch.as_tensor(datagen.initial_embedding(n, seed=datagen.seed_for(2, 1)))
     Xd = torch.from_numpy(X).cuda()
     out = []
-    for r in (512, 1024, 2048, 4096, 8192, 16384, 65536):
-        ctx = pixelsne.Context.from_data(Xd, 50.0, r, Y_init=y0, precision=pixelsne.FP32)
+    configs = [("pixel", r) for r in (512, 1024, 2048, 4096, 8192)] + [("data", 2048)]
+    for tree, r in configs:
+        ctx = pixelsne.Context.from_data(Xd, 50.0, r, Y_init=y0, precision=pixelsne.FP32,
+                                         tree=pixelsne.TREE_DATA if tree == "data"
+                                         else pixelsne.TREE_PIXEL)
         ctx.step(args.warmup)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ctx.step_async(args.steps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        ms, _ = timed_window(ctx, args.steps, profiled=False)
+        _, pt = timed_window(ctx, 20)
+        per = {k[:-3]: round(v / 20, 4) for k, v in pt.items() if k.endswith("_ms")}
         g = ctx.gradient(1.0)
-        row = {"r": r, "levels": ctx.stats().L, "ms_per_iter": ms, "kl": ctx.kl(),
-               "mean_visits": g["visits"].double().mean().item(),
-               "cells": ctx.stats().n_nodes}
-        log(f"[bench] r-sweep {json.dumps(row)}")
+        st = ctx.stats()
+        row = {"tree": tree, "r": r, "ms_per_iter": ms / args.steps,
+               "iterations": [args.warmup + 1, args.warmup + args.steps],
+               "pass_ms_after": per, "tree_build_ms": per["snap"] + per["sort"] + per["tree"],
+               "kl": ctx.kl(), "mean_visits": g["visits"].double().mean().item(),
+               "cells": st.n_nodes}
+        log(f"[bench] tree sweep {json.dumps(row)}")
         out.append(row)
         del ctx, g
     return out
@@ -574,8 +579,8 @@ def main():
                     help="run only the 5M time-to-KL experiment and print its own JSON line")
     ap.add_argument("--large-n", type=int, default=5_000_000)
     ap.add_argument("--r-sweep", action="store_true",
-                    help="run only the screen-size sweep (r = 512 ... 65,536) on the FP32 "
-                         "workload and print its own JSON line")
+                    help="run only the tree comparison (pixel tree at r = 512 ... 8,192 and the "
+                         "data-driven tree) on the FP32 workload and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is "
@@ -584,8 +589,8 @@ def main():
 
     if args.r_sweep:
         res = r_sweep(args)
-        print(json.dumps({"metric": "ms per iteration and exact-Z KL after 1,000 iterations "
-                                    "against screen size r",
+        print(json.dumps({"metric": "ms per iteration and exact-Z KL, pixel-aligned tree at "
+                                    "screen sizes r against the data-driven tree",
                           "unit": "ms", "higher_is_better": False, "n_gpus": 1,
                           "data": "synthetic", "dtype": "f32", "steps": args.steps,
                           "warmup": args.warmup, "result": res}), flush=True)

@@ -55,6 +55,14 @@ enum { PSNE_FP32 = 0, PSNE_FP64 = 1 };
 /* Representative point of a cell: centre of mass of its members (Eq. 8), or
  * the geometric centre of the cell (Section 4.1, iteration-independent). */
 enum { PSNE_COM_MASS = 0, PSNE_COM_CELL_CENTER = 1 };
+/* The Barnes-Hut tree: the pixel-aligned P-Quadtree of PixelSNE (Section 4.1:
+ * fixed depth log2 r, unit-pixel leaves), or Barnes-Hut-SNE's data-driven
+ * D-Quadtree (Section 3.3, Eq. 9-10: the root spans the data, cells split
+ * until each leaf holds one point; here on a 2^32 x 2^32 grid over the root,
+ * levels 0..32, so points in one grid cell share a leaf), rebuilt every
+ * iteration, walked by the same traversal.  PSNE_TREE_DATA requires
+ * PSNE_COM_MASS. */
+enum { PSNE_TREE_PIXEL = 0, PSNE_TREE_DATA = 1 };
 /* Element type of the input matrix X. */
 enum { PSNE_X_F32 = 0, PSNE_X_F64 = 1, PSNE_X_U8 = 2 };
 /* Output frames of pixelsne_get_Y. */
@@ -111,6 +119,7 @@ typedef struct {
                                  (w*w)*(b1+b2) < th2*((b1*dx)*dx + (b2*dy)*dy), no fused
                                  multiply-add [0].  1: the test and the distances in FP64
                                  (the FP64 path always does this). */
+    int32_t tree;             /* PSNE_TREE_PIXEL | PSNE_TREE_DATA [PIXEL] */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -250,6 +259,21 @@ psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, v
 psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uint32_t* keys,
                                  uint32_t* perm, uint32_t* prefix, uint32_t* count,
                                  double* sum);
+
+/*
+ * Export the data-driven tree (PSNE_TREE_DATA) built by the last
+ * pixelsne_gradient / iteration; PSNE_E_INVAL for the pixel tree.
+ *   level_size host int64 [33] (always written), levels 0..32
+ *   keys   device uint64 [n]   64-bit grid Morton keys in sorted order
+ *   perm   device uint32 [n]   point index at each sorted position
+ *   prefix device uint64 [n_nodes] (key >> 2 (32 - level)), count device
+ *   uint32 [n_nodes], sum device float64 [n_nodes][2]: cells of level 0, 1,
+ *   ..., 32, each level ascending by prefix.
+ * Pass NULL device pointers to query level_size only.  Synchronises.
+ */
+psne_status pixelsne_export_tree64(const pixelsne_ctx* c, int64_t* level_size, uint64_t* keys,
+                                   uint32_t* perm, uint64_t* prefix, uint32_t* count,
+                                   double* sum);
 
 /* Export P: *nnz (host) always; row_ptr int64 [n+1], col int32 [nnz],
  * val float64 [nnz] device pointers may be NULL.  Synchronises. */

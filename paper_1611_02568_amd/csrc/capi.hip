@@ -65,6 +65,11 @@ psne_status check_params(const pixelsne_params* p) {
     if (p->graphs != 0 && p->graphs != 1) return invalid("graphs must be 0 or 1");
     if (p->data_order != 0 && p->data_order != 1) return invalid("data_order must be 0 or 1");
     if (p->opening_fp64 != 0 && p->opening_fp64 != 1) return invalid("opening_fp64 must be 0 or 1");
+    if (p->tree != PSNE_TREE_PIXEL && p->tree != PSNE_TREE_DATA) return invalid("unknown tree");
+    if (p->tree == PSNE_TREE_DATA && p->com_mode != PSNE_COM_MASS) {
+        set_error("the data-driven tree takes centres of mass only (PSNE_COM_MASS)");
+        return PSNE_E_UNSUPPORTED;
+    }
     return PSNE_OK;
 }
 
@@ -118,8 +123,10 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &c->mm_part, sizeof(double) * 4 * c->mm_n)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->sc, sizeof(DevScalars))) != hipSuccess) return e;
     TreeBufs& tb = c->tb;
+    const bool dtree = c->prm.tree == PSNE_TREE_DATA;
+    const int lmax = dtree ? kDLevels : c->L;       // deepest level of the tree
     int64_t mx = 0;
-    for (int l = 0; l <= c->L; l++) {
+    for (int l = 0; l <= lmax; l++) {
         const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : n;
         mx += cap < n ? cap : n;
     }
@@ -136,8 +143,13 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     }
     if ((e = dalloc(c, &tb.hist, 4 * 256 * (size_t)tb.sort_blocks)) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.dtot, 4 * 256)) != hipSuccess) return e;
-    if ((e = dalloc(c, &tb.lvl_cnt, 4 * (size_t)(c->L + 1) * tb.tree_blocks)) != hipSuccess) return e;
-    if ((e = dalloc(c, &tb.ltot, 4 * (size_t)(c->L + 1))) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.lvl_cnt, 4 * (size_t)(lmax + 1) * tb.tree_blocks)) != hipSuccess) return e;
+    if ((e = dalloc(c, &tb.ltot, 4 * (size_t)(lmax + 1))) != hipSuccess) return e;
+    if (dtree) {
+        for (int h = 0; h < 2; h++)
+            if ((e = dalloc(c, &tb.key64[h], 8 * (size_t)n)) != hipSuccess) return e;
+        if ((e = dalloc(c, &tb.cursor, 4 * (size_t)(mx + 1))) != hipSuccess) return e;
+    }
     if ((e = dalloc(c, &tb.wfirst, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.wlast, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.first_child, 4 * (size_t)mx)) != hipSuccess) return e;
@@ -290,6 +302,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->graphs = 1;
     p->reorder_growth = 2.0;
     p->opening_fp64 = 0;
+    p->tree = PSNE_TREE_PIXEL;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -564,6 +577,7 @@ psne_status pixelsne_gradient(pixelsne_ctx* c, double alpha, void* B, void* A, v
 psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uint32_t* keys,
                                  uint32_t* perm, uint32_t* prefix, uint32_t* count, double* sum) {
     if (!c || !level_size) return invalid("null argument");
+    if (c->prm.tree != PSNE_TREE_PIXEL) return invalid("pixelsne_export_tree64 exports the data-driven tree");
     const void* ptrs[5] = {keys, perm, prefix, count, sum};
     for (const void* p : ptrs)
         if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
@@ -575,6 +589,25 @@ psne_status pixelsne_export_tree(const pixelsne_ctx* c, int64_t* level_size, uin
     e = run_export_tree(c, keys, perm, prefix, count, sum);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_tree");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_export_tree64(const pixelsne_ctx* c, int64_t* level_size, uint64_t* keys,
+                                   uint32_t* perm, uint64_t* prefix, uint32_t* count,
+                                   double* sum) {
+    if (!c || !level_size) return invalid("null argument");
+    if (c->prm.tree != PSNE_TREE_DATA) return invalid("the context does not build the data-driven tree");
+    const void* ptrs[5] = {keys, perm, prefix, count, sum};
+    for (const void* p : ptrs)
+        if (p && !is_device_ptr(p)) return invalid("outputs must be device pointers");
+    DevScalars h;
+    hipError_t e = hipMemcpyAsync(&h, c->sc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_tree64");
+    for (int l = 0; l <= kDLevels; l++) level_size[l] = h.level_size[l];
+    e = run_export_dtree(c, keys, perm, prefix, count, sum);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "export_tree64");
     return PSNE_OK;
 }
 

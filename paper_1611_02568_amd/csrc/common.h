@@ -10,6 +10,10 @@ namespace psne {
 
 constexpr int kWave = 64;
 constexpr int kMaxLevels = 17;          // L <= 16 (r <= 65536): levels 0..16
+// The data-driven tree (Barnes-Hut-SNE's D-Quadtree) splits down to single
+// points on a 2^32 x 2^32 grid over the screen: levels 0..32, 64-bit keys.
+constexpr int kDLevels = 32;
+constexpr int kMaxLevelsAll = kDLevels + 1;
 
 // Row chunks of the attraction pass: at most kChunkRows rows; a chunk of more
 // than one row holds fewer than kChunkMaxNnz nonzeros.  Columns are packed
@@ -30,8 +34,8 @@ struct DevScalars {
     int32_t nonfinite;  // set when a non-finite position appears
     int64_t n_nodes;    // occupied cells of the last tree
     int64_t n_chunks;   // row chunks of the attraction's copy of P
-    uint32_t level_size[kMaxLevels];
-    uint32_t level_base[kMaxLevels + 1];
+    uint32_t level_size[kMaxLevelsAll];
+    uint32_t level_base[kMaxLevelsAll + 1];
 };
 
 // One quadtree cell as the traversal reads it (32 bytes, one scalar load).

@@ -29,6 +29,11 @@ struct TreeBufs {
     double2* nsum = nullptr;                 // [max_nodes] coordinate sums (FP64)
     uint32_t* leaf_of = nullptr;             // [n] leaf cell of each sorted position
     void* zs = nullptr;                      // [n][2] positions in sorted order (state type)
+    // data-driven tree only
+    uint64_t* key64[2] = {nullptr, nullptr}; // 64-bit grid Morton keys (sort ping-pong)
+    uint32_t* cursor = nullptr;              // [max_nodes + 1] first cell of the next level at
+                                             // or after a cell's start: its children are
+                                             // [cursor[g], cursor[g + 1])
 };
 
 }  // namespace psne
@@ -116,6 +121,15 @@ bool is_device_ptr(const void* p);
 // iteration passes (iter.hip); each enqueues on c->stream
 hipError_t run_snap(pixelsne_ctx* c);
 hipError_t run_sort(pixelsne_ctx* c);
+// the data-driven tree (dtree.hip): snap with 64-bit grid keys, their sort,
+// and the cells; run_snap / run_sort / run_tree call these in that mode
+hipError_t run_snap_dtree(pixelsne_ctx* c);
+hipError_t run_sort_dtree(pixelsne_ctx* c);
+hipError_t run_tree_dtree(pixelsne_ctx* c);
+hipError_t run_export_dtree(const pixelsne_ctx* c, uint64_t* keys, uint32_t* perm,
+                            uint64_t* prefix, uint32_t* count, double* sum);
+// exclusive scan of each row of a [rows][len] uint32 array in place; row totals to tot
+hipError_t run_rows_scan(uint32_t* a, int64_t rows, int64_t len, uint32_t* tot, hipStream_t s);
 // stable sort of (tb.key[0], index) on the low `bits` key bits
 hipError_t run_sort_bits(pixelsne_ctx* c, int bits);
 hipError_t run_tree(pixelsne_ctx* c);

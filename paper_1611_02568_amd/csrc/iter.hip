@@ -553,10 +553,41 @@ __device__ __forceinline__ void push_entry(int& a, int& b, int& c, int& d, int v
         : "s"(va), "s"(vb), "s"(vc), "s"(vd), "{m0}"(sel));
 }
 
+// The traversal's stack: entry k (a sibling group: its first cell, size and
+// level, and the 64-bit mask of lanes that descend into it) lives in lane k of
+// four registers.  A walk pushes at most three pending groups per level plus
+// the one it expands next, so 3 (levels) + 1 entries suffice: 52 for the pixel
+// tree (at most 17 levels), 100 for the data-driven tree (33 levels), which
+// takes a second set of four registers for entries 64..127 (DEEP).
+template <bool DEEP>
+struct WaveStack {
+    int f0 = 0, i0 = 0, lo0 = 0, hi0 = 0;
+    int f1 = 0, i1 = 0, lo1 = 0, hi1 = 0;
+    __device__ __forceinline__ void push(int sp, int f, int info, int lo, int hi) {
+        if (!DEEP || sp < kWave) push_entry(f0, i0, lo0, hi0, f, info, lo, hi, sp);
+        else push_entry(f1, i1, lo1, hi1, f, info, lo, hi, sp - kWave);
+    }
+    __device__ __forceinline__ void read(int sp, uint32_t& first, uint32_t& info,
+                                         uint64_t& mask) const {
+        if (!DEEP || sp < kWave) {
+            first = (uint32_t)__builtin_amdgcn_readlane(f0, sp);
+            info = (uint32_t)__builtin_amdgcn_readlane(i0, sp);
+            mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi0, sp) << 32) |
+                   (uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo0, sp);
+        } else {
+            const int k = sp - kWave;
+            first = (uint32_t)__builtin_amdgcn_readlane(f1, k);
+            info = (uint32_t)__builtin_amdgcn_readlane(i1, k);
+            mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(hi1, k) << 32) |
+                   (uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo1, k);
+        }
+    }
+};
+
 // F32T (FP32 path only): the opening test and the distances in FP32 on the
 // cells' FP32 copies (cells32), operands and operations rounded as the FP64
 // test's expression written in single precision; otherwise in FP64 on nodes.
-template <typename T, bool COUNT, bool F32T>
+template <typename T, bool COUNT, bool F32T, bool DEEP>
 __global__ __launch_bounds__(kBlock) void k_traverse(
     const Node* __restrict__ nodes, const CellF* __restrict__ cells32,
     const double2* __restrict__ nsum, const T* __restrict__ zs,
@@ -585,22 +616,20 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     T rx = T(0), ry = T(0);
     uint32_t nvis = 0, nuse = 0;
 
-    // Stack entry k lives in lane k of these registers: first cell of a
-    // sibling group, (group size | level << 8), lane mask (lo, hi).
-    int st_first = 0, st_info = 0, st_mlo = 0, st_mhi = 0;
+    // stack entries: first cell of a sibling group, (group size | level << 8),
+    // lane mask (lo, hi)
+    WaveStack<DEEP> st;
     int sp = 0;
     const uint64_t m0 = ballot64(valid);
     if (m0) {
-        push_entry(st_first, st_info, st_mlo, st_mhi, 0, 1, (int)(uint32_t)m0,
-                   (int)(uint32_t)(m0 >> 32), 0);
+        st.push(0, 0, 1, (int)(uint32_t)m0, (int)(uint32_t)(m0 >> 32));
         sp = 1;
     }
     while (sp > 0) {
         sp--;
-        const uint32_t first = (uint32_t)__builtin_amdgcn_readlane(st_first, sp);
-        const uint32_t info = (uint32_t)__builtin_amdgcn_readlane(st_info, sp);
-        const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(st_mhi, sp) << 32) |
-                              (uint64_t)(uint32_t)__builtin_amdgcn_readlane(st_mlo, sp);
+        uint32_t first, info;
+        uint64_t mask;
+        st.read(sp, first, info, mask);
         const uint32_t nsib = info & 0xFFu;
         const int level = (int)(info >> 8);
         const bool act = __builtin_amdgcn_inverse_ballot_w64(mask);   // lane in mask
@@ -616,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 const uint32_t c = first + q;
                 const CellF nd = grp[q];
                 uint64_t om = 0;
-                if (level < L) {
+                if (nd.child != 0u) {
                     const float dx = zxf - nd.cx, dy = zyf - nd.cy;
                     const float d2 = dist2f(b1f, b2f, dx, dy);
                     const bool near = !(diag2f < mulf_nc(th2f, d2));
@@ -649,9 +678,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                     }
                 }
                 if (om) {
-                    push_entry(st_first, st_info, st_mlo, st_mhi, (int)(nd.child & 0x3FFFFFFFu),
-                               (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
-                               (int)(uint32_t)om, (int)(uint32_t)(om >> 32), sp);
+                    st.push(sp, (int)(nd.child & 0x3FFFFFFFu),
+                            (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
+                            (int)(uint32_t)om, (int)(uint32_t)(om >> 32));
                     sp++;
                 }
             }
@@ -670,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             // Every lane evaluates the term; lanes that do not take the cell
             // add it with mass 0, which leaves their sums bit for bit as they
             // were and keeps the loop free of divergent branches.
-            if (level < L) {
+            if (nd.child != 0u) {
                 // inner cell: the opening test and, for lanes that accept, the
                 // force term share one distance
                 const double dx = zx - nd.cx, dy = zy - nd.cy;
@@ -707,9 +736,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 }
             }
             if (om) {
-                push_entry(st_first, st_info, st_mlo, st_mhi, (int)(nd.child & 0x3FFFFFFFu),
-                           (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
-                           (int)(uint32_t)om, (int)(uint32_t)(om >> 32), sp);
+                st.push(sp, (int)(nd.child & 0x3FFFFFFFu),
+                        (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
+                        (int)(uint32_t)om, (int)(uint32_t)(om >> 32));
                 sp++;
             }
         }
@@ -1306,6 +1335,7 @@ StepParams step_params(const pixelsne_ctx* c, double alpha) {
 int64_t attract_block_count(int64_t n) { return attract_blocks(n); }
 
 hipError_t run_snap(pixelsne_ctx* c) {
+    if (c->prm.tree == PSNE_TREE_DATA) return run_snap_dtree(c);
     if (fp64(c))
         k_snap<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             (const double*)c->zh, (double*)c->z, c->tb.key[0], c->tb.idx[0], c->sc, c->n, c->r);
@@ -1315,7 +1345,15 @@ hipError_t run_snap(pixelsne_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t run_sort(pixelsne_ctx* c) { return run_sort_bits(c, 2 * c->L); }
+hipError_t run_sort(pixelsne_ctx* c) {
+    if (c->prm.tree == PSNE_TREE_DATA) return run_sort_dtree(c);
+    return run_sort_bits(c, 2 * c->L);
+}
+
+hipError_t run_rows_scan(uint32_t* a, int64_t rows, int64_t len, uint32_t* tot, hipStream_t s) {
+    k_rows_scan<<<dim3((unsigned)rows), kBlock, 0, s>>>(a, len, tot);
+    return hipGetLastError();
+}
 
 hipError_t run_sort_bits(pixelsne_ctx* c, int bits) {
     TreeBufs& tb = c->tb;
@@ -1337,6 +1375,7 @@ hipError_t run_sort_bits(pixelsne_ctx* c, int bits) {
 }
 
 hipError_t run_tree(pixelsne_ctx* c) {
+    if (c->prm.tree == PSNE_TREE_DATA) return run_tree_dtree(c);
     TreeBufs& tb = c->tb;
     const uint32_t* keys = tb.key[tb.sorted];
     const uint32_t* perm = tb.idx[tb.sorted];
@@ -1377,9 +1416,14 @@ hipError_t run_tree(pixelsne_ctx* c) {
 template <typename T, bool COUNT, bool F32T>
 void launch_traverse(pixelsne_ctx* c, double th2, uint32_t* visits, uint32_t* used, double* Zi) {
     TreeBufs& tb = c->tb;
-    k_traverse<T, COUNT, F32T><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-        tb.nodes, tb.cells32, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc,
-        c->n, c->L, th2, c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
+    if (c->prm.tree == PSNE_TREE_DATA)
+        k_traverse<T, COUNT, F32T, true><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            tb.nodes, tb.cells32, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc,
+            c->n, c->L, th2, c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
+    else
+        k_traverse<T, COUNT, F32T, false><<<grid_for(c->n), kBlock, 0, c->stream>>>(
+            tb.nodes, tb.cells32, tb.nsum, (const T*)tb.zs, tb.idx[tb.sorted], tb.leaf_of, c->sc,
+            c->n, c->L, th2, c->prm.com_mode, (T*)c->R, c->zpart, c->orig, Zi, visits, used);
 }
 
 hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi) {

@@ -19,6 +19,7 @@ PSNE_E_NUMERIC, PSNE_E_STATE, PSNE_E_UNSUPPORTED = -4, -5, -6
 FP32, FP64 = 0, 1
 COM_MASS, COM_CELL_CENTER = 0, 1
 X_F32, X_F64, X_U8 = 0, 1, 2
+TREE_PIXEL, TREE_DATA = 0, 1
 FRAME_PIXEL, FRAME_SCREEN, FRAME_Y = 0, 1, 2
 
 _STATUS = {PSNE_E_INVAL: "invalid argument", PSNE_E_NOMEM: "out of device memory",
@@ -45,6 +46,7 @@ class Params(C.Structure):
         ("graphs", C.c_int32),
         ("reorder_growth", C.c_double),
         ("opening_fp64", C.c_int32),
+        ("tree", C.c_int32),
     ]
 
 
@@ -97,6 +99,7 @@ SIGNATURES = {
                                     C.POINTER(C.c_double)]),
     "pixelsne_export_tree": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
     "pixelsne_export_P": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp]),
+    "pixelsne_export_tree64": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
     "pixelsne_knn": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "pixelsne_perplexity": (C.c_int, [_vp, _i64, _i32, _d, _vp, _vp, _vp]),
     "pixelsne_mlp_create": (_vp, [_i32, _i32, _i32, _u64, _vp]),
@@ -295,6 +298,24 @@ class Context:
         s2 = (C.c_int64 * (L + 1))()
         _check(load().pixelsne_export_tree(self._h, s2, _ptr(keys), _ptr(perm), _ptr(pre),
                                            _ptr(cnt), _ptr(sm)))
+        return {"level_size": sizes, "keys": keys, "perm": perm, "prefix": pre[:m],
+                "count": cnt[:m], "sum": sm[:m]}
+
+    def export_tree64(self):
+        """The data-driven tree (TREE_DATA): level sizes 0..32, 64-bit keys,
+        permutation, prefixes, counts and sums, as export_tree."""
+        sizes = (C.c_int64 * 33)()
+        _check(load().pixelsne_export_tree64(self._h, sizes, None, None, None, None, None))
+        sizes = [sizes[i] for i in range(33)]
+        m = sum(sizes)
+        keys = torch.empty(self.n, dtype=torch.int64, device="cuda")
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        pre = torch.empty(max(m, 1), dtype=torch.int64, device="cuda")
+        cnt = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        sm = torch.empty((max(m, 1), 2), dtype=torch.float64, device="cuda")
+        s2 = (C.c_int64 * 33)()
+        _check(load().pixelsne_export_tree64(self._h, s2, _ptr(keys), _ptr(perm), _ptr(pre),
+                                             _ptr(cnt), _ptr(sm)))
         return {"level_size": sizes, "keys": keys, "perm": perm, "prefix": pre[:m],
                 "count": cnt[:m], "sum": sm[:m]}
 
