@@ -120,6 +120,11 @@ typedef struct {
                                  multiply-add [0].  1: the test and the distances in FP64
                                  (the FP64 path always does this). */
     int32_t tree;             /* PSNE_TREE_PIXEL | PSNE_TREE_DATA [PIXEL] */
+    int32_t knn_trees;        /* pixelsne_init_ex: 0 = exact brute-force kNN [0]; > 0 =
+                                 the approximate kNN of pixelsne_knn_approx with this many
+                                 random-projection trees (Section 4.3) */
+    int32_t knn_leaf;         /* its leaf size, >= 2k + 2; 0 => 2k + 2 [0] */
+    int32_t knn_explore;      /* its rounds of neighbour exploring [1] */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -366,6 +371,25 @@ psne_status pixelsne_neighborhood_precision(const pixelsne_ctx* c, const int32_t
  */
 psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
                          int32_t* idx, double* d2, void* stream);
+
+/*
+ * Approximate k nearest neighbours (Section 4.3, the K-NNG of LargeVis):
+ * `trees` random-projection trees (a range of more than leaf_size points
+ * splits by the hyperplane halfway between two of its points drawn from the
+ * seed; cut in the middle when a side would get fewer than k + 1 points)
+ * give each point its leaf mates as candidates; then `explore` rounds
+ * replace each point's list by the best k of its list and its neighbours'
+ * lists.  Lists keep the best k by (squared distance in FP64, index),
+ * distinct, self excluded; all decisions in FP64, so the result is a
+ * deterministic function of X and the seed.
+ *   X device [n][D] of x_dtype; idx device int32 [n][k], d2 device float64
+ *   [n][k] ascending.  1 <= k <= min(n - 1, 256), trees >= 1, explore >= 0,
+ *   leaf_size >= 2k + 2 (0 => 2k + 2), n < 2^31.  Allocates its work
+ *   buffers (about 24 n k bytes).  Synchronises.
+ */
+psne_status pixelsne_knn_approx(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
+                                int32_t trees, int32_t leaf_size, int32_t explore,
+                                uint64_t seed, int32_t* idx, double* d2, void* stream);
 
 /*
  * Per-row Gaussian calibration (Section 3.2): for each row find b_i with

@@ -49,6 +49,8 @@ def _load():
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_num_threads.argtypes = [C.c_int]
     lib.orc_knn.argtypes = [_dp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, _i32p, _dp]
+    lib.orc_knn_approx.argtypes = [_dp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_int32, C.c_uint64, _i32p, _dp]
     lib.orc_perplexity.argtypes = [_dp, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                    _dp, _dp, _i32p]
     lib.orc_symmetrize.restype = C.c_int64
@@ -125,6 +127,21 @@ def knn(X, k: int, rows=None):
     idx = np.empty((m, k), np.int32)
     d2 = np.empty((m, k), np.float64)
     _check(_load().orc_knn(X, n, D, k, rp, m, idx, d2), "knn")
+    return idx, d2
+
+
+def knn_approx(X, k: int, n_trees: int = 4, leaf_size: int | None = None, explore: int = 1,
+               seed: int = 0):
+    """Approximate kNN of Section 4.3 (random-projection trees, then rounds of
+    neighbours of neighbours); leaf_size (>= 2k + 2) defaults to 2k + 2.
+    Returns (idx int32 [n,k], d2 float64 [n,k]) ascending by (d2, index)."""
+    X = _f64(X)
+    n, D = X.shape
+    leaf = 2 * k + 2 if leaf_size is None else int(leaf_size)
+    idx = np.empty((n, k), np.int32)
+    d2 = np.empty((n, k), np.float64)
+    _check(_load().orc_knn_approx(X, n, D, k, int(n_trees), leaf, int(explore),
+                                  int(seed) & (2 ** 64 - 1), idx, d2), "knn_approx")
     return idx, d2
 
 

@@ -140,6 +140,188 @@ int orc_knn(const double* X, int64_t n, int32_t D, int32_t k, const int64_t* row
 }
 
 /* ------------------------------------------------------------------ */
+/* Approximate k nearest neighbours (Section 4.3: the K-NNG of          */
+/* LargeVis): a few random-projection trees give every point candidate  */
+/* neighbours (the other points of its leaf); then, since the neighbours */
+/* of a point's neighbours are likely its neighbours too, a few rounds   */
+/* replace each point's list by the best k of the list and its          */
+/* neighbours' lists (every round reads the previous round's lists).    */
+/*                                                                      */
+/* A tree splits a set of points (a range of a permutation, in order)   */
+/* by the hyperplane halfway between two of its points a and b, chosen  */
+/* by a counter-based generator: point i goes right iff                 */
+/*   sum_d (x_id - (x_ad + x_bd) / 2) (x_ad - x_bd) > 0                 */
+/* (FP64, terms in order of d, no fused multiply-add); the split keeps   */
+/* the order inside each side.  If a side would hold fewer than k + 1    */
+/* points (equal points, or a plane near the edge), or below level 48,   */
+/* the range is cut in the middle instead, so that with leaf_size >=     */
+/* 2k + 2 every leaf offers each of its points at least k candidates.    */
+/* Ranges of at most leaf_size points are leaves.  The generator is     */
+/* SplitMix64 (Steele, Lea and Flood, 2014) keyed by seed, tree, level  */
+/* and the range's first position: a = h0 mod m, b = h1 mod (m - 1),     */
+/* b += 1 if b >= a.  Lists are the best k by (d^2, index), distinct,   */
+/* self excluded.                                                       */
+/* ------------------------------------------------------------------ */
+static inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+static uint64_t rp_draw(uint64_t seed, int32_t tree, int32_t level, int64_t a, int which) {
+    uint64_t x = splitmix64(seed ^ (uint64_t)(uint32_t)tree);
+    x = splitmix64(x ^ (uint64_t)(uint32_t)level);
+    return splitmix64(x ^ (((uint64_t)a << 1) | (uint64_t)which));
+}
+
+static double sqdist(const double* X, int32_t D, int64_t i, int64_t j) {
+    const double* a = X + i * (int64_t)D;
+    const double* b = X + j * (int64_t)D;
+    double s = 0.0;
+    for (int t = 0; t < D; t++) { double e = a[t] - b[t]; s += e * e; }
+    return s;
+}
+
+/* keep the best k of a sorted list (ascending (d, j)); no duplicates */
+static void list_insert(double* ld, int32_t* lj, int32_t* m, int32_t k, double d, int32_t j) {
+    if (*m == k && !knn_less(d, j, ld[k - 1], lj[k - 1])) return;
+    for (int32_t q = 0; q < *m; q++) if (lj[q] == j) return;
+    int32_t pos = *m < k ? *m : k - 1;
+    while (pos > 0 && knn_less(d, j, ld[pos - 1], lj[pos - 1])) {
+        ld[pos] = ld[pos - 1]; lj[pos] = lj[pos - 1]; pos--;
+    }
+    ld[pos] = d; lj[pos] = j;
+    if (*m < k) (*m)++;
+}
+
+#define RP_MAX_LEVEL 48
+
+int orc_knn_approx(const double* X, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                   int32_t leaf_size, int32_t explore, uint64_t seed, int32_t* idx_out,
+                   double* d2_out) {
+    if (!X || n < 2 || D < 1 || k < 1 || k > n - 1 || n_trees < 1 || leaf_size < 2 * k + 2 ||
+        explore < 0 || n >= ((int64_t)1 << 31))
+        return ORC_EINVAL;
+    int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* tmp = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* seg = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)n);    /* (a, b) pairs */
+    int64_t* seg2 = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)n);
+    unsigned char* side = (unsigned char*)malloc((size_t)n);
+    double* ld = (double*)malloc(sizeof(double) * (size_t)n * k);
+    int32_t* lj = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * k);
+    double* nd = (double*)malloc(sizeof(double) * (size_t)n * k);
+    int32_t* nj = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * k);
+    int32_t* lm = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+    int32_t* nm = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+    int rc = ORC_OK;
+    if (!perm || !tmp || !seg || !seg2 || !side || !ld || !lj || !nd || !nj || !lm || !nm) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    for (int32_t tr = 0; tr < n_trees; tr++) {
+        for (int64_t i = 0; i < n; i++) perm[i] = i;
+        int64_t ns = 1;
+        seg[0] = 0; seg[1] = n;
+        for (int32_t level = 0;; level++) {
+            int64_t ns2 = 0, split = 0;
+            for (int64_t s = 0; s < ns; s++) {
+                const int64_t a = seg[2 * s], b = seg[2 * s + 1], m = b - a;
+                if (m <= leaf_size) {                  /* a leaf: keep */
+                    seg2[2 * ns2] = a; seg2[2 * ns2 + 1] = b; ns2++;
+                    continue;
+                }
+                split = 1;
+                int64_t nl = 0;
+                if (level < RP_MAX_LEVEL) {
+                    int64_t ia = (int64_t)(rp_draw(seed, tr, level, a, 0) % (uint64_t)m);
+                    int64_t ib = (int64_t)(rp_draw(seed, tr, level, a, 1) % (uint64_t)(m - 1));
+                    if (ib >= ia) ib++;
+                    const double* xa = X + perm[a + ia] * (int64_t)D;
+                    const double* xb = X + perm[a + ib] * (int64_t)D;
+                    for (int64_t p = a; p < b; p++) {
+                        const double* xi = X + perm[p] * (int64_t)D;
+                        double acc = 0.0;
+                        for (int d = 0; d < D; d++) {
+                            double mid = (xa[d] + xb[d]) * 0.5;
+                            double v = xa[d] - xb[d];
+                            acc += (xi[d] - mid) * v;
+                        }
+                        side[p] = acc > 0.0;
+                        nl += side[p] ? 0 : 1;
+                    }
+                }
+                if (nl < k + 1 || m - nl < k + 1) {
+                    nl = m / 2;                        /* cut in the middle, order kept */
+                } else {
+                    int64_t l = a, r = a + nl;
+                    for (int64_t p = a; p < b; p++) {
+                        if (side[p]) tmp[r++] = perm[p];
+                        else tmp[l++] = perm[p];
+                    }
+                    for (int64_t p = a; p < b; p++) perm[p] = tmp[p];
+                }
+                seg2[2 * ns2] = a; seg2[2 * ns2 + 1] = a + nl; ns2++;
+                seg2[2 * ns2] = a + nl; seg2[2 * ns2 + 1] = b; ns2++;
+            }
+            int64_t* sw = seg; seg = seg2; seg2 = sw;
+            ns = ns2;
+            if (!split) break;
+        }
+        /* leaf mates are candidates */
+        int64_t s;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (s = 0; s < ns; s++) {
+            const int64_t a = seg[2 * s], b = seg[2 * s + 1];
+            for (int64_t p = a; p < b; p++) {
+                const int64_t i = perm[p];
+                for (int64_t q = a; q < b; q++) {
+                    if (q == p) continue;
+                    const int64_t j = perm[q];
+                    list_insert(ld + i * k, lj + i * k, &lm[i], k, sqdist(X, D, i, j), (int32_t)j);
+                }
+            }
+        }
+    }
+    for (int32_t e = 0; e < explore; e++) {
+        int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (i = 0; i < n; i++) {
+            double* od = nd + i * k;
+            int32_t* oj = nj + i * k;
+            int32_t om = lm[i];
+            for (int32_t q = 0; q < om; q++) { od[q] = ld[i * k + q]; oj[q] = lj[i * k + q]; }
+            for (int32_t a = 0; a < lm[i]; a++) {
+                const int64_t j = lj[i * k + a];
+                for (int32_t c = 0; c < lm[j]; c++) {
+                    const int64_t l = lj[j * k + c];
+                    if (l == i) continue;
+                    list_insert(od, oj, &om, k, sqdist(X, D, i, l), (int32_t)l);
+                }
+            }
+            nm[i] = om;
+        }
+        double* sd = ld; ld = nd; nd = sd;
+        int32_t* sj = lj; lj = nj; nj = sj;
+        int32_t* sm = lm; lm = nm; nm = sm;
+    }
+    {
+        int64_t i;
+        for (i = 0; i < n; i++) {
+            if (lm[i] < k) { rc = ORC_EINVAL; goto done; }   /* cannot happen: see above */
+            for (int32_t q = 0; q < k; q++) {
+                idx_out[i * k + q] = lj[i * k + q];
+                d2_out[i * k + q] = ld[i * k + q];
+            }
+        }
+    }
+done:
+    free(perm); free(tmp); free(seg); free(seg2); free(side);
+    free(ld); free(lj); free(nd); free(nj); free(lm); free(nm);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Perplexity calibration (Section 3.2): for each row find the          */
 /* Gaussian precision b_i with entropy H(P_i) = ln(u) (natural log),   */
 /* p_{j|i} = exp(-b_i * delta_j) / sum, delta_j = d2_ij - min_j d2_ij   */

@@ -66,6 +66,8 @@ psne_status check_params(const pixelsne_params* p) {
     if (p->data_order != 0 && p->data_order != 1) return invalid("data_order must be 0 or 1");
     if (p->opening_fp64 != 0 && p->opening_fp64 != 1) return invalid("opening_fp64 must be 0 or 1");
     if (p->tree != PSNE_TREE_PIXEL && p->tree != PSNE_TREE_DATA) return invalid("unknown tree");
+    if (p->knn_trees < 0 || p->knn_leaf < 0 || p->knn_explore < 0)
+        return invalid("knn_trees, knn_leaf and knn_explore must be >= 0");
     if (p->tree == PSNE_TREE_DATA && p->com_mode != PSNE_COM_MASS) {
         set_error("the data-driven tree takes centres of mass only (PSNE_COM_MASS)");
         return PSNE_E_UNSUPPORTED;
@@ -303,6 +305,9 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->reorder_growth = 2.0;
     p->opening_fp64 = 0;
     p->tree = PSNE_TREE_PIXEL;
+    p->knn_trees = 0;
+    p->knn_leaf = 0;
+    p->knn_explore = 1;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -332,7 +337,18 @@ pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perpl
     if (e == hipSuccess) e = hipMalloc(&d2, sizeof(double) * n * k);
     if (e == hipSuccess) e = hipMalloc(&Pc, sizeof(double) * n * k);
     std::string err;
-    if (e == hipSuccess) e = psne::knn(X, n, D, p.x_dtype, (int32_t)k, idx, d2, c->stream, &err);
+    const int32_t leaf = p.knn_leaf > 0 ? p.knn_leaf : (int32_t)(2 * k + 2);
+    if (p.knn_trees > 0 && leaf < 2 * k + 2) {
+        invalid("knn_leaf must be >= 2k + 2");
+        cleanup();
+        free_ctx(c);
+        return nullptr;
+    }
+    if (e == hipSuccess)
+        e = p.knn_trees > 0
+                ? psne::knn_approx(X, n, D, p.x_dtype, (int32_t)k, p.knn_trees, leaf,
+                                   p.knn_explore, p.seed, idx, d2, c->stream, &err)
+                : psne::knn(X, n, D, p.x_dtype, (int32_t)k, idx, d2, c->stream, &err);
     if (e == hipSuccess) e = psne::perplexity(d2, n, (int32_t)k, perplexity, Pc, nullptr, c->stream);
     int64_t* rp = nullptr;
     uint32_t* col = nullptr;
@@ -722,6 +738,30 @@ psne_status pixelsne_knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, i
         return PSNE_E_NUMERIC;
     }
     if (e != hipSuccess) return device_error(nullptr, e, "knn");
+    return PSNE_OK;
+}
+
+psne_status pixelsne_knn_approx(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
+                                int32_t trees, int32_t leaf_size, int32_t explore,
+                                uint64_t seed, int32_t* idx, double* d2, void* stream) {
+    if (n < 2 || n >= ((int64_t)1 << 31)) return invalid("n must be in [2, 2^31)");
+    if (D < 1) return invalid("D must be >= 1");
+    if (k < 1 || k > n - 1 || k > 256) return invalid("k must be in [1, min(n - 1, 256)]");
+    if (trees < 1 || explore < 0) return invalid("trees >= 1 and explore >= 0 required");
+    const int32_t leaf = leaf_size > 0 ? leaf_size : 2 * k + 2;
+    if (leaf < 2 * k + 2) return invalid("leaf_size must be >= 2k + 2");
+    if (x_dtype != PSNE_X_F32 && x_dtype != PSNE_X_F64 && x_dtype != PSNE_X_U8)
+        return invalid("unknown x_dtype");
+    if (!is_device_ptr(X) || !is_device_ptr(idx) || !is_device_ptr(d2))
+        return invalid("X, idx, d2 must be device pointers");
+    std::string err;
+    hipError_t e = psne::knn_approx(X, n, D, x_dtype, k, trees, leaf, explore, seed, idx, d2,
+                                    (hipStream_t)stream, &err);
+    if (e != hipSuccess && !err.empty()) {
+        set_error(err);
+        return PSNE_E_DEVICE;
+    }
+    if (e != hipSuccess) return device_error(nullptr, e, "knn_approx");
     return PSNE_OK;
 }
 

@@ -188,6 +188,11 @@ hipError_t projection_keys(const void* X, int64_t n, int32_t D, int32_t x_dtype,
                            hipStream_t s);
 hipError_t knn(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k, int32_t* idx,
                double* d2, hipStream_t s, std::string* err);
+// approximate kNN (knn_approx.hip): random-projection trees and rounds of
+// neighbour exploring; leaf >= 2k + 2; same outputs as knn
+hipError_t knn_approx(const void* X, int64_t n, int32_t D, int32_t x_dtype, int32_t k,
+                      int32_t trees, int32_t leaf, int32_t explore, uint64_t seed, int32_t* idx,
+                      double* d2, hipStream_t s, std::string* err);
 hipError_t perplexity(const double* d2, int64_t n, int32_t k, double u, double* P,
                       double* beta, hipStream_t s);
 // Symmetric CSR from kNN + conditional P.  Allocates row_ptr/col/val64 with

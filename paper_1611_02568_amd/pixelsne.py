@@ -47,6 +47,9 @@ class Params(C.Structure):
         ("reorder_growth", C.c_double),
         ("opening_fp64", C.c_int32),
         ("tree", C.c_int32),
+        ("knn_trees", C.c_int32),
+        ("knn_leaf", C.c_int32),
+        ("knn_explore", C.c_int32),
     ]
 
 
@@ -102,6 +105,8 @@ SIGNATURES = {
     "pixelsne_export_tree64": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
     "pixelsne_knn": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "pixelsne_perplexity": (C.c_int, [_vp, _i64, _i32, _d, _vp, _vp, _vp]),
+    "pixelsne_knn_approx": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _u64, _vp,
+                                      _vp, _vp]),
     "pixelsne_mlp_create": (_vp, [_i32, _i32, _i32, _u64, _vp]),
     "pixelsne_mlp_destroy": (None, [_vp]),
     "pixelsne_mlp_num_params": (_i64, [_vp]),
@@ -388,6 +393,20 @@ def knn(X: torch.Tensor, k: int):
     d2 = torch.empty((n, k), dtype=torch.float64, device=X.device)
     _check(load().pixelsne_knn(_ptr(X), n, D, _X_TYPES[X.dtype], int(k), _ptr(idx), _ptr(d2),
                                _stream()))
+    return idx, d2
+
+
+def knn_approx(X: torch.Tensor, k: int, trees: int = 4, leaf_size: int = 0, explore: int = 1,
+               seed: int = 0):
+    """Approximate kNN (random-projection trees + neighbour exploring):
+    (idx int32 [n,k], d2 float64 [n,k])."""
+    n, D = X.shape
+    X = X.contiguous()
+    idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, k), dtype=torch.float64, device=X.device)
+    _check(load().pixelsne_knn_approx(_ptr(X), n, D, _X_TYPES[X.dtype], int(k), int(trees),
+                                      int(leaf_size), int(explore), int(seed) & (2 ** 64 - 1),
+                                      _ptr(idx), _ptr(d2), _stream()))
     return idx, d2
 
 

@@ -604,3 +604,77 @@ def test_dtree_visits_more_cells_than_ptree(orc):
     Rd, Zd, vd = orc.Tree(z, r, kind=1).repulsion(beta, 0.5)
     assert vd.mean() > vp.mean()
     assert np.linalg.norm(Rd - Rp) <= 0.05 * np.linalg.norm(Rd)
+
+
+# --------------------------------------------------------------------------
+# approximate kNN (Section 4.3): random-projection trees + neighbour exploring
+# --------------------------------------------------------------------------
+def _splitmix64(x):
+    """SplitMix64 output function (Steele, Lea and Flood, 2014), on Python ints."""
+    m = (1 << 64) - 1
+    x = (x + 0x9E3779B97F4A7C15) & m
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & m
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & m
+    return x ^ (x >> 31)
+
+
+def test_knn_approx_one_leaf_is_exact(orc):
+    """With a leaf that holds every point, the candidates are all points: the
+    result is the exact kNN (NumPy brute force, ties to the smaller index)."""
+    X, _ = datagen.small_mixture(n=400, D=12, seed=51)
+    k = 7
+    idx, d2 = orc.knn_approx(X, k, n_trees=1, leaf_size=400, explore=0)
+    D = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(D, np.inf)
+    ref = np.lexsort((np.broadcast_to(np.arange(400), D.shape), D), axis=1)[:, :k]
+    assert np.array_equal(idx, ref)
+    np.testing.assert_allclose(d2, np.take_along_axis(D, ref, 1), rtol=1e-13)
+
+
+def test_knn_approx_root_split(orc):
+    """One split (leaf_size n - 1): the two points drawn from SplitMix64 for
+    tree 0, level 0, range start 0 define the hyperplane; each point's list is
+    the exact kNN among the points on its side of it (written here in plain
+    Python: FP64 terms summed in order of d)."""
+    n, k, seed = 200, 5, 77
+    X, _ = datagen.small_mixture(n=n, D=6, seed=53)
+    idx, _ = orc.knn_approx(X, k, n_trees=1, leaf_size=n - 1, explore=0, seed=seed)
+    h = _splitmix64(_splitmix64(_splitmix64(seed ^ 0) ^ 0) ^ ((0 << 1) | 0))
+    h1 = _splitmix64(_splitmix64(_splitmix64(seed ^ 0) ^ 0) ^ ((0 << 1) | 1))
+    ia = h % n
+    ib = h1 % (n - 1)
+    ib += ib >= ia
+    xa, xb = X[ia], X[ib]
+    side = np.zeros(n, bool)
+    for i in range(n):
+        acc = 0.0
+        for d in range(X.shape[1]):
+            acc += (float(X[i, d]) - (float(xa[d]) + float(xb[d])) * 0.5) * (float(xa[d]) - float(xb[d]))
+        side[i] = acc > 0.0
+    assert k + 1 <= side.sum() <= n - k - 1          # a proper split of this data
+    D = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(D, np.inf)
+    D[side[:, None] != side[None, :]] = np.inf
+    ref = np.lexsort((np.broadcast_to(np.arange(n), D.shape), D), axis=1)[:, :k]
+    assert np.array_equal(idx, ref)
+
+
+def test_knn_approx_exploring_improves(orc):
+    """Each round keeps the best k of a superset of the previous list, so every
+    sorted distance can only shrink; recall against the exact kNN rises and
+    reaches 0.95 here.  Lists are distinct, without the point itself."""
+    X, _ = datagen.small_mixture(n=3000, D=40, seed=55)
+    k = 20
+    ie, de = orc.knn(X, k)
+    prev = None
+    recalls = []
+    for e in range(3):
+        idx, d2 = orc.knn_approx(X, k, n_trees=3, explore=e, seed=9)
+        assert np.all(np.diff(d2, axis=1) >= 0)
+        assert np.all(idx != np.arange(3000)[:, None])
+        assert all(len(set(r)) == k for r in idx[:200].tolist())
+        if prev is not None:
+            assert np.all(d2 <= prev)
+        prev = d2
+        recalls.append(np.mean([len(set(a) & set(b)) / k for a, b in zip(idx.tolist(), ie.tolist())]))
+    assert recalls[0] < recalls[1] <= recalls[2] and recalls[2] >= 0.95
