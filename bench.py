@@ -490,6 +490,54 @@ def _oracle_rate(oracle, st, p, P, n, min_seconds, max_iters, chunk):
     return {"value": n * iters / t, "iterations": iters, "seconds": t}
 
 
+def knn_compare(args):
+    """Setup with the exact brute-force kNN against the approximate kNN of
+    Section 4.3 (random-projection trees + neighbour exploring) on the
+    5,000,000 x 100 workload with 1% outliers (perplexity 30, k 90, screen
+    4096): setup time of each, recall of the approximate lists on sampled rows
+    against the oracle's exact FP64 kNN of those rows, and the exact-Z KL after
+    1,000 iterations from the same start with each P (the paper reports the
+    quality of the RP-tree P as close to the exact one)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1611_02568_amd import datagen, pixelsne
+
+    torch.cuda.set_device(0)
+    n, r, u = args.large_n, 4096, 30.0
+    k = int(3 * u)
+    X, _, _ = datagen.zipf_mixture_outliers(n=n)
+    Xd = torch.from_numpy(X).cuda()
+    y0 = torch.as_tensor(datagen.initial_embedding(n, seed=datagen.seed_for(4, 1)))
+    out = {"n": n, "k": k, "trees": args.knn_trees, "explore": args.knn_explore}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx, _ = pixelsne.knn_approx(Xd, k, trees=args.knn_trees, explore=args.knn_explore, seed=1)
+    torch.cuda.synchronize()
+    out["approx_knn_s"] = time.perf_counter() - t0
+    rows = np.random.default_rng(15).choice(n, args.knn_rows, replace=False)
+    ei, _ = oracle.knn(X, k, rows=rows)
+    got = idx.cpu().numpy()[rows]
+    out["recall"] = float(np.mean([len(set(a.tolist()) & set(b.tolist())) / k
+                                   for a, b in zip(got, ei)]))
+    del idx
+    log(f"[knn] approximate kNN {out['approx_knn_s']:.2f} s, recall {out['recall']:.4f}")
+    for label, trees in (("approx", args.knn_trees), ("exact", 0)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = pixelsne.Context.from_data(Xd, u, r, Y_init=y0, precision=pixelsne.FP32,
+                                         knn_trees=trees, knn_explore=args.knn_explore, seed=1)
+        torch.cuda.synchronize()
+        out[label + "_setup_s"] = time.perf_counter() - t0
+        ctx.step(1000)
+        out[label + "_kl_1000"] = ctx.kl()
+        log(f"[knn] {label}: setup {out[label + '_setup_s']:.2f} s, "
+            f"KL after 1,000 iterations {out[label + '_kl_1000']:.5f}")
+        del ctx
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands (FP64, OpenMP over points) on this host's cores,
     on bounded samples of the workloads:
@@ -578,6 +626,12 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="run only the 5M time-to-KL experiment and print its own JSON line")
     ap.add_argument("--large-n", type=int, default=5_000_000)
+    ap.add_argument("--knn-compare", action="store_true",
+                    help="run only the exact vs approximate kNN setup comparison on the "
+                         "5M workload and print its own JSON line")
+    ap.add_argument("--knn-trees", type=int, default=8)
+    ap.add_argument("--knn-explore", type=int, default=1)
+    ap.add_argument("--knn-rows", type=int, default=200)
     ap.add_argument("--r-sweep", action="store_true",
                     help="run only the tree comparison (pixel tree at r = 512 ... 8,192 and the "
                          "data-driven tree) on the FP32 workload and print its own JSON line")
@@ -594,6 +648,13 @@ def main():
                           "unit": "ms", "higher_is_better": False, "n_gpus": 1,
                           "data": "synthetic", "dtype": "f32", "steps": args.steps,
                           "warmup": args.warmup, "result": res}), flush=True)
+        return
+
+    if args.knn_compare:
+        res = knn_compare(args)
+        print(json.dumps({"metric": "setup seconds, exact vs approximate kNN, 5M x 100",
+                          "unit": "s", "higher_is_better": False, "n_gpus": 1,
+                          "data": "synthetic", "dtype": "f32", "result": res}), flush=True)
         return
 
     if args.large:
