@@ -125,6 +125,9 @@ typedef struct {
                                  random-projection trees (Section 4.3) */
     int32_t knn_leaf;         /* its leaf size, >= 2k + 2; 0 => 2k + 2 [0] */
     int32_t knn_explore;      /* its rounds of neighbour exploring [1] */
+    int32_t attract_blocks_per_cu; /* blocks per compute unit of the persistent grid that
+                                 runs the attraction's row sums on the second stream beside
+                                 the tree and the traversal, 1..16 [2] */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
