@@ -434,41 +434,6 @@ __global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restric
     inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, (uint32_t)t, m);
 }
 
-// Several levels in one launch: one thread per cell of level l_top walks its
-// subtree's cells of levels l_top .. l_top + SPAN - 1 bottom-up (the cells
-// of a subtree at each level are a contiguous range, found from the first
-// children downward), so each cell is still summed from its children after
-// them, in child order, as one launch per level would.
-template <int SPAN>
-__global__ __launch_bounds__(kBlock) void k_tree_span(const uint32_t* __restrict__ keys,
-                                                      int l_top, int L, int com_mode,
-                                                      const DevScalars* __restrict__ sc,
-                                                      const uint32_t* __restrict__ first_child,
-                                                      Node* __restrict__ nodes,
-                                                      CellF* __restrict__ c32,
-                                                      double2* __restrict__ nsum) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= sc->level_size[l_top]) return;
-    uint32_t lo[SPAN], hi[SPAN];
-    lo[0] = (uint32_t)t;
-    hi[0] = (uint32_t)t + 1;
-#pragma unroll
-    for (int q = 1; q < SPAN; q++) {
-        const int l = l_top + q - 1;
-        const uint32_t bl = sc->level_base[l], bn = sc->level_base[l + 1];
-        lo[q] = first_child[bl + lo[q - 1]] - bn;
-        hi[q] = hi[q - 1] < sc->level_size[l] ? first_child[bl + hi[q - 1]] - bn
-                                              : sc->level_size[l + 1];
-    }
-#pragma unroll
-    for (int q = SPAN - 1; q >= 0; q--) {
-        const int l = l_top + q;
-        const uint32_t m = sc->level_size[l];
-        for (uint32_t c = lo[q]; c < hi[q]; c++)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, c, m);
-    }
-}
-
 // Levels top..0 in one block (a level l holds at most 4^l cells, so at most
 // kTopThreads for l <= kTopLevel): the block finishes a level before it
 // starts the one above.
@@ -1436,27 +1401,11 @@ hipError_t run_tree(pixelsne_ctx* c) {
             keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
             tb.wlast);
     }
-    // inner levels below the top block: three per launch (two for the last
-    // group when fewer remain), one launch per level for a single one
     const int top = c->L - 1 < kTopLevel ? c->L - 1 : kTopLevel;
-    for (int lb = c->L - 1; lb > top;) {
-        const int span = lb - top >= 3 ? 3 : lb - top;
-        const int lt = lb - span + 1;
-        const int64_t cap = lt < 31 ? (int64_t)1 << (2 * lt) : c->n;
-        const dim3 grid = grid_for(cap < c->n ? cap : c->n);
-        if (span == 3)
-            k_tree_span<3><<<grid, kBlock, 0, c->stream>>>(keys, lt, c->L, c->prm.com_mode, c->sc,
-                                                           tb.first_child, tb.nodes, tb.cells32,
-                                                           tb.nsum);
-        else if (span == 2)
-            k_tree_span<2><<<grid, kBlock, 0, c->stream>>>(keys, lt, c->L, c->prm.com_mode, c->sc,
-                                                           tb.first_child, tb.nodes, tb.cells32,
-                                                           tb.nsum);
-        else
-            k_tree_level<<<grid, kBlock, 0, c->stream>>>(keys, lt, c->L, c->prm.com_mode, c->sc,
-                                                         tb.first_child, tb.nodes, tb.cells32,
-                                                         tb.nsum);
-        lb = lt - 1;
+    for (int l = c->L - 1; l > top; l--) {
+        const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;
+        k_tree_level<<<grid_for(cap < c->n ? cap : c->n), kBlock, 0, c->stream>>>(
+            keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.cells32, tb.nsum);
     }
     if (top >= 0)
         k_tree_top<<<1, kTopThreads, 0, c->stream>>>(keys, top, c->L, c->prm.com_mode, c->sc,
