@@ -17,6 +17,8 @@ Functions follow the paper's sections:
   gradient / iterate .................... Eq. 5 in the pixel frame, Eq. 13
   kl .................................... Eq. 4 with exact Z
   neighborhood_precision ................ Eq. 14
+  Tree3 / gradient3 / iterate3 / kl3 .... the 3-D embedding (Section 1): voxel
+                                          octree, three-axis scaling
 """
 from __future__ import annotations
 
@@ -85,6 +87,19 @@ def _load():
                                 C.c_int32, C.c_int32, vp]
     lib.orc_kl.restype = C.c_double
     lib.orc_kl.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp]
+    lib.orc_tree3_build.restype = vp
+    lib.orc_tree3_build.argtypes = [_dp, C.c_int64, C.c_int32]
+    lib.orc_tree3_free.argtypes = [vp]
+    lib.orc_tree3_level_sizes.argtypes = [vp, _i64p]
+    lib.orc_tree3_level.argtypes = [vp, C.c_int32, _u32p, _i64p, _dp]
+    lib.orc_repulsion3.argtypes = [vp, _dp, _dp, C.c_double, _dp, _dp, _i64p]
+    lib.orc_gradient3.argtypes = [_dp, C.c_int64, C.c_int32, _dp, C.c_double, C.c_double, _i64p,
+                                  _i32p, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
+    lib.orc_iterate3.argtypes = [C.c_void_p, C.c_int64, _i64p, _i32p, _dp, _dp, _dp, _dp, _dp,
+                                 C.c_int32, C.c_int32]
+    lib.orc_normalize3.argtypes = [_dp, C.c_int64, C.c_int32, C.c_double, _dp, _dp, _dp]
+    lib.orc_kl3.restype = C.c_double
+    lib.orc_kl3.argtypes = [_dp, C.c_int64, _dp, _i64p, _i32p, _dp]
     _lib = lib
     return lib
 
@@ -389,3 +404,106 @@ def neighborhood_precision(hi, lo, ks):
             common += len(set(hi[i, :k].tolist()) & set(lo[i, :k].tolist()))
         out.append(common / (k * n))
     return out
+
+
+# --------------------------------------------------------------------------
+# The 3-D embedding (Section 1): voxel octree of fixed depth log2 r, the
+# steps of the 2-D functions above run over three axes.
+# --------------------------------------------------------------------------
+class Tree3:
+    """Voxel octree of z (n x 3) in an r x r x r cube (r a power of two, at
+    most 1024): levels 0..log2 r, unit-voxel leaves, octant prefix = Morton
+    key with x, y, z in bits 3b, 3b+1, 3b+2."""
+
+    def __init__(self, z, r: int):
+        self._lib = _load()
+        self.z = _f64(z)
+        self.r = r
+        self.L = int(r).bit_length() - 1
+        self.h = self._lib.orc_tree3_build(self.z, self.z.shape[0], r)
+        if not self.h:
+            raise RuntimeError("oracle octree build failed")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self._lib.orc_tree3_free(h)
+            self.h = None
+
+    def level_sizes(self):
+        s = np.empty(self.L + 1, np.int64)
+        self._lib.orc_tree3_level_sizes(self.h, s)
+        return s
+
+    def level(self, l: int):
+        """(prefix uint32, count int64, sums float64 [m,3]) ascending by prefix."""
+        m = int(self.level_sizes()[l])
+        pre = np.empty(m, np.uint32)
+        cnt = np.empty(m, np.int64)
+        sm = np.empty((m, 3), np.float64)
+        _check(self._lib.orc_tree3_level(self.h, l, pre, cnt, sm), "octree level")
+        return pre, cnt, sm
+
+    def repulsion(self, beta, theta: float):
+        """(R [n,3], Z_i, visits) with the FP64 opening test and centres of mass."""
+        n = self.z.shape[0]
+        R = np.empty((n, 3), np.float64)
+        Zi = np.empty(n, np.float64)
+        vis = np.empty(n, np.int64)
+        _check(self._lib.orc_repulsion3(self.h, self.z, _f64(beta), float(theta), R, Zi, vis),
+               "repulsion3")
+        return R, Zi, vis
+
+
+def gradient3(z, r: int, s, P, theta: float = 0.5, alpha: float = 1.0):
+    """Voxel-frame bracket B = alpha*A - R/Z of a 3-D embedding and its parts."""
+    z = _f64(z)
+    n = z.shape[0]
+    rp, col, val = _csr(P)
+    B = np.empty_like(z)
+    A = np.empty_like(z)
+    R = np.empty_like(z)
+    Zi = np.empty(n)
+    vis = np.empty(n, np.int64)
+    Z = np.empty(1)
+    _check(_load().orc_gradient3(z, n, r, _f64(s), float(theta), float(alpha), rp, col, val, B, A,
+                                 R, Zi, vis, Z), "gradient3")
+    return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": float(Z[0])}
+
+
+def normalize3(zh, r: int, eps: float = 1e-6):
+    """Three-axis screen-driven scaling: (z, gamma[3], zmin[3])."""
+    zh = _f64(zh)
+    z = np.empty_like(zh)
+    g = np.empty(3)
+    m = np.empty(3)
+    _check(_load().orc_normalize3(zh, zh.shape[0], r, float(eps), z, g, m), "normalize3")
+    return z, g, m
+
+
+class State3(State):
+    """Optimiser state of a 3-D embedding in the voxel frame."""
+
+    def __init__(self, y0, r: int, eps: float = 1e-6):
+        y0 = _f64(y0)
+        self.z, gamma, _ = normalize3(y0, r, eps)
+        self.s = gamma / float(r)
+        self.u = np.zeros_like(self.z)
+        self.g = np.ones_like(self.z)
+        self.t = 0
+
+
+def iterate3(state: State3, p: Params, P, n_iter: int):
+    """n_iter iterations of the 3-D loop (centres of mass, FP64 opening test;
+    p.com_mode, p.predicate and p.tree are not read)."""
+    rp, col, val = _csr(P)
+    _check(_load().orc_iterate3(C.byref(p), state.z.shape[0], rp, col, val, state.z, state.u,
+                                state.g, state.s, state.t, n_iter), "iterate3")
+    state.t += n_iter
+
+
+def kl3(z, s, P) -> float:
+    """KL(P || Q) of a 3-D embedding with exact Z over all pairs (O(n^2))."""
+    z = _f64(z)
+    rp, col, val = _csr(P)
+    return float(_load().orc_kl3(z, z.shape[0], _f64(s), rp, col, val))

@@ -1047,3 +1047,301 @@ double orc_kl(const double* z, int64_t n, const double* s, const int64_t* row_pt
     free(zrow);
     return cs_get(&c) + log(Z);
 }
+
+/* ================================================================== */
+/* The 3-D case (Section 1, footnote: the approach extends to 3-D      */
+/* embeddings).  The screen becomes a cube of r^3 voxels, the          */
+/* P-Quadtree an octree of fixed depth L = log2 r (L <= 10) with unit- */
+/* voxel leaves, the Morton key interleaves x, y, z in bits 3b, 3b+1,  */
+/* 3b+2 (child index 4 zbit + 2 ybit + xbit), and every per-axis step  */
+/* (scaling, beta, the metric of the opening test) runs over three     */
+/* axes: diag^2 = w^2 (b1 + b2 + b3), d^2 = sum_d b_d dz_d^2.  The     */
+/* opening test is FP64.  State arrays are [n][3].                     */
+/* ================================================================== */
+typedef struct {
+    int32_t child[8];
+    int32_t level;
+    uint32_t prefix;
+    int64_t count;
+    csum s[3];
+} onode3;
+
+typedef struct {
+    int32_t r, L;
+    int64_t n, nnodes, cap;
+    onode3* nodes;
+    int32_t* leaf_of;
+} otree3;
+
+static int32_t tree3_new_node(otree3* t, int32_t level, uint32_t prefix) {
+    if (t->nnodes == t->cap) {
+        int64_t nc = t->cap ? 2 * t->cap : 1024;
+        onode3* p = (onode3*)realloc(t->nodes, sizeof(onode3) * (size_t)nc);
+        if (!p) return -1;
+        t->nodes = p; t->cap = nc;
+    }
+    onode3* c = &t->nodes[t->nnodes];
+    memset(c, 0, sizeof(*c));
+    for (int q = 0; q < 8; q++) c->child[q] = -1;
+    c->level = level; c->prefix = prefix;
+    return (int32_t)t->nnodes++;
+}
+
+void orc_tree3_free(void* h) {
+    otree3* t = (otree3*)h;
+    if (!t) return;
+    free(t->nodes); free(t->leaf_of); free(t);
+}
+
+static inline uint32_t morton3(uint32_t px, uint32_t py, uint32_t pz, int L) {
+    uint32_t key = 0;
+    for (int b = 0; b < L; b++) {
+        key |= ((px >> b) & 1u) << (3 * b);
+        key |= ((py >> b) & 1u) << (3 * b + 1);
+        key |= ((pz >> b) & 1u) << (3 * b + 2);
+    }
+    return key;
+}
+
+/* each point, in index order, from the root down to its voxel */
+void* orc_tree3_build(const double* z, int64_t n, int32_t r) {
+    int L = log2_exact(r);
+    if (!z || n < 1 || L < 0 || L > 10) return NULL;
+    otree3* t = (otree3*)calloc(1, sizeof(otree3));
+    if (!t) return NULL;
+    t->r = r; t->L = L; t->n = n;
+    t->leaf_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!t->leaf_of || tree3_new_node(t, 0, 0) != 0) { orc_tree3_free(t); return NULL; }
+    for (int64_t i = 0; i < n; i++) {
+        uint32_t p[3];
+        for (int d = 0; d < 3; d++) p[d] = (uint32_t)pixel_of(z[3 * i + d], r);
+        int32_t c = 0;
+        for (int l = 0;; l++) {
+            onode3* nd = &t->nodes[c];
+            nd->count++;
+            for (int d = 0; d < 3; d++) cs_add(&nd->s[d], z[3 * i + d]);
+            if (l == L) break;
+            int sh = L - 1 - l;
+            int q = (int)(((p[2] >> sh) & 1u) << 2 | ((p[1] >> sh) & 1u) << 1 | ((p[0] >> sh) & 1u));
+            int32_t ch = nd->child[q];
+            if (ch < 0) {
+                uint32_t pre = (nd->prefix << 3) | (uint32_t)q;
+                ch = tree3_new_node(t, l + 1, pre);
+                if (ch < 0) { orc_tree3_free(t); return NULL; }
+                t->nodes[c].child[q] = ch;
+            }
+            c = ch;
+        }
+        t->leaf_of[i] = c;
+    }
+    return t;
+}
+
+int orc_tree3_level_sizes(const void* h, int64_t* sizes) {
+    const otree3* t = (const otree3*)h;
+    for (int l = 0; l <= t->L; l++) sizes[l] = 0;
+    for (int64_t c = 0; c < t->nnodes; c++) sizes[t->nodes[c].level]++;
+    return ORC_OK;
+}
+
+int orc_tree3_level(const void* h, int32_t level, uint32_t* prefix, int64_t* count, double* sum) {
+    const otree3* t = (const otree3*)h;
+    if (level < 0 || level > t->L) return ORC_EINVAL;
+    int64_t m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++) if (t->nodes[c].level == level) m++;
+    pref_t* v = (pref_t*)malloc(sizeof(pref_t) * (size_t)(m ? m : 1));
+    if (!v) return ORC_ENOMEM;
+    m = 0;
+    for (int64_t c = 0; c < t->nnodes; c++)
+        if (t->nodes[c].level == level) { v[m].prefix = t->nodes[c].prefix; v[m].id = c; m++; }
+    qsort(v, (size_t)m, sizeof(pref_t), pref_cmp);
+    for (int64_t a = 0; a < m; a++) {
+        const onode3* nd = &t->nodes[v[a].id];
+        if (prefix) prefix[a] = nd->prefix;
+        if (count) count[a] = nd->count;
+        if (sum) for (int d = 0; d < 3; d++) sum[3 * a + d] = cs_get(&nd->s[d]);
+    }
+    free(v);
+    return ORC_OK;
+}
+
+/* Barnes-Hut repulsion on the octree: as orc_repulsion_rows in three
+ * dimensions (FP64 opening test, own-voxel exclusion, mass centres). */
+int orc_repulsion3(const void* h, const double* z, const double* beta, double theta,
+                   double* R, double* Zi, int64_t* visits) {
+    const otree3* t = (const otree3*)h;
+    if (!t || !z || !beta || !(theta >= 0.0) || theta >= 1.0) return ORC_EINVAL;
+    const int L = t->L;
+    const double th2 = theta * theta;
+    const double bs = beta[0] + beta[1] + beta[2];
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i = 0; i < t->n; i++) {
+        const double* zi = z + 3 * i;
+        const int32_t own = t->leaf_of[i];
+        double r3[3] = {0.0, 0.0, 0.0}, zs = 0.0;
+        int64_t nv = 0;
+        int32_t stack[8 * 12];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            const int32_t c = stack[--sp];
+            const onode3* nd = &t->nodes[c];
+            nv++;
+            const double w = ldexp(1.0, L - nd->level);
+            double m = (double)nd->count, cc[3];
+            for (int d = 0; d < 3; d++) cc[d] = cs_get(&nd->s[d]) / m;
+            int use;
+            if (nd->level == L) {
+                use = 1;
+                if (c == own) {
+                    m -= 1.0;
+                    if (m <= 0.0) continue;
+                    for (int d = 0; d < 3; d++) cc[d] = (cs_get(&nd->s[d]) - zi[d]) / m;
+                }
+            } else {
+                double d2 = 0.0;
+                for (int d = 0; d < 3; d++) { double e = zi[d] - cc[d]; d2 += beta[d] * e * e; }
+                use = w * w * bs < th2 * d2;
+            }
+            if (use) {
+                double e[3], d2 = 0.0;
+                for (int d = 0; d < 3; d++) { e[d] = zi[d] - cc[d]; d2 += beta[d] * e[d] * e[d]; }
+                double q = 1.0 / (1.0 + d2);
+                zs += m * q;
+                for (int d = 0; d < 3; d++) r3[d] += m * q * q * e[d];
+            } else {
+                for (int ch = 7; ch >= 0; ch--)
+                    if (nd->child[ch] >= 0) stack[sp++] = nd->child[ch];
+            }
+        }
+        for (int d = 0; d < 3; d++) R[3 * i + d] = r3[d];
+        Zi[i] = zs;
+        if (visits) visits[i] = nv;
+    }
+    return ORC_OK;
+}
+
+int orc_gradient3(const double* z, int64_t n, int32_t r, const double* s, double theta,
+                  double alpha, const int64_t* row_ptr, const int32_t* col, const double* val,
+                  double* B, double* A, double* R, double* Zi, int64_t* visits, double* Z_out) {
+    const double beta[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+    void* h = orc_tree3_build(z, n, r);
+    if (!h) return ORC_ENOMEM;
+    int rc = orc_repulsion3(h, z, beta, theta, R, Zi, visits);
+    orc_tree3_free(h);
+    if (rc != ORC_OK) return rc;
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; i++) {
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            const int64_t j = col[e];
+            double dz[3], d2 = 0.0;
+            for (int d = 0; d < 3; d++) { dz[d] = z[3 * i + d] - z[3 * j + d]; d2 += beta[d] * dz[d] * dz[d]; }
+            const double q = 1.0 / (1.0 + d2);
+            for (int d = 0; d < 3; d++) a[d] += val[e] * q * dz[d];
+        }
+        for (int d = 0; d < 3; d++) A[3 * i + d] = a[d];
+    }
+    const double Z = orc_sum(Zi, n);
+    if (Z_out) *Z_out = Z;
+    for (int64_t e = 0; e < 3 * n; e++) B[e] = alpha * A[e] - R[e] / Z;
+    return ORC_OK;
+}
+
+/* the optimisation loop of orc_iterate over three axes */
+int orc_iterate3(const orc_params* p, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                 const double* val, double* z, double* u, double* g, double* s, int32_t t0,
+                 int32_t n_iter) {
+    if (!p || !z || !u || !g || !s) return ORC_EINVAL;
+    double* B = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* A = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* R = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* Zi = (double*)malloc(sizeof(double) * (size_t)n);
+    double* zh = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    int rc = (B && A && R && Zi && zh) ? ORC_OK : ORC_ENOMEM;
+    for (int32_t it = 0; it < n_iter && rc == ORC_OK; it++) {
+        const int32_t t = t0 + it;
+        const double alpha = t < p->exag_iters ? p->exaggeration : 1.0;
+        const double mu = t < p->mom_switch ? p->mom0 : p->mom1;
+        double Z;
+        rc = orc_gradient3(z, n, p->r, s, p->theta, alpha, row_ptr, col, val, B, A, R, Zi, NULL, &Z);
+        if (rc != ORC_OK) break;
+        for (int64_t e = 0; e < 3 * n; e++) {
+            double gn = (sgn(B[e]) != sgn(u[e])) ? g[e] + 0.2 : g[e] * 0.8;
+            if (gn < p->min_gain) gn = p->min_gain;
+            g[e] = gn;
+            u[e] = mu * u[e] - p->eta * gn * B[e];
+            zh[e] = z[e] + u[e];
+        }
+        for (int d = 0; d < 3; d++) {
+            double lo = zh[d], hi = zh[d];
+            for (int64_t i = 1; i < n; i++) {
+                const double v = zh[3 * i + d];
+                if (v < lo) lo = v;
+                if (v > hi) hi = v;
+            }
+            const double gam = hi - lo + p->eps;
+            for (int64_t i = 0; i < n; i++) {
+                z[3 * i + d] = (double)p->r * (zh[3 * i + d] - lo) / gam;
+                u[3 * i + d] *= (double)p->r / gam;
+            }
+            s[d] *= gam / (double)p->r;
+        }
+    }
+    free(B); free(A); free(R); free(Zi); free(zh);
+    return rc;
+}
+
+/* normalisation of an initial 3-D embedding: z, gamma[3], zmin[3] */
+int orc_normalize3(const double* zh, int64_t n, int32_t r, double eps, double* z, double* gamma,
+                   double* zmin) {
+    if (!zh || !z || n < 1) return ORC_EINVAL;
+    for (int d = 0; d < 3; d++) {
+        double lo = zh[d], hi = zh[d];
+        for (int64_t i = 1; i < n; i++) {
+            const double v = zh[3 * i + d];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        const double gam = hi - lo + eps;
+        for (int64_t i = 0; i < n; i++) z[3 * i + d] = (double)r * (zh[3 * i + d] - lo) / gam;
+        if (gamma) gamma[d] = gam;
+        if (zmin) zmin[d] = lo;
+    }
+    return ORC_OK;
+}
+
+/* KL (Eq. 4) of a 3-D embedding with the exact normaliser */
+double orc_kl3(const double* z, int64_t n, const double* s, const int64_t* row_ptr,
+               const int32_t* col, const double* val) {
+    const double b[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+    double* zrow = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!zrow) return NAN;
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < n; i++) {
+        csum a = {0, 0};
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double d2 = 0.0;
+            for (int d = 0; d < 3; d++) { double e = z[3 * i + d] - z[3 * j + d]; d2 += b[d] * e * e; }
+            cs_add(&a, 1.0 / (1.0 + d2));
+        }
+        zrow[i] = cs_get(&a);
+    }
+    double Z = orc_sum(zrow, n);
+    csum c = {0, 0};
+    for (i = 0; i < n; i++)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            const int64_t j = col[e];
+            const double p = val[e];
+            if (p <= 0.0) continue;
+            double d2 = 0.0;
+            for (int d = 0; d < 3; d++) { double ee = z[3 * i + d] - z[3 * j + d]; d2 += b[d] * ee * ee; }
+            cs_add(&c, p * log(p) + p * log(1.0 + d2));
+        }
+    free(zrow);
+    return cs_get(&c) + log(Z);
+}

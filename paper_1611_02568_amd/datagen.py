@@ -145,32 +145,32 @@ def zipf_mixture_outliers(n: int = 5_000_000, D: int = 100, K: int = 1000, a: fl
     return X[perm], lab[perm], mix
 
 
-def initial_embedding(n: int, seed: int, sigma: float = 1e-4) -> np.ndarray:
-    """y(0) ~ N(0, sigma^2 I) in 2-D, float64, shape (n, 2)."""
+def initial_embedding(n: int, seed: int, sigma: float = 1e-4, dim: int = 2) -> np.ndarray:
+    """y(0) ~ N(0, sigma^2 I) in dim dimensions, float64, shape (n, dim)."""
     rng = np.random.default_rng(seed)
-    return rng.standard_normal((n, 2)) * sigma
+    return rng.standard_normal((n, dim)) * sigma
 
 
-def uniform_pixels(n: int, r: int, seed: int, dtype=np.float64) -> np.ndarray:
-    """n positions uniform over the screen [0, r)^2 (tree and traversal tests)."""
+def uniform_pixels(n: int, r: int, seed: int, dtype=np.float64, dim: int = 2) -> np.ndarray:
+    """n positions uniform over the screen [0, r)^dim (tree and traversal tests)."""
     rng = np.random.default_rng(seed)
     top = np.nextafter(np.asarray(r, dtype), np.asarray(0, dtype))
-    return np.minimum((rng.random((n, 2)) * r).astype(dtype), top)
+    return np.minimum((rng.random((n, dim)) * r).astype(dtype), top)
 
 
 def clustered_pixels(n: int, r: int, seed: int, n_clusters: int = 8, spread: float = 0.02,
-                     dtype=np.float64) -> np.ndarray:
-    """n positions in [0, r)^2 concentrated in a few tight blobs (many points
+                     dtype=np.float64, dim: int = 2) -> np.ndarray:
+    """n positions in [0, r)^dim concentrated in a few tight blobs (many points
     share a pixel), with min 0 and the max pixel r - 1 on each axis so the
     whole screen is spanned as after normalisation."""
     rng = np.random.default_rng(seed)
-    centres = rng.random((n_clusters, 2)) * r
+    centres = rng.random((n_clusters, dim)) * r
     lab = rng.integers(0, n_clusters, n)
-    z = centres[lab] + rng.standard_normal((n, 2)) * (spread * r)
+    z = centres[lab] + rng.standard_normal((n, dim)) * (spread * r)
     top = np.nextafter(np.asarray(r, dtype), np.asarray(0, dtype))
     z = np.clip(z.astype(dtype), np.asarray(0, dtype), top)
-    z[0] = (0, 0)
-    z[1] = (top, top)
+    z[0] = 0
+    z[1] = top
     return z
 
 
