@@ -456,6 +456,87 @@ psne_status pixelsne_mlp_adam_step(pixelsne_mlp* m, const float* grad, float lr)
 psne_status pixelsne_mlp_place(pixelsne_mlp* m, const float* X, int64_t n, int32_t screen,
                                const double* s, double* Y_out);
 
+/* ---------------------------------------------------------------------- */
+/* 3-D embeddings                                                          */
+/* ---------------------------------------------------------------------- */
+/*
+ * PixelSNE in three dimensions (Section 1 notes that the method carries over
+ * to 3-D embeddings): the screen becomes a cube of r x r x r voxels, the
+ * P-Quadtree an octree of fixed depth L = log2 r whose leaves are single
+ * voxels, the Morton key interleaves the voxel coordinates x, y, z in bits
+ * 3b, 3b+1, 3b+2 (3L bits), and every per-axis step of Sections 4.1-4.2 and
+ * Eq. 12-13 runs over three axes: the opening test of Eq. 11 compares
+ * w^2 (b1 + b2 + b3) with theta^2 (b1 dz1^2 + b2 dz2^2 + b3 dz3^2),
+ * b_d = s_d^2, and the screen scaling rescales each axis to [0, r).
+ * Everything is FP64 (positions, velocities, gains, P, forces and the
+ * opening test) and cells are represented by their centre of mass (Eq. 8).
+ * Positions and all [n][3] arrays are float64, row-major, in the caller's
+ * numbering.
+ *
+ * pixelsne_params fields read: k, theta, exag_iters, exaggeration, eta, mom0,
+ * mom1, mom_switch, min_gain, eps, init_sigma, seed, x_dtype, Y_init (device
+ * float64 [n][3] in the y frame, or NULL => N(0, init_sigma^2 I) from seed),
+ * stream, knn_trees, knn_leaf, knn_explore.  precision must be PSNE_FP64,
+ * com_mode PSNE_COM_MASS and tree PSNE_TREE_PIXEL (else PSNE_E_UNSUPPORTED);
+ * the layout fields (reorder_*, data_order, graphs, opening_fp64,
+ * attract_blocks_per_cu) are not read.
+ * r is a power of two in [2, 1024]; 2 <= n <= 2^25.
+ */
+typedef struct pixelsne3_ctx pixelsne3_ctx;
+
+/* P from X exactly as pixelsne_init_ex (kNN, perplexity, symmetrisation),
+ * then the initial 3-D embedding and its first scaling.  NULL on failure. */
+pixelsne3_ctx* pixelsne3_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
+                                 int32_t r, const pixelsne_params* p);
+/* From a caller-built P, as pixelsne_init_with_P (copied and checked). */
+pixelsne3_ctx* pixelsne3_init_with_P(int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                     const int32_t* col, const double* val, int32_t r,
+                                     const pixelsne_params* p);
+void pixelsne3_destroy(pixelsne3_ctx* c);
+
+/* n_iter >= 0 iterations: voxel keys, sort, octree, Barnes-Hut repulsion and
+ * Z, sparse attraction, gains/momentum step, per-axis screen scaling.
+ * Synchronises at the end and checks for non-finite positions
+ * (PSNE_E_NUMERIC). */
+psne_status pixelsne3_step(pixelsne3_ctx* c, int32_t n_iter);
+
+/* The embedding in a PSNE_FRAME_*: z (float64 [n][3]), voxels
+ * clamp(floor(z), 0, r-1) (int32 [n][3]) or y = s * z (float64 [n][3]);
+ * device, caller-owned.  Asynchronous. */
+psne_status pixelsne3_get_Y(const pixelsne3_ctx* c, void* out, int32_t frame);
+
+/* Replace / read the optimiser state: z, u, g device float64 [n][3] (z in the
+ * voxel frame, 0 <= z < r; u or g NULL on set => zeros / ones), s host
+ * double[3], the iteration counter (sets the exaggeration and momentum
+ * schedule).  Both synchronise. */
+psne_status pixelsne3_set_state(pixelsne3_ctx* c, const double* z, const double* u,
+                                const double* g, const double* s, int32_t iteration);
+psne_status pixelsne3_get_state(const pixelsne3_ctx* c, double* z, double* u, double* g,
+                                double* s, int32_t* iteration);
+
+/* The voxel-frame gradient at the current state without stepping, as
+ * pixelsne_gradient in three dimensions: B = alpha A - R / Z, outputs device
+ * float64 [n][3] (B, A, R), Zi float64 [n], visits uint32 [n] (cells reached
+ * by each point's walk), Z host; any may be NULL.  Leaves the octree for
+ * pixelsne3_export_tree.  Synchronises. */
+psne_status pixelsne3_gradient(pixelsne3_ctx* c, double alpha, double* B, double* A, double* R,
+                               double* Zi, uint32_t* visits, double* Z);
+
+/* The octree of the last gradient / iteration: level_size host int64 [L+1]
+ * (always written); keys device uint32 [n] (Morton keys in sorted order),
+ * perm uint32 [n] (point at each sorted position), prefix uint32 [n_nodes]
+ * (key >> 3 (L - level)), count uint32 [n_nodes], sum float64 [n_nodes][3]:
+ * level 0, then 1, ..., L, each ascending by prefix.  NULL device pointers =>
+ * level sizes only.  Synchronises. */
+psne_status pixelsne3_export_tree(const pixelsne3_ctx* c, int64_t* level_size, uint32_t* keys,
+                                  uint32_t* perm, uint32_t* prefix, uint32_t* count,
+                                  double* sum);
+
+/* KL(P || Q) of Eq. 4 for the current 3-D embedding with the exact normaliser
+ * (O(n^2) pairs; pair terms in FP32 summed in FP64; the P terms in FP64).
+ * Allocates partial sums for the call.  *kl host.  Synchronises. */
+psne_status pixelsne3_kl(const pixelsne3_ctx* c, double* kl);
+
 #ifdef __cplusplus
 }
 #endif

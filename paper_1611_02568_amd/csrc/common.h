@@ -131,6 +131,26 @@ __device__ __forceinline__ v2_t<T> norm_pos(const T* __restrict__ zh,
     return V{zx, zy};
 }
 
+// 1 / x for x >= 1: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each roughly squaring the relative error, which ends
+// within an ulp or two of the correctly rounded quotient
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): the counter-based generator of the
+// generated initial embeddings
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace psne

@@ -132,6 +132,12 @@ hipError_t run_export_dtree(const pixelsne_ctx* c, uint64_t* keys, uint32_t* per
 hipError_t run_rows_scan(uint32_t* a, int64_t rows, int64_t len, uint32_t* tot, hipStream_t s);
 // stable sort of (tb.key[0], index) on the low `bits` key bits
 hipError_t run_sort_bits(pixelsne_ctx* c, int bits);
+// stable LSD radix sort (8-bit digits) of the pairs (key[0][i], i) on the low
+// `bits` key bits; the result lands in key[*sorted], idx[*sorted].  hist holds
+// 256 * sort_blocks_for(n) words, dtot 256.
+int64_t sort_blocks_for(int64_t n);
+hipError_t sort_pairs32(uint32_t* const key[2], uint32_t* const idx[2], int64_t n, int bits,
+                        uint32_t* hist, uint32_t* dtot, hipStream_t s, int* sorted);
 hipError_t run_tree(pixelsne_ctx* c);
 hipError_t run_traverse(pixelsne_ctx* c, uint32_t* visits, uint32_t* used, double* Zi);
 hipError_t run_zsum(pixelsne_ctx* c);
@@ -175,6 +181,8 @@ hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, d
 // checks a caller's CSR (offsets monotone from 0 to nnz, columns in range and
 // off the diagonal); *bad (host) = number of violations.  Synchronises.
 hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad);
+hipError_t check_csr(const int64_t* row_ptr, const uint32_t* col, int64_t n, int64_t nnz,
+                     hipStream_t s, int64_t* bad);
 // scatter an internal-order [n][2] state-type array to caller order
 hipError_t run_to_user_v2(const pixelsne_ctx* c, const void* in, void* out);
 hipError_t run_map_perm(const pixelsne_ctx* c, const uint32_t* perm, uint32_t* out);

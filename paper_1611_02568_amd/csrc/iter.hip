@@ -458,16 +458,6 @@ __global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __rest
 // ---------------------------------------------------------------------------
 // Barnes-Hut traversal
 // ---------------------------------------------------------------------------
-// 1 / x for x >= 1: the hardware estimate refined by two Newton-Raphson steps
-// r <- r + r (1 - x r), each roughly squaring the relative error, which ends
-// within an ulp or two of the correctly rounded quotient
-__device__ __forceinline__ double rcp_nr(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
 
 // one accepted cell: Z_i += m q and R_i += m q^2 (z_i - c), q = 1 / (1 + d^2)
 // (Eq. (11), (12)); m in the state type
@@ -1084,14 +1074,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     }
 }
 
-// counter-based initial embedding: SplitMix64 (Steele, Lea & Flood 2014)
-// uniforms through the Box-Muller transform
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
+// the initial embedding: splitmix64 uniforms through the Box-Muller transform
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_state(const double* __restrict__ Y, T* __restrict__ zh,
@@ -1355,23 +1338,30 @@ hipError_t run_rows_scan(uint32_t* a, int64_t rows, int64_t len, uint32_t* tot, 
     return hipGetLastError();
 }
 
-hipError_t run_sort_bits(pixelsne_ctx* c, int bits) {
-    TreeBufs& tb = c->tb;
+int64_t sort_blocks_for(int64_t n) { return ceil_div(n, kRsTile); }
+
+hipError_t sort_pairs32(uint32_t* const key[2], uint32_t* const idx[2], int64_t n, int bits,
+                        uint32_t* hist, uint32_t* dtot, hipStream_t s, int* sorted) {
+    const int64_t nb = sort_blocks_for(n);
     const int passes = (bits + 7) / 8;
     int cur = 0;
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
-        k_rs_hist<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
-            tb.key[cur], c->n, shift, tb.hist, tb.sort_blocks);
-        k_rows_scan<<<256, kBlock, 0, c->stream>>>(tb.hist, tb.sort_blocks, tb.dtot);
+        k_rs_hist<<<dim3((unsigned)nb), kBlock, 0, s>>>(key[cur], n, shift, hist, nb);
+        k_rows_scan<<<256, kBlock, 0, s>>>(hist, nb, dtot);
         // the first pass generates the identity permutation itself
-        k_rs_scatter<<<dim3((unsigned)tb.sort_blocks), kBlock, 0, c->stream>>>(
-            tb.key[cur], p == 0 ? nullptr : tb.idx[cur], tb.key[cur ^ 1], tb.idx[cur ^ 1], c->n,
-            shift, tb.hist, tb.dtot, tb.sort_blocks);
+        k_rs_scatter<<<dim3((unsigned)nb), kBlock, 0, s>>>(
+            key[cur], p == 0 ? nullptr : idx[cur], key[cur ^ 1], idx[cur ^ 1], n, shift, hist,
+            dtot, nb);
         cur ^= 1;
     }
-    tb.sorted = cur;
+    *sorted = cur;
     return hipGetLastError();
+}
+
+hipError_t run_sort_bits(pixelsne_ctx* c, int bits) {
+    TreeBufs& tb = c->tb;
+    return sort_pairs32(tb.key, tb.idx, c->n, bits, tb.hist, tb.dtot, c->stream, &tb.sorted);
 }
 
 hipError_t run_tree(pixelsne_ctx* c) {

@@ -32,18 +32,11 @@ constexpr int kRpMaxLevel = 48;
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)ceil_div(n > 0 ? n : 1, kBlock)); }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
-
 __device__ __forceinline__ uint64_t rp_draw(uint64_t seed, int tree, int level, int64_t a,
                                             int which) {
-    uint64_t x = mix64(seed ^ (uint64_t)(uint32_t)tree);
-    x = mix64(x ^ (uint64_t)(uint32_t)level);
-    return mix64(x ^ (((uint64_t)a << 1) | (uint64_t)which));
+    uint64_t x = splitmix64(seed ^ (uint64_t)(uint32_t)tree);
+    x = splitmix64(x ^ (uint64_t)(uint32_t)level);
+    return splitmix64(x ^ (((uint64_t)a << 1) | (uint64_t)which));
 }
 
 __device__ __forceinline__ double as_f64(float v) { return (double)v; }

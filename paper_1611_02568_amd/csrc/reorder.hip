@@ -383,22 +383,27 @@ hipError_t run_export_P(const pixelsne_ctx* c, int64_t* row_ptr, int32_t* col, d
     return e;
 }
 
-hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad) {
+hipError_t check_csr(const int64_t* row_ptr, const uint32_t* col, int64_t n, int64_t nnz,
+                     hipStream_t s, int64_t* bad) {
     unsigned long long* d = nullptr;
     hipError_t e = hipMalloc((void**)&d, sizeof(unsigned long long));
     if (e != hipSuccess) return e;
     unsigned long long h = 0;
-    e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        const int64_t nb = ceil_div(c->n, kBlock) < 4096 ? ceil_div(c->n, kBlock) : 4096;
-        k_check_csr<<<dim3((unsigned)nb), kBlock, 0, c->stream>>>(c->row_ptr, c->col, c->n, c->nnz, d);
+        const int64_t nb = ceil_div(n, kBlock) < 4096 ? ceil_div(n, kBlock) : 4096;
+        k_check_csr<<<dim3((unsigned)nb), kBlock, 0, s>>>(row_ptr, col, n, nnz, d);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d);
     *bad = (int64_t)h;
     return e;
+}
+
+hipError_t run_check_csr(const pixelsne_ctx* c, int64_t* bad) {
+    return check_csr(c->row_ptr, c->col, c->n, c->nnz, c->stream, bad);
 }
 
 hipError_t run_to_user_v2(const pixelsne_ctx* c, const void* in, void* out) {

@@ -125,6 +125,17 @@ SIGNATURES = {
     "pixelsne_kl_noalloc": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "pixelsne_mlp_adam_step": (C.c_int, [_vp, _vp, C.c_float]),
     "pixelsne_knn2d": (C.c_int, [_vp, _vp]),
+    "pixelsne3_init_ex": (_vp, [_vp, _i64, _i32, _d, _i32, C.POINTER(Params)]),
+    "pixelsne3_init_with_P": (_vp, [_i64, _i64, _vp, _vp, _vp, _i32, C.POINTER(Params)]),
+    "pixelsne3_destroy": (None, [_vp]),
+    "pixelsne3_step": (C.c_int, [_vp, _i32]),
+    "pixelsne3_get_Y": (C.c_int, [_vp, _vp, _i32]),
+    "pixelsne3_set_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _i32]),
+    "pixelsne3_get_state": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int32)]),
+    "pixelsne3_gradient": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "pixelsne3_export_tree": (C.c_int, [_vp, C.POINTER(C.c_int64), _vp, _vp, _vp, _vp, _vp]),
+    "pixelsne3_kl": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "pixelsne_neighborhood_precision": (C.c_int, [_vp, _vp, _i32, C.POINTER(_i32), _i32,
                                                   C.POINTER(C.c_double)]),
 }
@@ -377,6 +388,124 @@ class Context:
     def close(self):
         if getattr(self, "_h", None):
             load().pixelsne_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context3:
+    """A 3-D PixelSNE embedding on the current GPU (wraps pixelsne3_ctx*):
+    voxel octree, three-axis scaling, FP64 throughout."""
+
+    def __init__(self, handle, n, r, params: Params, keep=()):
+        if not handle:
+            raise PixelSNEError(PSNE_E_INVAL, _err())
+        self._h = C.c_void_p(handle)
+        self.n = n
+        self.r = r
+        self.L = int(r).bit_length() - 1
+        self.params = params
+        self._keep = keep
+
+    @staticmethod
+    def _params(Y_init, dev, kw):
+        kw.setdefault("precision", FP64)
+        p = default_params(**kw)
+        if Y_init is not None:
+            Y_init = torch.as_tensor(Y_init, dtype=torch.float64).to(dev).contiguous()
+            p.Y_init = Y_init.data_ptr()
+        p.stream = _stream().value
+        return p, Y_init
+
+    @classmethod
+    def from_data(cls, X: torch.Tensor, perplexity: float, screen: int, Y_init=None, **kw):
+        """pixelsne3_init_ex on a device matrix X [n, D]; Y_init [n, 3] (y frame)."""
+        n, D = X.shape
+        p, Y_init = cls._params(Y_init, X.device, kw)
+        p.x_dtype = _X_TYPES[X.dtype]
+        h = load().pixelsne3_init_ex(_ptr(X.contiguous()), n, D, float(perplexity), screen,
+                                     C.byref(p))
+        return cls(h, n, screen, p, (Y_init,))
+
+    @classmethod
+    def from_P(cls, row_ptr, col, val, screen: int, Y_init=None, **kw):
+        """pixelsne3_init_with_P on a CSR P (int64 / int32 / float64)."""
+        dev = torch.device("cuda")
+        row_ptr = torch.as_tensor(row_ptr, dtype=torch.int64).to(dev).contiguous()
+        col = torch.as_tensor(col, dtype=torch.int32).to(dev).contiguous()
+        val = torch.as_tensor(val, dtype=torch.float64).to(dev).contiguous()
+        n = row_ptr.numel() - 1
+        p, Y_init = cls._params(Y_init, dev, kw)
+        h = load().pixelsne3_init_with_P(n, val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                         screen, C.byref(p))
+        return cls(h, n, screen, p, (Y_init,))
+
+    def step(self, n_iter: int = 1):
+        _check(load().pixelsne3_step(self._h, int(n_iter)))
+
+    def get_Y(self, frame: int = FRAME_Y) -> torch.Tensor:
+        dt = torch.int32 if frame == FRAME_SCREEN else torch.float64
+        out = torch.empty((self.n, 3), dtype=dt, device="cuda")
+        _check(load().pixelsne3_get_Y(self._h, _ptr(out), int(frame)))
+        return out
+
+    def set_state(self, z, s, u=None, g=None, iteration: int = 0):
+        f = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64).cuda().contiguous()
+        z, u, g = f(z), f(u), f(g)
+        sv = (C.c_double * 3)(*[float(x) for x in s])
+        _check(load().pixelsne3_set_state(self._h, _ptr(z), _ptr(u), _ptr(g), sv, int(iteration)))
+
+    def get_state(self):
+        z = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        u = torch.empty_like(z)
+        g = torch.empty_like(z)
+        sv = (C.c_double * 3)()
+        it = C.c_int32()
+        _check(load().pixelsne3_get_state(self._h, _ptr(z), _ptr(u), _ptr(g), sv, C.byref(it)))
+        return {"z": z, "u": u, "g": g, "s": (sv[0], sv[1], sv[2]), "iteration": it.value}
+
+    def gradient(self, alpha: float = 1.0):
+        """Voxel-frame bracket B = alpha*A - R/Z and its parts at the current state."""
+        B = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        A = torch.empty_like(B)
+        R = torch.empty_like(B)
+        Zi = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        vis = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        Z = C.c_double()
+        _check(load().pixelsne3_gradient(self._h, float(alpha), _ptr(B), _ptr(A), _ptr(R),
+                                         _ptr(Zi), _ptr(vis), C.byref(Z)))
+        return {"B": B, "A": A, "R": R, "Zi": Zi, "visits": vis, "Z": Z.value}
+
+    def export_tree(self):
+        L = self.L
+        sizes = (C.c_int64 * (L + 1))()
+        _check(load().pixelsne3_export_tree(self._h, sizes, None, None, None, None, None))
+        sizes = [sizes[i] for i in range(L + 1)]
+        m = sum(sizes)
+        keys = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        pre = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        cnt = torch.empty(max(m, 1), dtype=torch.int32, device="cuda")
+        sm = torch.empty((max(m, 1), 3), dtype=torch.float64, device="cuda")
+        s2 = (C.c_int64 * (L + 1))()
+        _check(load().pixelsne3_export_tree(self._h, s2, _ptr(keys), _ptr(perm), _ptr(pre),
+                                            _ptr(cnt), _ptr(sm)))
+        return {"level_size": sizes, "keys": keys, "perm": perm, "prefix": pre[:m],
+                "count": cnt[:m], "sum": sm[:m]}
+
+    def kl(self) -> float:
+        """KL(P || Q) of the 3-D embedding with the exact normaliser."""
+        v = C.c_double()
+        _check(load().pixelsne3_kl(self._h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pixelsne3_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "pixelsne.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pixelsne_[a-z_A-Z0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pixelsne3?_[a-z_A-Z0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -85,3 +85,34 @@ def test_null_context_calls(psne):
     assert lib.pixelsne_kl(None, None) == psne.PSNE_E_INVAL
     assert lib.pixelsne_knn2d(None, None) == psne.PSNE_E_INVAL
     assert lib.pixelsne_neighborhood_precision(None, None, 10, None, 1, None) == psne.PSNE_E_INVAL
+
+
+def test_null_context_calls_3d(psne):
+    lib = psne.load()
+    assert lib.pixelsne3_step(None, 1) == psne.PSNE_E_INVAL
+    assert lib.pixelsne3_get_Y(None, None, 0) == psne.PSNE_E_INVAL
+    assert lib.pixelsne3_kl(None, None) == psne.PSNE_E_INVAL
+    assert lib.pixelsne3_gradient(None, 1.0, None, None, None, None, None, None) == psne.PSNE_E_INVAL
+    lib.pixelsne3_destroy(None)
+
+
+@pytest.mark.parametrize("kw,r,n,frag", [
+    ({}, 64, 10, "device pointers"),                            # host CSR pointers
+    ({"precision": 0}, 64, 10, "FP64"),
+    ({"com_mode": 1}, 64, 10, "FP64"),
+    ({"tree": 1}, 64, 10, "FP64"),
+    ({}, 2048, 10, "power of two in [2, 1024]"),
+    ({}, 48, 10, "power of two in [2, 1024]"),
+    ({}, 64, 1, "n must be"),
+    ({"theta": 1.0}, 64, 10, "theta"),
+])
+def test_init3_validation(psne, kw, r, n, frag):
+    kw = dict({"precision": 1}, **kw)
+    p = psne.default_params(**kw)
+    rp = np.zeros(n + 1, np.int64)
+    col = np.zeros(4, np.int32)
+    val = np.zeros(4)
+    h = psne.load().pixelsne3_init_with_P(n, 4, rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                          r, C.byref(p))
+    assert not h
+    assert frag in psne.load().pixelsne_last_error().decode()
