@@ -375,6 +375,53 @@ def r_sweep(args):
     return out
 
 
+def three_d(args):
+    """The 3-D embedding (voxel octree of depth log2 r; Section 1 notes that
+    the method extends to 3-D) on the FP32 workload's data (1,000,000 x 128
+    mixture, perplexity 50), FP64 throughout, at cube sides r = 256 and
+    1,024, with the step size n / 12 (at this n the default 200 leaves the
+    initial blob nearly unchanged for hundreds of iterations).  Per
+    configuration: wall time per iteration over `--steps` iterations after
+    `--warmup` (one synchronisation at the end), and again over `--steps`
+    iterations ending at iteration 500 (the embedding formed), with the mean
+    visited cells per point, the cells of the octree and the exact-Z KL at
+    each point.  Setup (kNN, P) is not timed."""
+    import torch
+
+    from paper_1611_02568_amd import datagen, pixelsne
+
+    torch.cuda.set_device(0)
+    n = args.n
+    X, _, _ = datagen.zipf_mixture_1m(n=n)
+    y0 = torch.as_tensor(datagen.initial_embedding(n, seed=datagen.seed_for(2, 1), dim=3))
+    Xd = torch.from_numpy(X).cuda()
+    out = []
+    def window(ctx, first, last):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(last - first + 1)
+        ms = (time.perf_counter() - t0) * 1e3 / (last - first + 1)
+        g = ctx.gradient(1.0)
+        tr = ctx.export_tree()
+        return {"iterations": [first, last], "ms_per_iter": ms,
+                "points_iter_per_s": n / (ms * 1e-3),
+                "mean_visits": g["visits"].double().mean().item(),
+                "cells": int(sum(tr["level_size"])), "kl": ctx.kl()}
+
+    late = max(500, args.warmup + 2 * args.steps)
+    for r in (256, 1024):
+        ctx = pixelsne.Context3.from_data(Xd, 50.0, r, Y_init=y0, eta=n / 12.0)
+        ctx.step(args.warmup)
+        row = {"r": r, "eta": n / 12.0,
+               "early": window(ctx, args.warmup + 1, args.warmup + args.steps)}
+        ctx.step(late - args.steps - (args.warmup + args.steps))
+        row["formed"] = window(ctx, late - args.steps + 1, late)
+        log(f"[bench] 3-D {json.dumps(row)}")
+        out.append(row)
+        del ctx
+    return out
+
+
 def time_to_kl_large(args):
     """The 5,000,000 x 100 workload with 1% outliers (perplexity 30, k 90, screen
     4096): a 100-1024-1024-2 network is trained on the converged plain run of a
@@ -646,6 +693,9 @@ def main():
     ap.add_argument("--r-sweep", action="store_true",
                     help="run only the tree comparison (pixel tree at r = 512 ... 8,192 and the "
                          "data-driven tree) on the FP32 workload and print its own JSON line")
+    ap.add_argument("--three-d", action="store_true",
+                    help="run only the 3-D embedding (voxel octree) on the FP32 workload's data "
+                         "and print its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is "
@@ -658,6 +708,15 @@ def main():
                                     "screen sizes r against the data-driven tree",
                           "unit": "ms", "higher_is_better": False, "n_gpus": 1,
                           "data": "synthetic", "dtype": "f32", "steps": args.steps,
+                          "warmup": args.warmup, "result": res}), flush=True)
+        return
+
+    if args.three_d:
+        res = three_d(args)
+        print(json.dumps({"metric": "3-D embedding: ms per iteration and exact-Z KL, voxel "
+                                    "octree, 1M x 128",
+                          "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+                          "data": "synthetic", "dtype": "f64", "steps": args.steps,
                           "warmup": args.warmup, "result": res}), flush=True)
         return
 

@@ -12,12 +12,13 @@
 //   sort      stable radix sort of (key, index) on 3L bits (shared with the
 //             2-D path)
 //   tree      cells of every level numbered from the sorted keys (a cell of
-//             level l = a run of equal key >> 3(L - l)); leaf sums over each
-//             leaf's sorted positions, inner sums from the <= 8 children, one
-//             launch per level
-//   traverse  one thread per sorted position walks the octree depth first
-//             without a stack: children are consecutive cells, so after a
-//             cell it moves to the next sibling or climbs to the parent
+//             level l = a run of equal key >> 3(L - l)); leaf sums by a
+//             segmented scan per wavefront and the pieces of each leaf, inner
+//             sums from the <= 8 children, one launch per level
+//   traverse  the 64 points of a wavefront walk the union of their paths
+//             depth first without a stack: children are consecutive cells,
+//             so after a cell the wave moves to the next sibling or climbs
+//             to the parent
 //   zsum      Z = sum of the per-point terms (fixed order)
 //   attract   one wavefront per row of P
 //   update    gains / momentum step and per-block min / max of z + u
@@ -102,6 +103,8 @@ struct pixelsne3_ctx {
     uint32_t* fchild = nullptr;             // first child of each inner cell
     uint32_t* parent = nullptr;
     uint32_t* leaf_of = nullptr;            // [n] leaf of each sorted position
+    double* zs = nullptr;                   // [n][3] positions in sorted order
+    double* zscan = nullptr;                // [n][3] per-wave segmented leaf scan
     bool have_tree = false;
 
     std::vector<void*> allocs;
@@ -263,9 +266,43 @@ __device__ __forceinline__ void write_cell3(Node3* __restrict__ nodes, double* _
     nsum[3 * (int64_t)g + 2] = sz;
 }
 
-// leaves: the sum over each leaf's run of sorted positions
-__global__ __launch_bounds__(kBlock) void k3_leaves(const uint32_t* __restrict__ perm,
-                                                    const double* __restrict__ z, int64_t n,
+// Leaf sums, part 1 (one thread per sorted position): gather the point into
+// sorted order (zs) and run a segmented inclusive scan over each wave's 64
+// positions, segments = leaves (runs of equal leaf index), fixed shuffle
+// pattern.  zscan[p] then holds the sum of the positions of p's leaf from
+// max(leaf start, wave start) to p.
+__global__ __launch_bounds__(kBlock) void k3_leaf_scan(const uint32_t* __restrict__ perm,
+                                                       const uint32_t* __restrict__ leaf_of,
+                                                       const double* __restrict__ z, int64_t n,
+                                                       double* __restrict__ zs,
+                                                       double* __restrict__ zscan) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = p < n;
+    const int lane = lane_id();
+    double v[3] = {0.0, 0.0, 0.0};
+    uint32_t leaf = 0xFFFFFFFFu;
+    if (valid) {
+        const int64_t i = perm[p];
+        for (int d = 0; d < 3; d++) v[d] = z[3 * i + d];
+        leaf = leaf_of[p];
+        for (int d = 0; d < 3; d++) zs[3 * p + d] = v[d];
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t lu = __shfl_up(leaf, o, kWave);
+        double u[3];
+        for (int d = 0; d < 3; d++) u[d] = __shfl_up(v[d], o, kWave);
+        if (lane >= o && lu == leaf)
+            for (int d = 0; d < 3; d++) v[d] += u[d];
+    }
+    if (valid)
+        for (int d = 0; d < 3; d++) zscan[3 * p + d] = v[d];
+}
+
+// Leaf sums, part 2 (one thread per leaf): the piece in the wave of the
+// leaf's first position, the whole waves inside the leaf, and the piece in
+// the wave of its last position.
+__global__ __launch_bounds__(kBlock) void k3_leaves(const double* __restrict__ zscan, int64_t n,
                                                     int L, const Scalars3* __restrict__ sc,
                                                     const uint32_t* __restrict__ nstart,
                                                     Node3* __restrict__ nodes,
@@ -275,14 +312,15 @@ __global__ __launch_bounds__(kBlock) void k3_leaves(const uint32_t* __restrict__
     const uint32_t g = sc->level_base[L] + (uint32_t)q;
     const int64_t a = nstart[g];
     const int64_t e = g + 1 < sc->level_base[L + 1] ? (int64_t)nstart[g + 1] : n;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int64_t p = a; p < e; p++) {
-        const int64_t i = perm[p];
-        sx += z[3 * i];
-        sy += z[3 * i + 1];
-        sz += z[3 * i + 2];
+    const int64_t wa = a / kWave, wb = (e - 1) / kWave;
+    double sm[3];
+    for (int d = 0; d < 3; d++) sm[d] = zscan[3 * (e - 1) + d];
+    if (wa < wb) {
+        for (int d = 0; d < 3; d++) sm[d] += zscan[3 * (wa * kWave + kWave - 1) + d];
+        for (int64_t w = wa + 1; w < wb; w++)
+            for (int d = 0; d < 3; d++) sm[d] += zscan[3 * (w * kWave + kWave - 1) + d];
     }
-    write_cell3(nodes, nsum, g, sx, sy, sz, (uint32_t)(e - a), 0u);
+    write_cell3(nodes, nsum, g, sm[0], sm[1], sm[2], (uint32_t)(e - a), 0u);
 }
 
 // inner cells of level l: the sums of their (consecutive) children
@@ -312,62 +350,77 @@ __global__ __launch_bounds__(kBlock) void k3_inner(int l, const Scalars3* __rest
 // A leaf is always used; the leaf holding the point itself counts its other
 // points only, at their mean.  An inner cell of side w is used when
 // w^2 (b1 + b2 + b3) < theta^2 d^2, else its children are visited in order.
+//
+// The 64 points of a wavefront (neighbours in Morton order) walk the union of
+// their walks together: the wave steps through cells in depth-first order
+// and enters a cell's children when any of its lanes opens the cell.  A lane
+// takes part in a cell only if it opened every ancestor: `mark` holds the
+// level of the last cell the lane used (or skipped), and the lane sits out
+// every cell deeper than that until the wave returns to that level.  The
+// cell address is the same for the whole wave, so cells arrive through
+// scalar loads, and each lane's sums run in the order of its own walk.
 __global__ __launch_bounds__(kBlock) void k3_traverse(
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
-    const double* __restrict__ z, const Node3* __restrict__ nodes,
+    const double* __restrict__ zs, const Node3* __restrict__ nodes,
     const double* __restrict__ nsum, const uint32_t* __restrict__ parent,
     const Scalars3* __restrict__ sc, int64_t n, int L, double th2, double* __restrict__ R,
     double* __restrict__ Zi, uint32_t* __restrict__ visits) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n) return;
-    const int64_t i = perm[s];
-    const uint32_t own = leaf_of[s];
+    const bool valid = s < n;
+    const int64_t i = valid ? (int64_t)perm[s] : 0;
+    const uint32_t own = valid ? leaf_of[s] : 0xFFFFFFFFu;
     const double b0 = sc->s[0] * sc->s[0], b1 = sc->s[1] * sc->s[1], b2 = sc->s[2] * sc->s[2];
     double bs;
     {
 #pragma clang fp contract(off)
         bs = (b0 + b1) + b2;
     }
-    const double x = z[3 * i], y = z[3 * i + 1], w3 = z[3 * i + 2];
+    const double x = valid ? zs[3 * s] : 0.0, y = valid ? zs[3 * s + 1] : 0.0,
+                 w3 = valid ? zs[3 * s + 2] : 0.0;
     double rx = 0.0, ry = 0.0, rz = 0.0, zacc = 0.0;
     uint32_t nv = 0;
+    int mark = valid ? 0x7FFFFFFF : -1;
     uint32_t g = 0;
     int lvl = 0;
     for (;;) {
         const Node3 nd = nodes[g];
-        nv++;
-        bool use = true, descend = false;
-        double m = (double)nd.count, cx = nd.cx, cy = nd.cy, cz = nd.cz;
-        if (nd.child == 0u) {
-            if (g == own) {
-                m -= 1.0;
-                if (m > 0.0) {
-                    cx = (nsum[3 * (int64_t)g] - x) / m;
-                    cy = (nsum[3 * (int64_t)g + 1] - y) / m;
-                    cz = (nsum[3 * (int64_t)g + 2] - w3) / m;
-                } else {
+        bool open = false;
+        if (lvl <= mark) {
+            nv++;
+            bool use = true;
+            double m = (double)nd.count, cx = nd.cx, cy = nd.cy, cz = nd.cz;
+            if (nd.child == 0u) {
+                if (g == own) {
+                    m -= 1.0;
+                    if (m > 0.0) {
+                        cx = (nsum[3 * (int64_t)g] - x) / m;
+                        cy = (nsum[3 * (int64_t)g + 1] - y) / m;
+                        cz = (nsum[3 * (int64_t)g + 2] - w3) / m;
+                    } else {
+                        use = false;
+                    }
+                }
+            } else {
+                const double d2 = dist3(b0, b1, b2, x - cx, y - cy, w3 - cz);
+                const double wc = (double)(1u << (L - lvl));
+                if (!(mul_nc3(mul_nc3(wc, wc), bs) < mul_nc3(th2, d2))) {
                     use = false;
+                    open = true;
                 }
             }
-        } else {
-            const double d2 = dist3(b0, b1, b2, x - cx, y - cy, w3 - cz);
-            const double wc = (double)(1u << (L - lvl));
-            if (!(mul_nc3(mul_nc3(wc, wc), bs) < mul_nc3(th2, d2))) {
-                use = false;
-                descend = true;
+            if (use) {
+                const double dx = x - cx, dy = y - cy, dz = w3 - cz;
+                const double q = rcp_nr(1.0 + dist3(b0, b1, b2, dx, dy, dz));
+                const double mq = m * q;
+                zacc += mq;
+                const double f = mq * q;
+                rx += f * dx;
+                ry += f * dy;
+                rz += f * dz;
             }
+            mark = open ? 0x7FFFFFFF : lvl;
         }
-        if (use) {
-            const double dx = x - cx, dy = y - cy, dz = w3 - cz;
-            const double q = rcp_nr(1.0 + dist3(b0, b1, b2, dx, dy, dz));
-            const double mq = m * q;
-            zacc += mq;
-            const double f = mq * q;
-            rx += f * dx;
-            ry += f * dy;
-            rz += f * dz;
-        }
-        if (descend) {
+        if (ballot64(open)) {
             g = nd.child & kChildMask3;
             lvl++;
             continue;
@@ -387,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void k3_traverse(
         }
         if (done) break;
     }
+    if (!valid) return;
     R[3 * i] = rx;
     R[3 * i + 1] = ry;
     R[3 * i + 2] = rz;
@@ -424,15 +478,20 @@ __global__ __launch_bounds__(kBlock) void k3_zfinal(const double* __restrict__ p
 // ---------------------------------------------------------------------------
 // attraction A_i = sum_j p_ij w_ij (z_i - z_j) (Eq. 5 first term, Eq. 12)
 // ---------------------------------------------------------------------------
+// Rows are taken in the Morton order of their points (perm), so that waves
+// running at the same time gather the positions of nearby points, whose
+// neighbours largely coincide.
 __global__ __launch_bounds__(kBlock) void k3_attract(const int64_t* __restrict__ rp,
                                                      const uint32_t* __restrict__ col,
                                                      const double* __restrict__ val,
                                                      const double* __restrict__ z,
+                                                     const uint32_t* __restrict__ perm,
                                                      const Scalars3* __restrict__ sc, int64_t n,
                                                      double* __restrict__ A) {
     const int lane = lane_id();
-    const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
-    if (row >= n) return;
+    const int64_t wv = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (wv >= n) return;
+    const int64_t row = perm[wv];
     const double b0 = sc->s[0] * sc->s[0], b1 = sc->s[1] * sc->s[1], b2 = sc->s[2] * sc->s[2];
     const double x = z[3 * row], y = z[3 * row + 1], w3 = z[3 * row + 2];
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -847,6 +906,8 @@ hipError_t alloc3(pixelsne3_ctx* c) {
     if ((e = dalloc3(c, &c->fchild, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc3(c, &c->parent, 4 * (size_t)mx)) != hipSuccess) return e;
     if ((e = dalloc3(c, &c->leaf_of, 4 * (size_t)n)) != hipSuccess) return e;
+    if ((e = dalloc3(c, &c->zs, v3)) != hipSuccess) return e;
+    if ((e = dalloc3(c, &c->zscan, v3)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -886,7 +947,9 @@ hipError_t run_forces3(pixelsne3_ctx* c, uint32_t* visits) {
     k3_tree_nodes<<<dim3((unsigned)c->tree_blocks), kBlock, 0, c->stream>>>(
         keys, n, c->L, c->lvl_cnt, c->tree_blocks, c->ltot, c->sc, c->nstart, c->fchild,
         c->parent, c->leaf_of);
-    k3_leaves<<<grid_for(n), kBlock, 0, c->stream>>>(perm, c->z, n, c->L, c->sc, c->nstart,
+    k3_leaf_scan<<<grid_for(n), kBlock, 0, c->stream>>>(perm, c->leaf_of, c->z, n, c->zs,
+                                                        c->zscan);
+    k3_leaves<<<grid_for(n), kBlock, 0, c->stream>>>(c->zscan, n, c->L, c->sc, c->nstart,
                                                      c->nodes, c->nsum);
     for (int l = c->L - 1; l >= 0; l--) {
         const int64_t cap = (int64_t)1 << (3 * l);
@@ -894,12 +957,12 @@ hipError_t run_forces3(pixelsne3_ctx* c, uint32_t* visits) {
                                                                          c->nodes, c->nsum);
     }
     k3_traverse<<<grid_for(n), kBlock, 0, c->stream>>>(
-        perm, c->leaf_of, c->z, c->nodes, c->nsum, c->parent, c->sc, n, c->L,
+        perm, c->leaf_of, c->zs, c->nodes, c->nsum, c->parent, c->sc, n, c->L,
         c->prm.theta * c->prm.theta, c->R, c->Zi, visits);
     k3_zpart<<<dim3((unsigned)c->zpart_n), kBlock, 0, c->stream>>>(c->Zi, n, c->zpart);
     k3_zfinal<<<1, kBlock, 0, c->stream>>>(c->zpart, c->zpart_n, c->sc);
     k3_attract<<<dim3((unsigned)ceil_div(n, kBlock / kWave)), kBlock, 0, c->stream>>>(
-        c->row_ptr, c->col, c->val, c->z, c->sc, n, c->A);
+        c->row_ptr, c->col, c->val, c->z, perm, c->sc, n, c->A);
     c->have_tree = true;
     return hipGetLastError();
 }
