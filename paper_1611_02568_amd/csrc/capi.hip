@@ -172,8 +172,13 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &c->rp_int, 8 * (size_t)(n + 1))) != hipSuccess) return e;
     if ((e = dalloc(c, &c->ch_row, 4 * (size_t)(n + 1))) != hipSuccess) return e;
     if ((e = dalloc(c, &c->ch_tmp, 8 * (size_t)(n + 1))) != hipSuccess) return e;
-    if ((e = dalloc(c, &c->pk, 4 * (size_t)c->nnz)) != hipSuccess) return e;
-    if ((e = dalloc(c, &c->vch, state_bytes(c) * (size_t)c->nnz)) != hipSuccess) return e;
+    // FP32: column words and values interleaved in pk; FP64: values in vch
+    if (c->prm.precision == PSNE_FP64) {
+        if ((e = dalloc(c, &c->pk, 4 * (size_t)c->nnz)) != hipSuccess) return e;
+        if ((e = dalloc(c, &c->vch, 8 * (size_t)c->nnz)) != hipSuccess) return e;
+    } else {
+        if ((e = dalloc(c, &c->pk, 8 * (size_t)c->nnz)) != hipSuccess) return e;
+    }
     if ((e = dalloc(c, &c->zh2, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->u2, v2)) != hipSuccess) return e;
     if ((e = dalloc(c, &c->g2, v2)) != hipSuccess) return e;

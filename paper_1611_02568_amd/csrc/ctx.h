@@ -89,8 +89,9 @@ struct pixelsne_ctx {
     int64_t* rp_int = nullptr;               // [n + 1] internal-order row offsets
     uint32_t* ch_row = nullptr;              // [n + 1] first internal row of each chunk
     int64_t* ch_tmp = nullptr;               // [n + 1] chunk numbering scratch
-    uint32_t* pk = nullptr;                  // [nnz] internal column | row-in-chunk << 27
-    void* vch = nullptr;                     // [nnz] values (state type)
+    uint32_t* pk = nullptr;                  // [nnz] internal column | row-in-chunk << 27;
+                                             // FP32: [nnz][2], each word beside its value
+    void* vch = nullptr;                     // FP64: [nnz] values
 
     // one iteration captured as a HIP graph, one per state-buffer parity
     // (renumbering swaps the state buffers with their spares)

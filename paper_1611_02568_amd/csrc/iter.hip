@@ -895,8 +895,10 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             acc[t / kChunkRows][t % kChunkRows][1] = T(0);
         }
         __syncthreads();
-        const __amdgpu_buffer_rsrc_t rpk = stream_rsrc(pk + e0, e1 - e0);
-        const __amdgpu_buffer_rsrc_t rval = stream_rsrc(val + e0, e1 - e0);
+        constexpr bool kPair = sizeof(T) == 4;      // FP32: word and value side by side
+        const __amdgpu_buffer_rsrc_t rpk =
+            kPair ? stream_rsrc(pk + 2 * e0, 2 * (e1 - e0)) : stream_rsrc(pk + e0, e1 - e0);
+        const __amdgpu_buffer_rsrc_t rval = kPair ? rpk : stream_rsrc(val + e0, e1 - e0);
         for (int64_t b = e0 + (int64_t)w * kWave; b < e1; b += (int64_t)kBlock * kBatches<T>) {
             uint32_t j[kBatches<T>];
             int r[kBatches<T>];
@@ -905,10 +907,18 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             for (int q = 0; q < kBatches<T>; q++) {
                 const int64_t x = b + q * kBlock + lane;
                 const int off = (int)(x - e0);
-                const uint32_t v = stream_load<uint32_t>(rpk, off);
+                uint32_t v;
+                if constexpr (kPair) {
+                    const auto pv = __builtin_amdgcn_raw_buffer_load_b64(rpk, off * 8, 0,
+                                                                         kStreamPolicy);
+                    v = pv[0];
+                    p[q] = (T)__uint_as_float(pv[1]);
+                } else {
+                    v = stream_load<uint32_t>(rpk, off);
+                    p[q] = stream_load<T>(rval, off);
+                }
                 j[q] = v & kColMask;
                 r[q] = x < e1 ? (int)(v >> kColBits) : kChunkRows;
-                p[q] = stream_load<T>(rval, off);
             }
             V zj[kBatches<T>];
 #pragma unroll

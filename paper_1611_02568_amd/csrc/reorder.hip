@@ -124,6 +124,19 @@ constexpr int kBuildThreads = 1024;
 // (bitonic), then every aligned run of 64 is sorted again by (row, column).
 // A value is found in its caller row by binary search for the caller's column
 // (rows of the caller's P are ascending).
+// One nonzero of the chunked copy.  FP32: the column word and the value side
+// by side in pk ([nnz][2] words, one 64-bit load in the attraction); FP64:
+// column words in pk, values in vch.
+__device__ __forceinline__ void put_nz(uint32_t* __restrict__ pk, float* __restrict__,
+                                       int64_t e, uint32_t key, float v) {
+    reinterpret_cast<uint2*>(pk)[e] = uint2{key, __float_as_uint(v)};
+}
+__device__ __forceinline__ void put_nz(uint32_t* __restrict__ pk, double* __restrict__ vch,
+                                       int64_t e, uint32_t key, double v) {
+    pk[e] = key;
+    vch[e] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBuildThreads) void k_chunk_build(
     const int64_t* __restrict__ rp_c, const uint32_t* __restrict__ col_c,
@@ -146,10 +159,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_chunk_build(
             for (int64_t lr = 0; lr < nr; lr++) {
                 const int64_t s0 = rp_c[orig[ra + lr]], o = rp_int[ra + lr];
                 const int64_t len = rp_int[ra + lr + 1] - o;
-                for (int64_t e = t; e < len; e += kBuildThreads) {
-                    pk[o + e] = inv[col_c[s0 + e]] | ((uint32_t)lr << kColBits);
-                    vch[o + e] = val_c[s0 + e];
-                }
+                for (int64_t e = t; e < len; e += kBuildThreads)
+                    put_nz(pk, vch, o + e, inv[col_c[s0 + e]] | ((uint32_t)lr << kColBits),
+                           val_c[s0 + e]);
             }
             continue;
         }
@@ -217,8 +229,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_chunk_build(
                 if (col_c[mid] <= cu) lo = mid;
                 else hi = mid;
             }
-            pk[e0 + p] = k;                                // column | row << 27
-            vch[e0 + p] = val_c[lo];
+            put_nz(pk, vch, e0 + p, k, val_c[lo]);         // column | row << 27
         }
         __syncthreads();
     }

@@ -469,3 +469,36 @@ def test_kl_matches_oracle(psne, small_problem, prec):
     got = ctx.get_state()
     ref = oracle.kl(got["z"].double().cpu().numpy(), np.array(got["s"]), P)
     assert abs(ctx.kl() - ref) <= 1e-5 * ref
+
+
+def test_plain_entry_point(psne):
+    """pixelsne_init(X, n, D, perplexity, screen_w, screen_h) with every default
+    (FP32 X, generated initial embedding): the P it builds is the oracle's and
+    the embedding's exact-Z KL falls over the run."""
+    X, _ = datagen.small_mixture(n=2000, dtype=np.float32)
+    ctx = psne.Context.from_data_plain(torch.as_tensor(X).cuda(), 30.0, 512)
+    rp, col, val = (t.cpu().numpy() for t in ctx.export_P())
+    orp, ocol, oval = oracle.build_P(X.astype(np.float64), 30.0)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    np.testing.assert_allclose(val, oval, rtol=6e-8)
+    k0 = ctx.kl()
+    ctx.step(300)
+    st = ctx.stats()
+    assert st.iteration == 300 and st.precision == psne.FP32
+    assert ctx.kl() < 0.6 * k0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nonfinite_step_reports_numeric_error(psne, prec):
+    """A step size so large that the update overflows (u = -eta g B = +-inf):
+    the step reports PSNE_E_NUMERIC.  Every kernel of that iteration works on
+    finite inputs, and the context is released without stepping again."""
+    n = 500
+    X, _ = datagen.small_mixture(n=n, D=10, seed=4)
+    P = oracle.build_P(X, 10.0)
+    ctx = psne.Context.from_P(*P, screen=256, precision=prec, eta=1e308, reorder_every=0,
+                              Y_init=torch.as_tensor(datagen.initial_embedding(n, seed=5)))
+    with pytest.raises(psne.PixelSNEError) as err:
+        ctx.step(1)
+    assert err.value.code == psne.PSNE_E_NUMERIC
+    ctx.close()
