@@ -44,7 +44,9 @@ def main():
         ctx = pixelsne.Context.from_data(Xd, 50.0, 2048, Y_init=y0,
                                          precision=pixelsne.FP64 if args.fp64 else pixelsne.FP32)
         print("setup done", flush=True)
-        ctx.step(args.warmup)
+        for done in range(0, args.warmup, 100):
+            ctx.step(min(100, args.warmup - done))
+            print(f"warm-up {min(done + 100, args.warmup)}", flush=True)
         for done in range(0, args.steps, 100):
             ctx.step(min(100, args.steps - done))
             print(f"iterations {args.warmup + min(done + 100, args.steps)}", flush=True)
