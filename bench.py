@@ -750,7 +750,7 @@ def main():
     dom = max(per, key=per.get)
     if dom == "traverse":
         ach = main32["traverse"]["TFLOPs"]
-        roof = {"bound": "alu", "kernel": "k_traverse<float, false>", "achieved": ach,
+        roof = {"bound": "alu", "kernel": "k_traverse<float, false, true, false>", "achieved": ach,
                 "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
                 "traffic": None}
     elif dom == "attract":
