@@ -49,10 +49,11 @@ struct alignas(32) Node {
 };
 
 // The traversal's copy of a cell for the FP32 path (16 bytes): the
-// representative point rounded to FP32, and count and child as in Node.
+// representative point and the point count rounded to FP32 (the mass the FP32
+// force terms use), and child as in Node.
 struct alignas(16) CellF {
     float cx, cy;
-    uint32_t count;
+    float mass;
     uint32_t child;
 };
 

@@ -288,7 +288,7 @@ __device__ __forceinline__ void put_cell(Node* __restrict__ nodes, CellF* __rest
     nodes[g].count = count;
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
-    if (c32) c32[g] = CellF{(float)cx, (float)cy, count, child};
+    if (c32) c32[g] = CellF{(float)cx, (float)cy, (float)count, child};
 }
 
 // Leaves: a run head sums its run's positions in order (FP64).

@@ -282,7 +282,7 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __re
     nodes[g].count = count;
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
-    if (c32) c32[g] = CellF{(float)cx, (float)cy, count, child};
+    if (c32) c32[g] = CellF{(float)cx, (float)cy, (float)count, child};
 }
 
 // Leaf sums, part 1 (one thread per sorted position): gather the position
@@ -516,17 +516,6 @@ __device__ __forceinline__ float mulf_nc(float a, float b) {
     return a * b;
 }
 
-// one used cell in the FP32 path: q = 1 / (1 + d^2) in FP32, Z_i summed in FP64
-__device__ __forceinline__ void bh_term32(float d2, float dx, float dy, float m, double& zacc,
-                                          float& rx, float& ry) {
-    const float q = __builtin_amdgcn_rcpf(1.0f + d2);
-    const float mq = m * q;
-    zacc += (double)mq;
-    const float f = mq * q;
-    rx += f * dx;
-    ry += f * dy;
-}
-
 // Write a stack entry (four wave-uniform words, in scalar registers) into
 // lane `sel` of the four per-lane stack registers.  With one scalar operand
 // per vector instruction the lane select goes through m0 (an input operand:
@@ -629,44 +618,63 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             CellF grp[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) grp[q] = cells32[first + q];
+            float zg = 0.f;
 #pragma unroll
             for (uint32_t q = 0; q < 4; q++) {
                 if (q >= nsib) break;
                 const uint32_t c = first + q;
                 const CellF nd = grp[q];
                 uint64_t om = 0;
+                // per lane: the distance, q = 1 / (1 + d^2), the mass term m q
+                // and whether the lane takes the cell; the sums follow below
+                float dx, dy, qq, mq;
+                bool use;
                 if (nd.child != 0u) {
-                    const float dx = zxf - nd.cx, dy = zyf - nd.cy;
+                    dx = zxf - nd.cx;
+                    dy = zyf - nd.cy;
                     const float d2 = dist2f(b1f, b2f, dx, dy);
-                    const bool near = !(diag2f < mulf_nc(th2f, d2));
-                    om = ballot64(near) & mask;
-                    const bool use = act && !near;
-                    bh_term32(d2, dx, dy, use ? (float)nd.count : 0.f, zacc, rx, ry);
+                    const uint64_t near = ballot64(!(diag2f < mulf_nc(th2f, d2)));
+                    om = near & mask;
+                    use = __builtin_amdgcn_inverse_ballot_w64(mask & ~near);
+                    qq = __builtin_amdgcn_rcpf(1.0f + d2);
+                    mq = qq * nd.mass;
                     if (COUNT) {
                         nuse += use ? 1u : 0u;
                         nvis += act ? 1u : 0u;
                     }
                 } else {
                     float cx = nd.cx, cy = nd.cy;
-                    float m = (float)nd.count;
-                    bool use = act;
+                    float m = nd.mass;
+                    use = act;
                     if (c == own) {
-                        const uint32_t others = nd.count - 1u;
+                        // the exact count from the FP64 record (its FP32 copy
+                        // is rounded above 2^24)
+                        const uint32_t others = nodes[c].count - 1u;
                         m = (float)others;
                         if (others > 0u && com_mode != PSNE_COM_CELL_CENTER) {
                             const double2 sm = nsum[c];
-                            cx = (float)((sm.x - zx) / (double)others);
-                            cy = (float)((sm.y - zy) / (double)others);
+                            const double inv = 1.0 / (double)others;
+                            cx = (float)((sm.x - zx) * inv);
+                            cy = (float)((sm.y - zy) * inv);
                         }
                         use = act && others > 0u;
                     }
-                    const float dx = zxf - cx, dy = zyf - cy;
-                    bh_term32(dist2f(b1f, b2f, dx, dy), dx, dy, use ? m : 0.f, zacc, rx, ry);
+                    dx = zxf - cx;
+                    dy = zyf - cy;
+                    qq = __builtin_amdgcn_rcpf(1.0f + dist2f(b1f, b2f, dx, dy));
+                    mq = qq * m;
                     if (COUNT) {
                         nuse += use ? 1u : 0u;
                         nvis += act ? 1u : 0u;
                     }
                 }
+                // every lane adds the term; a lane that does not take the cell
+                // adds zeros, which leaves its sums bit for bit as they were
+                mq = use ? mq : 0.f;
+                zg += mq;
+                const float f = mq * qq;
+                rx = fmaf(f, dx, rx);
+                ry = fmaf(f, dy, ry);
                 if (om) {
                     st.push(sp, (int)(nd.child & 0x3FFFFFFFu),
                             (int)(((nd.child >> 30) + 1u) | ((uint32_t)(level + 1) << 8)),
@@ -674,6 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                     sp++;
                 }
             }
+            zacc += (double)zg;
         } else {
         const double diag2 = ldexp(bsum, 2 * (L - level));
         // the group's records (children are consecutive) in one batch of scalar loads
@@ -689,25 +698,25 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             // Every lane evaluates the term; lanes that do not take the cell
             // add it with mass 0, which leaves their sums bit for bit as they
             // were and keeps the loop free of divergent branches.
+            double dx, dy, d2;
+            T m;
+            bool use;
             if (nd.child != 0u) {
                 // inner cell: the opening test and, for lanes that accept, the
                 // force term share one distance
-                const double dx = zx - nd.cx, dy = zy - nd.cy;
-                const double d2 = dist2(b1, b2, dx, dy);
-                const bool near = !(diag2 < mul_nc(th2, d2));
-                om = ballot64(near) & mask;   // every lane runs this loop
-                const bool use = act && !near;
-                bh_term<T>(d2, dx, dy, use ? (T)nd.count : T(0), zacc, rx, ry);
-                if (COUNT) {
-                    nuse += use ? 1u : 0u;
-                    nvis += act ? 1u : 0u;
-                }
+                dx = zx - nd.cx;
+                dy = zy - nd.cy;
+                d2 = dist2(b1, b2, dx, dy);
+                const uint64_t near = ballot64(!(diag2 < mul_nc(th2, d2)));
+                om = near & mask;   // every lane runs this loop
+                use = __builtin_amdgcn_inverse_ballot_w64(mask & ~near);
+                m = (T)nd.count;
             } else {
                 // leaf (one pixel): always used; at its own leaf a point counts
                 // the others only, at their centre of mass in mass mode
                 double cx = nd.cx, cy = nd.cy;
-                T m = (T)nd.count;
-                bool use = act;
+                m = (T)nd.count;
+                use = act;
                 if (c == own) {
                     const uint32_t others = nd.count - 1u;
                     m = (T)others;
@@ -718,12 +727,14 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                     }
                     use = act && others > 0u;
                 }
-                const double dx = zx - cx, dy = zy - cy;
-                bh_term<T>(dist2(b1, b2, dx, dy), dx, dy, use ? m : T(0), zacc, rx, ry);
-                if (COUNT) {
-                    nuse += use ? 1u : 0u;
-                    nvis += act ? 1u : 0u;
-                }
+                dx = zx - cx;
+                dy = zy - cy;
+                d2 = dist2(b1, b2, dx, dy);
+            }
+            bh_term<T>(d2, dx, dy, use ? m : T(0), zacc, rx, ry);
+            if (COUNT) {
+                nuse += use ? 1u : 0u;
+                nvis += act ? 1u : 0u;
             }
             if (om) {
                 st.push(sp, (int)(nd.child & 0x3FFFFFFFu),
