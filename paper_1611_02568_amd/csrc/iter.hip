@@ -842,6 +842,33 @@ __device__ __forceinline__ void seg_scan(T& x, T& y, int key, uint64_t cont) {
     if (cont & (1ull << 32)) seg_step<0x143, 0xC>(x, y, key);
 }
 
+// An in-row step of the FP32 scan with the lanes that take a value known in
+// scalar registers: a row shift by d moves each lane's value to one lane d
+// above, so a source lane whose destination does not take it sends 0 (SRC:
+// bit s set when lane s + d takes), and the step is a select and an add
+// with the shift folded in, per coordinate.
+template <int CTRL>
+__device__ __forceinline__ void seg_step_src(float& x, float& y, uint64_t src) {
+    const bool send = __builtin_amdgcn_inverse_ballot_w64(src);
+    const float sx = send ? x : 0.f, sy = send ? y : 0.f;
+    x += dpp_t<CTRL, 0xF>(sx);
+    y += dpp_t<CTRL, 0xF>(sy);
+}
+
+// FP32: lane l takes the value d lanes below when lanes l - d + 1 .. l all
+// continue their predecessor's run (A_d, from CONT by doubling); the two
+// broadcasts across rows keep the key comparison.
+template <>
+__device__ __forceinline__ void seg_scan<float>(float& x, float& y, int key, uint64_t cont) {
+    const uint64_t a2 = cont & (cont << 1), a4 = a2 & (a2 << 2), a8 = a4 & (a4 << 4);
+    if (cont) seg_step_src<0x111>(x, y, cont >> 1);
+    if (a2) seg_step_src<0x112>(x, y, a2 >> 2);
+    if (a4) seg_step_src<0x114>(x, y, a4 >> 4);
+    if (a8) seg_step_src<0x118>(x, y, a8 >> 8);
+    if (cont & ((1ull << 16) | (1ull << 48))) seg_step<0x142, 0xA>(x, y, key);
+    if (cont & (1ull << 32)) seg_step<0x143, 0xC>(x, y, key);
+}
+
 // The chunk's column words and values are read once per iteration through
 // buffer resources over the chunk's range: 32-bit offsets, and the hardware's
 // range check returns 0 past the end instead of a per-lane select.  Loads
