@@ -182,10 +182,14 @@ def run_gpu(args):
         if name == "fp64" and args.no_fp64:
             continue
         ctx.step(args.warmup)
-        saved = ctx.get_state() if args.reps > 1 else None
-        # the timed region: K iterations after the warm-up, with HIP events
-        # recorded by the library on its streams between the passes
-        ms, pt = timed_window(ctx, K, profiled=not args.plain_timing)
+        saved = ctx.get_state()
+
+        def restore(st):
+            ctx.set_state(st["z"], st["s"], u=st["u"], g=st["g"], iteration=st["iteration"])
+
+        # the timed region: K iterations after the warm-up as the library
+        # runs them (graph replay), between two events on the caller's stream
+        ms, _ = timed_window(ctx, K, profiled=False)
         log(f"[bench] {name}: {K} iterations in {ms:.1f} ms")
         if args.plain_timing:
             out[name] = {"value": n * K / (ms / 1e3), "ms_per_step": ms / K}
@@ -195,30 +199,43 @@ def run_gpu(args):
         vis = gr["visits"].double().mean().item()
         used = gr["used"].double().mean().item()
         del gr
-        res = pass_metrics(n, nnz, sb, K, ms, pt, vis, used, ctx.stats().n_nodes)
+        n_nodes = ctx.stats().n_nodes
+        # the same K iterations again from the saved state with HIP events
+        # recorded by the library between the passes (per-pass times; the
+        # pass-timed iterations launch their kernels directly)
+        restore(saved)
+        ms_p, pt = timed_window(ctx, K)
+        res = pass_metrics(n, nnz, sb, K, ms, pt, vis, used, n_nodes)
         res["iterations"] = [args.warmup + 1, args.warmup + K]
+        res["ms_per_step_pass_timed"] = ms_p / K
         log(f"[bench] {name}: passes {json.dumps({k: round(v, 4) for k, v in res['pass_ms'].items()})}")
         # repetitions: the same K iterations again from the saved state
         reps = [ms / K]
         for _ in range(args.reps - 1):
-            ctx.set_state(saved["z"], saved["s"], u=saved["u"], g=saved["g"],
-                          iteration=saved["iteration"])
-            ms_r, _ = timed_window(ctx, K)
+            restore(saved)
+            ms_r, _ = timed_window(ctx, K, profiled=False)
             reps.append(ms_r / K)
         res["reps_ms_per_step"] = reps
         res["ms_per_step_mean"] = float(np.mean(reps))
         res["ms_per_step_sd"] = float(np.std(reps, ddof=1)) if len(reps) > 1 else 0.0
         del saved
-        # steady state: iterations 981-1000 of the run (untimed iterations up to 980)
+        # steady state: iterations 981-1000 of the run (untimed iterations up
+        # to 980), timed the same way, then again with the pass events
         it = ctx.stats().iteration
         if it < 980:
             ctx.step(980 - it)
         it0 = ctx.stats().iteration
-        ms_s, pt_s = timed_window(ctx, 20)
+        saved = ctx.get_state()
+        ms_s, _ = timed_window(ctx, 20, profiled=False)
         gr = ctx.gradient(1.0)
-        st = pass_metrics(n, nnz, sb, 20, ms_s, pt_s, gr["visits"].double().mean().item(),
-                          gr["used"].double().mean().item(), ctx.stats().n_nodes)
+        vis_s = gr["visits"].double().mean().item()
+        used_s = gr["used"].double().mean().item()
         del gr
+        n_nodes_s = ctx.stats().n_nodes
+        restore(saved)
+        _, pt_s = timed_window(ctx, 20)
+        del saved
+        st = pass_metrics(n, nnz, sb, 20, ms_s, pt_s, vis_s, used_s, n_nodes_s)
         st["iterations"] = [it0 + 1, it0 + 20]
         res["steady_state"] = st
         log(f"[bench] {name}: steady state (iterations {it0 + 1}-{it0 + 20}) "
