@@ -563,6 +563,10 @@ struct WaveStack {
     }
 };
 
+// a sibling group's records, read together
+struct alignas(16) CellF4 { CellF c[4]; };
+struct alignas(32) Node4 { Node n[4]; };
+
 // F32T (FP32 path only): the opening test and the distances in FP32 on the
 // cells' FP32 copies (cells32), operands and operations rounded as the FP64
 // test's expression written in single precision; otherwise in FP64 on nodes.
@@ -615,9 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
         if constexpr (F32T) {
             // (w w)(b1 + b2) with w = 2^(L - level): a power-of-two scaling, exact in FP32
             const float diag2f = ldexpf(bsumf, 2 * (L - level));
-            CellF grp[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) grp[q] = cells32[first + q];
+            // the group's four records (children are consecutive; the array
+            // has three records of slack at its end) in one 64-byte scalar load
+            const CellF4 g4 = *reinterpret_cast<const CellF4*>(cells32 + first);
+            const CellF* grp = g4.c;
             float zg = 0.f;
 #pragma unroll
             for (uint32_t q = 0; q < 4; q++) {
@@ -686,9 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
         } else {
         const double diag2 = ldexp(bsum, 2 * (L - level));
         // the group's records (children are consecutive) in one batch of scalar loads
-        Node grp[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) grp[q] = nodes[first + q];
+        const Node4 g4 = *reinterpret_cast<const Node4*>(nodes + first);
+        const Node* grp = g4.n;
 #pragma unroll
         for (uint32_t q = 0; q < 4; q++) {
             if (q >= nsib) break;
