@@ -143,11 +143,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
         __syncthreads();
     }
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    // every item's key and value loaded up front, so that the loads overlap
+    // instead of waiting behind each round's barriers
+    uint32_t keys[kRsItems], vals[kRsItems];
+#pragma unroll
+    for (int j = 0; j < kRsItems; j++) {
+        const int64_t p = base + j * kBlock + t;
+        keys[j] = p < n ? kin[p] : 0u;
+        vals[j] = p < n ? (vin ? vin[p] : (uint32_t)p) : 0u;
+    }
+#pragma unroll
     for (int j = 0; j < kRsItems; j++) {
         const int64_t p = base + j * kBlock + t;
         const bool valid = p < n;
-        const uint32_t key = valid ? kin[p] : 0u;
-        const uint32_t val = valid ? (vin ? vin[p] : (uint32_t)p) : 0u;
+        const uint32_t key = keys[j];
+        const uint32_t val = vals[j];
         const uint32_t d = (key >> shift) & 255u;
         wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
         __syncthreads();
