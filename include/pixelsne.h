@@ -127,7 +127,14 @@ typedef struct {
     int32_t knn_explore;      /* its rounds of neighbour exploring [1] */
     int32_t attract_blocks_per_cu; /* blocks per compute unit of the persistent grid that
                                  runs the attraction's row sums on the second stream beside
-                                 the tree and the traversal, 1..16 [2] */
+                                 the tree and the traversal, 0..16 [2]; 0: none (the
+                                 helper below then does all of them, after Z) */
+    int32_t attract_help_blocks_per_cu; /* blocks per compute unit of the helper that
+                                 joins the row sums on the context's stream once the
+                                 traversal and Z are done, taking whatever row chunks the
+                                 second stream has not started, 0..16 [3]; 0: no helper.
+                                 At least one of the two is >= 1.  Results are identical
+                                 for every setting. */
 } pixelsne_params;
 
 /* Fill *p with the defaults shown in brackets above. */
@@ -479,7 +486,7 @@ psne_status pixelsne_mlp_place(pixelsne_mlp* m, const float* X, int64_t n, int32
  * stream, knn_trees, knn_leaf, knn_explore.  precision must be PSNE_FP64,
  * com_mode PSNE_COM_MASS and tree PSNE_TREE_PIXEL (else PSNE_E_UNSUPPORTED);
  * the layout fields (reorder_*, data_order, graphs, opening_fp64,
- * attract_blocks_per_cu) are not read.
+ * attract_blocks_per_cu, attract_help_blocks_per_cu) are not read.
  * r is a power of two in [2, 1024]; 2 <= n <= 2^25.
  */
 typedef struct pixelsne3_ctx pixelsne3_ctx;

@@ -68,8 +68,12 @@ psne_status check_params(const pixelsne_params* p) {
     if (p->tree != PSNE_TREE_PIXEL && p->tree != PSNE_TREE_DATA) return invalid("unknown tree");
     if (p->knn_trees < 0 || p->knn_leaf < 0 || p->knn_explore < 0)
         return invalid("knn_trees, knn_leaf and knn_explore must be >= 0");
-    if (p->attract_blocks_per_cu < 1 || p->attract_blocks_per_cu > 16)
-        return invalid("attract_blocks_per_cu must be in [1, 16]");
+    if (p->attract_blocks_per_cu < 0 || p->attract_blocks_per_cu > 16)
+        return invalid("attract_blocks_per_cu must be in [0, 16]");
+    if (p->attract_help_blocks_per_cu < 0 || p->attract_help_blocks_per_cu > 16)
+        return invalid("attract_help_blocks_per_cu must be in [0, 16]");
+    if (p->attract_blocks_per_cu == 0 && p->attract_help_blocks_per_cu == 0)
+        return invalid("attract_blocks_per_cu and attract_help_blocks_per_cu are both 0");
     if (p->tree == PSNE_TREE_DATA && p->com_mode != PSNE_COM_MASS) {
         set_error("the data-driven tree takes centres of mass only (PSNE_COM_MASS)");
         return PSNE_E_UNSUPPORTED;
@@ -121,6 +125,7 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
         hipSuccess)
         return e;
     c->side_blocks = (int64_t)c->prm.attract_blocks_per_cu * (cus > 0 ? cus : 1);
+    c->help_blocks = (int64_t)c->prm.attract_help_blocks_per_cu * (cus > 0 ? cus : 1);
     c->zpart_n = ceil_div(n, 256);
     if ((e = dalloc(c, &c->zpart, sizeof(double) * c->zpart_n)) != hipSuccess) return e;
     c->mm_n = attract_block_count(n);
@@ -316,6 +321,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->knn_leaf = 0;
     p->knn_explore = 1;
     p->attract_blocks_per_cu = 2;
+    p->attract_help_blocks_per_cu = 3;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,

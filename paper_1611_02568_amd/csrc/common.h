@@ -34,6 +34,8 @@ struct DevScalars {
     int32_t nonfinite;  // set when a non-finite position appears
     int64_t n_nodes;    // occupied cells of the last tree
     int64_t n_chunks;   // row chunks of the attraction's copy of P
+    uint32_t att_next;  // the attraction's work queue: next row chunk to take
+    uint32_t att_pad;
     uint32_t level_size[kMaxLevelsAll];
     uint32_t level_base[kMaxLevelsAll + 1];
 };

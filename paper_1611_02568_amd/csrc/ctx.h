@@ -101,11 +101,13 @@ struct pixelsne_ctx {
     // a second stream, forked after the snap pass and joined before the
     // update, so that the memory-bound sums share the GPU with the sort, tree
     // and the ALU-bound traversal.  side_blocks: its persistent grid, sized
-    // to leave most of each CU to the traversal.
+    // to leave most of each CU to the traversal.  help_blocks: the grid of
+    // the helper that joins the sums on the main stream after Z.
     void* A = nullptr;
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t side_blocks = 0;
+    int64_t help_blocks = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int32_t parity = 0;
     bool graph_failed = false;

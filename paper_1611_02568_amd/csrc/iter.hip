@@ -912,14 +912,21 @@ template <> __device__ __forceinline__ double stream_load<double>(__amdgpu_buffe
 // second stream beside the traversal: 8 beats 10, 12, 16, 20 and 24)
 template <typename T> constexpr int kBatches = 8;
 
-// One block per row chunk (grid-stride over the chunks).  Wavefront w takes
+// One block per row chunk.  MODE 0 (the iteration's row sums, on the second
+// stream) and MODE 2 (a helper launched on the main stream once the traversal
+// and Z are done) take chunks from one work queue, a counter in DevScalars
+// that k_finalize clears for the next iteration: while the main stream is
+// busy the second stream's few blocks per CU do the work, and whatever is
+// left when it frees the CUs is shared with the helper's blocks.  Which
+// block takes a chunk does not change its sums.  MODE 1 walks the chunks
+// grid-stride.  Wavefront w takes
 // the runs w, w + 4, ... of the chunk's nonzeros (column order, each run of
 // 64 ordered by row): loads kBatches runs at once, computes the terms
 // p_ij w_ij (z_i - z_j) with z_i from LDS, sums each row's terms across the
 // run with a segmented scan, and adds the totals to its own LDS partial sums
 // (one writer per address, no atomics).  Thread t < rows of the chunk then
 // adds the four waves' partials in a fixed order.  Sums are therefore
-// reproducible.  MODE 0 (the iteration) writes the row sums A_i in the
+// reproducible.  MODE 0 and 2 (the iteration) write the row sums A_i in the
 // internal order; MODE 1 (the gradient hook) writes A_i and the full
 // gradient B_i = alpha A_i - R_i / Z in the caller's order, after the
 // traversal.
@@ -927,17 +934,28 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_attract(
     const uint32_t* __restrict__ ch_row, const int64_t* __restrict__ rp_int,
     const uint32_t* __restrict__ pk, const T* __restrict__ val, const T* __restrict__ z,
-    const T* __restrict__ R, const DevScalars* __restrict__ sc, double alpha,
+    const T* __restrict__ R, DevScalars* __restrict__ sc, double alpha,
     const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout) {
     using V = v2_t<T>;
     __shared__ T acc[4][kChunkRows][2];
     __shared__ V zrow[kChunkRows];
+    __shared__ uint32_t s_next;
+    constexpr bool kQueue = MODE != 1;
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const double s0 = sc->s[0], s1 = sc->s[1];
     const T b1 = (T)(s0 * s0), b2 = (T)(s1 * s1);
     const int64_t nch = sc->n_chunks;
     constexpr uint32_t kColMask = (1u << kColBits) - 1u;
-    for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    int64_t ch = blockIdx.x;
+    if (kQueue) {
+        if (t == 0) s_next = atomicAdd(&sc->att_next, 1u);
+        __syncthreads();
+        ch = s_next;
+    }
+    while (ch < nch) {
+        // the next chunk's ticket is taken while this one is summed
+        uint32_t ticket = 0;
+        if (kQueue && t == 0) ticket = atomicAdd(&sc->att_next, 1u);
         const int64_t ra = ch_row[ch];
         const int nr = (int)((int64_t)ch_row[ch + 1] - ra);
         const int64_t e0 = rp_int[ra], e1 = rp_int[ra + nr];
@@ -999,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             const T mx = ((acc[0][t][0] + acc[1][t][0]) + acc[2][t][0]) + acc[3][t][0];
             const T my = ((acc[0][t][1] + acc[1][t][1]) + acc[2][t][1]) + acc[3][t][1];
             const int64_t i = ra + t;
-            if (MODE == 0) {
+            if (MODE != 1) {
                 reinterpret_cast<V*>(Aout)[i] = V{mx, my};
             } else {
                 const double Z = sc->Z;
@@ -1010,7 +1028,9 @@ __global__ __launch_bounds__(kBlock) void k_attract(
                 if (Bout) reinterpret_cast<V*>(Bout)[orig[i]] = V{bx, by};
             }
         }
+        if (kQueue && t == 0) s_next = ticket;
         __syncthreads();
+        ch = kQueue ? (int64_t)s_next : ch + gridDim.x;
     }
 }
 
@@ -1133,6 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
             sc->s[d] = sc->s[d] * (gamma / (double)r);
         }
         if (advance) sc->t += 1;
+        sc->att_next = 0;
     }
 }
 
@@ -1516,18 +1537,27 @@ hipError_t run_attract(pixelsne_ctx* c, double alpha, void* A, void* B) {
     return hipGetLastError();
 }
 
-// The iteration's attraction row sums into c->A, on the second stream.
-static hipError_t run_attract_sums(pixelsne_ctx* c) {
-    const dim3 grid((unsigned)c->side_blocks);
+// The iteration's attraction row sums into c->A: MODE 0 on the second
+// stream, or (HELP) the MODE 2 helper on the main stream, both taking chunks
+// from the same queue.
+template <int MODE>
+static hipError_t launch_attract_sums(pixelsne_ctx* c, const dim3 grid, hipStream_t s) {
     if (fp64(c))
-        k_attract<double, 0><<<grid, kBlock, 0, c->side>>>(
+        k_attract<double, MODE><<<grid, kBlock, 0, s>>>(
             c->ch_row, c->rp_int, c->pk, (const double*)c->vch, (const double*)c->z, nullptr,
             c->sc, 0.0, c->orig, (double*)c->A, nullptr);
     else
-        k_attract<float, 0><<<grid, kBlock, 0, c->side>>>(
+        k_attract<float, MODE><<<grid, kBlock, 0, s>>>(
             c->ch_row, c->rp_int, c->pk, (const float*)c->vch, (const float*)c->z, nullptr,
             c->sc, 0.0, c->orig, (float*)c->A, nullptr);
     return hipGetLastError();
+}
+
+static hipError_t run_attract_sums(pixelsne_ctx* c, bool help) {
+    const int64_t blocks = help ? c->help_blocks : c->side_blocks;
+    if (blocks == 0) return hipSuccess;
+    if (!help) return launch_attract_sums<0>(c, dim3((unsigned)blocks), c->side);
+    return launch_attract_sums<2>(c, dim3((unsigned)blocks), c->stream);
 }
 
 static hipError_t run_update(pixelsne_ctx* c) {
@@ -1568,7 +1598,7 @@ static hipError_t iteration(pixelsne_ctx* c, hipEvent_t* ev) {
     if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
     if ((e = mark(9, c->side)) != hipSuccess) return e;
-    if ((e = run_attract_sums(c)) != hipSuccess) return e;
+    if ((e = run_attract_sums(c, false)) != hipSuccess) return e;
     if ((e = mark(10, c->side)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
@@ -1579,6 +1609,7 @@ static hipError_t iteration(pixelsne_ctx* c, hipEvent_t* ev) {
     if ((e = mark(4, c->stream)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;
     if ((e = mark(5, c->stream)) != hipSuccess) return e;
+    if ((e = run_attract_sums(c, true)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess) return e;
     if ((e = mark(6, c->stream)) != hipSuccess) return e;
     if ((e = run_update(c)) != hipSuccess) return e;

@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("knn_leaf", C.c_int32),
         ("knn_explore", C.c_int32),
         ("attract_blocks_per_cu", C.c_int32),
+        ("attract_help_blocks_per_cu", C.c_int32),
     ]
 
 

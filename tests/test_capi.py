@@ -68,7 +68,12 @@ def test_init_validation(psne, args, frag):
 @pytest.mark.parametrize("kw,frag", [({"theta": 1.0}, "theta"), ({"precision": 7}, "precision"),
                                      ({"com_mode": 3}, "com_mode"), ({"struct_size": 8}, "struct_size"),
                                      ({"eta": 0.0}, "eta"), ({"reorder_growth": 0.5}, "reorder_growth"),
-                                     ({"reorder_every": -1}, "reorder_every")])
+                                     ({"reorder_every": -1}, "reorder_every"),
+                                     ({"attract_blocks_per_cu": 17}, "attract_blocks_per_cu"),
+                                     ({"attract_help_blocks_per_cu": -1},
+                                      "attract_help_blocks_per_cu"),
+                                     ({"attract_blocks_per_cu": 0,
+                                       "attract_help_blocks_per_cu": 0}, "both 0")])
 def test_params_validation(psne, kw, frag):
     X = np.zeros((10, 4), np.float32)
     assert not _init(psne, X.ctypes.data, 10, 4, 3.0, 512, 512, **kw)
