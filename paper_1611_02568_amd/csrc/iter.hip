@@ -16,6 +16,7 @@
 //   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -430,18 +431,50 @@ __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, in
                keys[nodes[g].start], com_mode);
 }
 
-// One level of inner cells, one thread per cell.
-__global__ __launch_bounds__(kBlock) void k_tree_level(const uint32_t* __restrict__ keys, int l,
-                                                       int L, int com_mode,
+// Up to kGroupLevels consecutive levels of inner cells in one launch.  Block
+// b owns the cells [b K, (b + 1) K) of the group's top level and, below
+// them, their descendants, which form one contiguous range per level (cells
+// are numbered in Morton order within a level, and the children of a cell
+// are consecutive): thread 0 follows first_child down to find the ranges,
+// then the block sums the levels bottom-up, one level per barrier.  Each cell
+// is summed by inner_cell exactly as one launch per level would.
+constexpr int kGroupLevels = 5;
+constexpr int64_t kGroupBlocks = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_tree_group(const uint32_t* __restrict__ keys,
+                                                       int ltop, int lbot, int L, int com_mode,
+                                                       uint32_t K,
                                                        const DevScalars* __restrict__ sc,
                                                        const uint32_t* __restrict__ first_child,
                                                        Node* __restrict__ nodes,
                                                        CellF* __restrict__ c32,
                                                        double2* __restrict__ nsum) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t m = sc->level_size[l];
-    if (t >= m) return;
-    inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, (uint32_t)t, m);
+    __shared__ uint32_t lo[kGroupLevels], hi[kGroupLevels];
+    const int t = threadIdx.x;
+    const uint32_t mtop = sc->level_size[ltop];
+    const uint32_t a0 = blockIdx.x * K;
+    if (a0 >= mtop) return;
+    if (t == 0) {
+        uint32_t a = a0, e = a0 + K < mtop ? a0 + K : mtop;
+        lo[0] = a;
+        hi[0] = e;
+        for (int l = ltop; l < lbot; l++) {
+            // children of the level-l cells [a, e) at level l + 1
+            const uint32_t base = sc->level_base[l], nbase = sc->level_base[l + 1];
+            const uint32_t m = sc->level_size[l];
+            a = first_child[base + a] - nbase;
+            e = e < m ? first_child[base + e] - nbase : sc->level_size[l + 1];
+            lo[l + 1 - ltop] = a;
+            hi[l + 1 - ltop] = e;
+        }
+    }
+    __syncthreads();
+    for (int l = lbot; l >= ltop; l--) {
+        const uint32_t m = sc->level_size[l];
+        for (uint32_t x = lo[l - ltop] + t; x < hi[l - ltop]; x += kBlock)
+            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, x, m);
+        __syncthreads();
+    }
 }
 
 // Levels top..0 in one block (a level l holds at most 4^l cells, so at most
@@ -1475,10 +1508,14 @@ hipError_t run_tree(pixelsne_ctx* c) {
             tb.wlast);
     }
     const int top = c->L - 1 < kTopLevel ? c->L - 1 : kTopLevel;
-    for (int l = c->L - 1; l > top; l--) {
-        const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;
-        k_tree_level<<<grid_for(cap < c->n ? cap : c->n), kBlock, 0, c->stream>>>(
-            keys, l, c->L, c->prm.com_mode, c->sc, tb.first_child, tb.nodes, tb.cells32, tb.nsum);
+    for (int lbot = c->L - 1; lbot > top; lbot -= kGroupLevels) {
+        const int ltop = lbot - (kGroupLevels - 1) > top ? lbot - (kGroupLevels - 1) : top + 1;
+        // the top level holds at most min(4^ltop, n) cells; K of them per block
+        const int64_t cap = ltop < 31 ? std::min((int64_t)1 << (2 * ltop), c->n) : c->n;
+        const int64_t K = ceil_div(cap, kGroupBlocks);
+        k_tree_group<<<dim3((unsigned)ceil_div(cap, K)), kBlock, 0, c->stream>>>(
+            keys, ltop, lbot, c->L, c->prm.com_mode, (uint32_t)K, c->sc, tb.first_child, tb.nodes,
+            tb.cells32, tb.nsum);
     }
     if (top >= 0)
         k_tree_top<<<1, kTopThreads, 0, c->stream>>>(keys, top, c->L, c->prm.com_mode, c->sc,
