@@ -748,6 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
             double dx, dy, d2;
             T m;
             bool use;
+            uint64_t take = mask;   // lanes that take the cell
             if (nd.child != 0u) {
                 // inner cell: the opening test and, for lanes that accept, the
                 // force term share one distance
@@ -756,7 +757,8 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 d2 = dist2(b1, b2, dx, dy);
                 const uint64_t near = ballot64(!(diag2 < mul_nc(th2, d2)));
                 om = near & mask;   // every lane runs this loop
-                use = __builtin_amdgcn_inverse_ballot_w64(mask & ~near);
+                take = mask & ~near;
+                use = __builtin_amdgcn_inverse_ballot_w64(take);
                 m = (T)nd.count;
             } else {
                 // leaf (one pixel): always used; at its own leaf a point counts
@@ -778,7 +780,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 dy = zy - cy;
                 d2 = dist2(b1, b2, dx, dy);
             }
-            bh_term<T>(d2, dx, dy, use ? m : T(0), zacc, rx, ry);
+            // skipped when every lane opens the cell (the FP64 reciprocal is
+            // a long sequence; the FP32 path gains nothing from the branch)
+            if (take) bh_term<T>(d2, dx, dy, use ? m : T(0), zacc, rx, ry);
             if (COUNT) {
                 nuse += use ? 1u : 0u;
                 nvis += act ? 1u : 0u;
