@@ -906,18 +906,39 @@ __device__ __forceinline__ void seg_step_src(float& x, float& y, uint64_t src) {
     y += dpp_t<CTRL, 0xF>(sy);
 }
 
+// Lanes s .. s + w - 1 that continue the run of lane s - 1 without a break:
+// the lowest run of set bits of CONT starting at bit s, as a lane mask.
+__device__ __forceinline__ uint64_t run_from(uint64_t cont, int s, int w) {
+    const uint64_t wmask = (1ull << w) - 1ull;
+    const uint64_t x = (cont >> s) & wmask;
+    return (((~x & (x + 1ull)) - 1ull) & wmask) << s;   // bits below the lowest clear bit
+}
+
 // FP32: lane l takes the value d lanes below when lanes l - d + 1 .. l all
-// continue their predecessor's run (A_d, from CONT by doubling); the two
-// broadcasts across rows keep the key comparison.
+// continue their predecessor's run (A_d, from CONT by doubling).  Across
+// rows the same masks decide: rows 1 and 3 take lanes 15 and 47 (one
+// broadcast), then rows 2 and 3 take lane 31 (a scalar read), each lane when
+// its run reaches back to that lane.  The multiplier 1 or 0 leaves a lane
+// that does not take the value exactly as it was.
 template <>
-__device__ __forceinline__ void seg_scan<float>(float& x, float& y, int key, uint64_t cont) {
+__device__ __forceinline__ void seg_scan<float>(float& x, float& y, int, uint64_t cont) {
     const uint64_t a2 = cont & (cont << 1), a4 = a2 & (a2 << 2), a8 = a4 & (a4 << 4);
     if (cont) seg_step_src<0x111>(x, y, cont >> 1);
     if (a2) seg_step_src<0x112>(x, y, a2 >> 2);
     if (a4) seg_step_src<0x114>(x, y, a4 >> 4);
     if (a8) seg_step_src<0x118>(x, y, a8 >> 8);
-    if (cont & ((1ull << 16) | (1ull << 48))) seg_step<0x142, 0xA>(x, y, key);
-    if (cont & (1ull << 32)) seg_step<0x143, 0xC>(x, y, key);
+    const uint64_t ta = run_from(cont, 16, 16) | run_from(cont, 48, 16);
+    if (ta) {
+        const float m = __builtin_amdgcn_inverse_ballot_w64(ta) ? 1.f : 0.f;
+        x = fmaf(dpp_t<0x142, 0xF>(x), m, x);   // row r gets lane 16 r - 1; row 0 gets 0
+        y = fmaf(dpp_t<0x142, 0xF>(y), m, y);
+    }
+    const uint64_t tb = run_from(cont, 32, 32);
+    if (tb) {
+        const float m = __builtin_amdgcn_inverse_ballot_w64(tb) ? 1.f : 0.f;
+        x = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31)), m, x);
+        y = fmaf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), 31)), m, y);
+    }
 }
 
 // The chunk's column words and values are read once per iteration through
@@ -975,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
     const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout) {
     using V = v2_t<T>;
     __shared__ T acc[4][kChunkRows][2];
-    __shared__ V zrow[kChunkRows];
+    __shared__ V zrow[kChunkRows + 1];   // entry kChunkRows: 0 for lanes past the end
     __shared__ uint32_t s_next;
     constexpr bool kQueue = MODE != 1;
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
@@ -996,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_attract(
         const int64_t ra = ch_row[ch];
         const int nr = (int)((int64_t)ch_row[ch + 1] - ra);
         const int64_t e0 = rp_int[ra], e1 = rp_int[ra + nr];
-        if (t < kChunkRows) zrow[t] = t < nr ? reinterpret_cast<const V*>(z)[ra + t] : V{T(0), T(0)};
+        if (t <= kChunkRows) zrow[t] = t < nr ? reinterpret_cast<const V*>(z)[ra + t] : V{T(0), T(0)};
         if (t < 4 * kChunkRows) {
             acc[t / kChunkRows][t % kChunkRows][0] = T(0);
             acc[t / kChunkRows][t % kChunkRows][1] = T(0);
@@ -1032,18 +1053,22 @@ __global__ __launch_bounds__(kBlock) void k_attract(
             for (int q = 0; q < kBatches<T>; q++) zj[q] = reinterpret_cast<const V*>(z)[j[q]];
 #pragma unroll
             for (int q = 0; q < kBatches<T>; q++) {
-                const V zi = zrow[r[q] < kChunkRows ? r[q] : 0];
+                const V zi = zrow[r[q]];
                 const T dx = zi.x - zj[q].x, dy = zi.y - zj[q].y;
                 const T wq = rcp_fast<T>(T(1) + b1 * dx * dx + b2 * dy * dy);
                 const T pw = p[q] * wq;
                 T sx = pw * dx, sy = pw * dy;
-                const int nk = __shfl_down(r[q], 1, kWave);
-                const bool last = lane == kWave - 1 || nk != r[q];
-                // lanes past the chunk's end (key kChunkRows) count as runs of
-                // their own: their sums are never used
-                const uint64_t cont = ~((ballot64(last) << 1) | 1ull) & ballot64(r[q] < kChunkRows);
+                // lane l continues the run of lane l - 1 when both carry the
+                // same row (the row of lane l - 1 by a whole-wave shift; lane 0
+                // sees -1); lanes past the chunk's end (row kChunkRows) belong
+                // to no run and are never written.  A lane ends its run when
+                // the next lane does not continue it.
+                const int rprev = __builtin_amdgcn_update_dpp(-1, r[q], 0x138, 0xF, 0xF, false);
+                const uint64_t live = ballot64(r[q] < kChunkRows);
+                const uint64_t cont = ballot64(rprev == r[q]) & live;
+                const uint64_t last = ~(cont >> 1) & live;
                 seg_scan<T>(sx, sy, r[q], cont);
-                if (r[q] < kChunkRows && last) {
+                if (__builtin_amdgcn_inverse_ballot_w64(last)) {
                     acc[w][r[q]][0] += sx;
                     acc[w][r[q]][1] += sy;
                 }
