@@ -214,14 +214,24 @@ __global__ __launch_bounds__(kBlock) void k_tree_count(const uint32_t* __restric
 // Number each cell: for every level, the rank of the cell holding sorted
 // position s.  Positions that open a cell write its start and first
 // child (children of a cell are consecutive in the next level).
+// Then the leaf sums, part 1: gather the position into sorted order and run a
+// segmented inclusive scan over each wave's 64 positions (segments = leaves,
+// fixed shuffle pattern, FP64).  A leaf that starts and ends inside the wave
+// gets its sum here; otherwise the wave records the piece of the segment that
+// covers its first position (wfirst) and the piece of the segment that covers
+// its last position (wlast).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     const uint32_t* __restrict__ keys, int64_t n, int L, const uint32_t* __restrict__ off,
     int64_t nb, const uint32_t* __restrict__ ltot, DevScalars* __restrict__ sc,
     uint32_t* __restrict__ first_child, Node* __restrict__ nodes,
-    uint32_t* __restrict__ leaf_of) {
+    uint32_t* __restrict__ leaf_of, const uint32_t* __restrict__ perm, const T* __restrict__ z,
+    double2* __restrict__ nsum, T* __restrict__ zs, double2* __restrict__ wfirst,
+    double2* __restrict__ wlast) {
+    using V = v2_t<T>;
     __shared__ uint32_t wc[4][kMaxLevels];
     __shared__ uint32_t lbase[kMaxLevels + 1];
-    const int t = threadIdx.x, w = t >> 6;
+    const int t = threadIdx.x, w = t >> 6, lane = lane_id();
     if (t == 0) {
         uint32_t b = 0;
         for (int l = 0; l <= L; l++) {
@@ -240,13 +250,17 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     }
     const int64_t s = (int64_t)blockIdx.x * kBlock + t;
     const bool valid = s < n;
+    V p = V{T(0), T(0)};
+    if (valid) p = reinterpret_cast<const V*>(z)[perm[s]];
     const int l0 = valid ? first_new_level(keys, s, L) : L + 1;
+    // the next position starts a new leaf (or there is none)
+    const bool tail = valid && (s == n - 1 || keys[s + 1] != keys[s]);
     for (int l = 0; l <= L; l++) {
         const uint64_t b = ballot64(l0 <= l);
-        if (lane_id() == 0) wc[w][l] = (uint32_t)__popcll(b);
+        if (lane == 0) wc[w][l] = (uint32_t)__popcll(b);
     }
     __syncthreads();
-    const uint64_t le = lanemask_lt() | (1ull << lane_id());
+    const uint64_t le = lanemask_lt() | (1ull << lane);
     uint32_t rank[kMaxLevels];
 #pragma unroll
     for (int l = 0; l < kMaxLevels; l++) {
@@ -259,16 +273,43 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
             rank[l] = 0;
         }
     }
-    if (!valid) return;
-    leaf_of[s] = lbase[L] + rank[L];
+    const uint32_t lf = lbase[L] + rank[L];
+    if (valid) {
+        leaf_of[s] = lf;
+        reinterpret_cast<V*>(zs)[s] = p;
 #pragma unroll
-    for (int l = 0; l < kMaxLevels; l++) {
-        if (l <= L && l0 <= l) {
-            const uint32_t gid = lbase[l] + rank[l];
-            nodes[gid].start = (uint32_t)s;
-            nodes[gid].level = (uint32_t)l;
-            first_child[gid] = l < L ? lbase[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L] : 0u;
+        for (int l = 0; l < kMaxLevels; l++) {
+            if (l <= L && l0 <= l) {
+                const uint32_t gid = lbase[l] + rank[l];
+                nodes[gid].start = (uint32_t)s;
+                nodes[gid].level = (uint32_t)l;
+                first_child[gid] = l < L ? lbase[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L] : 0u;
+            }
         }
+    }
+    // leaf sums: a position opens its leaf when its key differs from the
+    // previous position's (l0 <= L)
+    double vx = (double)p.x, vy = (double)p.y;
+    bool f = valid && l0 <= L;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double ax = __shfl_up(vx, o, kWave), ay = __shfl_up(vy, o, kWave);
+        const bool af = __shfl_up((int)f, o, kWave) != 0;
+        if (lane >= o) {
+            if (!f) {
+                vx = ax + vx;
+                vy = ay + vy;
+            }
+            f = f || af;
+        }
+    }
+    const int64_t wv = s / kWave;
+    if (tail) {
+        if (f) nsum[lf] = double2{vx, vy};
+        else wfirst[wv] = double2{vx, vy};
+    } else if (valid && lane == kWave - 1) {
+        wlast[wv] = double2{vx, vy};
+        if (!f) wfirst[wv] = double2{vx, vy};
     }
 }
 
@@ -294,53 +335,6 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __re
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
     if (c32) c32[g] = CellF{(float)cx, (float)cy, (float)count, child};
-}
-
-// Leaf sums, part 1 (one thread per sorted position): gather the position
-// into sorted order and run a segmented inclusive scan over each wave's 64
-// positions (segments = leaves, fixed shuffle pattern, FP64).  A leaf that
-// starts and ends inside the wave gets its sum here; otherwise the wave
-// records the piece of the segment that covers its first position (wfirst)
-// and the piece of the segment that covers its last position (wlast).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_leaf_scan(
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ leaf_of,
-    const T* __restrict__ z, int64_t n, double2* __restrict__ nsum, T* __restrict__ zs,
-    double2* __restrict__ wfirst, double2* __restrict__ wlast) {
-    using V = v2_t<T>;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int lane = lane_id();
-    const bool valid = s < n;
-    const uint32_t lf = valid ? leaf_of[s] : 0xFFFFFFFFu;
-    V p = V{T(0), T(0)};
-    if (valid) {
-        p = reinterpret_cast<const V*>(z)[perm[s]];
-        reinterpret_cast<V*>(zs)[s] = p;
-    }
-    const bool head = valid && (s == 0 || leaf_of[s - 1] != lf);
-    const bool tail = valid && (s == n - 1 || leaf_of[s + 1] != lf);
-    double vx = (double)p.x, vy = (double)p.y;
-    bool f = head;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const double ax = __shfl_up(vx, o, kWave), ay = __shfl_up(vy, o, kWave);
-        const bool af = __shfl_up((int)f, o, kWave) != 0;
-        if (lane >= o) {
-            if (!f) {
-                vx = ax + vx;
-                vy = ay + vy;
-            }
-            f = f || af;
-        }
-    }
-    const int64_t wv = s / kWave;
-    if (tail) {
-        if (f) nsum[lf] = double2{vx, vy};
-        else wfirst[wv] = double2{vx, vy};
-    } else if (valid && lane == kWave - 1) {
-        wlast[wv] = double2{vx, vy};
-        if (!f) wfirst[wv] = double2{vx, vy};
-    }
 }
 
 // Leaf sums, part 2 (one thread per leaf): a leaf that spans several waves
@@ -1518,19 +1512,18 @@ hipError_t run_tree(pixelsne_ctx* c) {
         keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks);
     k_rows_scan<<<dim3((unsigned)(c->L + 1)), kBlock, 0, c->stream>>>(tb.lvl_cnt, tb.tree_blocks,
                                                                       tb.ltot);
-    k_tree_nodes<<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
-        keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child, tb.nodes,
-        tb.leaf_of);
     if (fp64(c)) {
-        k_leaf_scan<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            perm, tb.leaf_of, (const double*)c->z, c->n, tb.nsum, (double*)tb.zs, tb.wfirst,
+        k_tree_nodes<double><<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child,
+            tb.nodes, tb.leaf_of, perm, (const double*)c->z, tb.nsum, (double*)tb.zs, tb.wfirst,
             tb.wlast);
         k_tree_leaves<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
             tb.wlast);
     } else {
-        k_leaf_scan<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            perm, tb.leaf_of, (const float*)c->z, c->n, tb.nsum, (float*)tb.zs, tb.wfirst,
+        k_tree_nodes<float><<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
+            keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child,
+            tb.nodes, tb.leaf_of, perm, (const float*)c->z, tb.nsum, (float*)tb.zs, tb.wfirst,
             tb.wlast);
         k_tree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
             keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
