@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kQB = 128;       // query rows per block
 constexpr int kCB = 128;       // candidate columns per tile
-constexpr int kKC = 16;        // reduction chunk staged in LDS (2 threads x 8 per row)
+constexpr int kKC = 32;        // reduction chunk staged in LDS (2 threads x 16 per row)
 constexpr int kCap = 512;      // candidate list capacity per row
 constexpr int kMargin = 32;    // extra candidates kept for the exact re-rank
 
@@ -105,12 +105,13 @@ __device__ void compact_row(int q, int64_t grow, uint32_t* cnt, uint32_t* thr, u
 // chunk's global loads in flight while the current one is multiplied.
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-template <typename X>
+template <typename X, bool VEC>
 __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm, int64_t n,
                                                         int D, const float* __restrict__ nrm,
                                                         int kp, uint64_t* __restrict__ cand,
                                                         uint32_t* __restrict__ cand_cnt,
                                                         uint32_t* __restrict__ cand_thr) {
+    static_assert(!VEC || std::is_same<X, float>::value, "16-byte loads of FP32 rows");
     // [buffer][k][row]: rows 0..127 queries, 128..255 candidates
     __shared__ float S[2][kKC][2 * kQB + 4];
     __shared__ uint32_t cnt[kQB];
@@ -147,11 +148,30 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
         const X* pq = Xm + (okq ? rq : 0) * (int64_t)D + kH * (t & 1);
         const X* pc = Xm + (okc ? rc : 0) * (int64_t)D + kH * (t & 1);
         auto fetch = [&](int k0) {
-            const int lim = D - k0 - kH * (t & 1);          // elements left in the row
+            if constexpr (VEC) {
+                // FP32 rows, D a multiple of kKC, 16-byte aligned: whole chunks
+                // in 16-byte loads
 #pragma unroll
-            for (int e = 0; e < kH; e++) {
-                g[e] = (okq && e < lim) ? to_f32(pq[k0 + e]) : 0.0f;
-                g[kH + e] = (okc && e < lim) ? to_f32(pc[k0 + e]) : 0.0f;
+                for (int u = 0; u < kH; u += 4) {
+                    // rows past n read row 0 (pq, pc are clamped) and are zeroed
+                    const float4 a = *reinterpret_cast<const float4*>(pq + k0 + u);
+                    const float4 c = *reinterpret_cast<const float4*>(pc + k0 + u);
+                    g[u] = okq ? a.x : 0.0f;
+                    g[u + 1] = okq ? a.y : 0.0f;
+                    g[u + 2] = okq ? a.z : 0.0f;
+                    g[u + 3] = okq ? a.w : 0.0f;
+                    g[kH + u] = okc ? c.x : 0.0f;
+                    g[kH + u + 1] = okc ? c.y : 0.0f;
+                    g[kH + u + 2] = okc ? c.z : 0.0f;
+                    g[kH + u + 3] = okc ? c.w : 0.0f;
+                }
+            } else {
+                const int lim = D - k0 - kH * (t & 1);          // elements left in the row
+#pragma unroll
+                for (int e = 0; e < kH; e++) {
+                    g[e] = (okq && e < lim) ? to_f32(pq[k0 + e]) : 0.0f;
+                    g[kH + e] = (okc && e < lim) ? to_f32(pc[k0 + e]) : 0.0f;
+                }
             }
         };
         auto store = [&](int buf) {
@@ -758,8 +778,15 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
         k_knn_candidates_i8<<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(
             (const uint8_t*)Xm, n, D, nrm_i, kp, cand, ccnt, cthr);
     } else {
-        k_knn_candidates<X><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(Xm, n, D, nrm, kp,
-                                                                             cand, ccnt, cthr);
+        bool vec = false;
+        if constexpr (std::is_same<X, float>::value)
+            vec = D % kKC == 0 && ((uintptr_t)Xm & 15) == 0;
+        if (vec)
+            k_knn_candidates<float, true><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(
+                (const float*)Xm, n, D, nrm, kp, cand, ccnt, cthr);
+        else
+            k_knn_candidates<X, false><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(
+                Xm, n, D, nrm, kp, cand, ccnt, cthr);
     }
     k_knn_rerank<X><<<dim3((unsigned)n), 256, 0, s>>>(Xm, D, k, cand, ccnt, cthr, nrm, nmax,
                                                       kExact ? 1 : 0, idx, d2, flag);
