@@ -97,6 +97,30 @@ __device__ void compact_row(int q, int64_t grow, uint32_t* cnt, uint32_t* thr, u
     __syncthreads();
 }
 
+// After a tile: compact the rows whose lists could overflow during the next
+// one.  Threads 0..kQB-1 test their row and the waves' ballots go through LDS,
+// so the block walks only the rows that need it (usually none).
+__device__ void compact_full_rows(int64_t q0, uint32_t* cnt, uint32_t* thr, uint64_t* cand,
+                                  uint64_t* sbuf, uint64_t* need, int kp) {
+    static_assert(kQB == 2 * 64, "two waves test the rows");
+    const int t = threadIdx.x;
+    if (t < kQB) {
+        const uint64_t b = ballot64(cnt[t] > (uint32_t)(kCap - kCB));
+        if (lane_id() == 0) need[t >> 6] = b;
+    }
+    __syncthreads();
+    // need[] is next written after the next tile's barriers
+    const uint64_t m0 = need[0], m1 = need[1];
+    for (int h = 0; h < 2; h++) {
+        uint64_t m = h ? m1 : m0;
+        while (m) {
+            const int q = 64 * h + __ffsll((long long)m) - 1;
+            m &= m - 1;
+            compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
+        }
+    }
+}
+
 // Candidate generation.  One block (four waves) per kQB query rows sweeps all
 // candidate columns in tiles of kCB; the 128 x 128 distance tile comes from
 // FP32 MFMA (v_mfma_f32_32x32x2f32), each wave owning a 64 x 64 quarter as
@@ -119,6 +143,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
     __shared__ float nq[kQB];
     __shared__ float nc[kCB];
     __shared__ uint64_t sbuf[512];
+    __shared__ uint64_t need[2];
 
     const int t = threadIdx.x, w = t >> 6, lane = lane_id();
     const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
@@ -233,10 +258,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
                 }
             }
         __syncthreads();
-        // compact the rows that could overflow during the next tile
-        for (int q = 0; q < kQB; q++) {
-            if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
-        }
+        compact_full_rows(q0, cnt, thr, cand, sbuf, need, kp);
     }
     for (int q = 0; q < kQB; q++) {
         if (q0 + q < n) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
@@ -283,6 +305,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates_i8(const uint8_t* __rest
     __shared__ int32_t nq[kQB];
     __shared__ int32_t nc[kCB];
     __shared__ uint64_t sbuf[512];
+    __shared__ uint64_t need[2];
 
     const int t = threadIdx.x, w = t >> 6, lane = lane_id();
     const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
@@ -385,9 +408,7 @@ __global__ __launch_bounds__(256) void k_knn_candidates_i8(const uint8_t* __rest
                 }
             }
         __syncthreads();
-        for (int q = 0; q < kQB; q++) {
-            if (cnt[q] > (uint32_t)(kCap - kCB)) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
-        }
+        compact_full_rows(q0, cnt, thr, cand, sbuf, need, kp);
     }
     for (int q = 0; q < kQB; q++) {
         if (q0 + q < n) compact_row(q, q0 + q, cnt, thr, cand, sbuf, kp);
