@@ -174,21 +174,25 @@ __global__ __launch_bounds__(256) void k_knn_candidates(const X* __restrict__ Xm
         const X* pc = Xm + (okc ? rc : 0) * (int64_t)D + kH * (t & 1);
         auto fetch = [&](int k0) {
             if constexpr (VEC) {
-                // FP32 rows, D a multiple of kKC, 16-byte aligned: whole chunks
-                // in 16-byte loads
+                // FP32 rows, D a multiple of 4, 16-byte aligned: 16-byte loads;
+                // a group of four past the row's end reads the row's first four
+                // (D >= 4), a row past n reads row 0, and both are zeroed
+                const int lim = D - k0 - kH * (t & 1);          // elements left in the row
 #pragma unroll
                 for (int u = 0; u < kH; u += 4) {
-                    // rows past n read row 0 (pq, pc are clamped) and are zeroed
-                    const float4 a = *reinterpret_cast<const float4*>(pq + k0 + u);
-                    const float4 c = *reinterpret_cast<const float4*>(pc + k0 + u);
-                    g[u] = okq ? a.x : 0.0f;
-                    g[u + 1] = okq ? a.y : 0.0f;
-                    g[u + 2] = okq ? a.z : 0.0f;
-                    g[u + 3] = okq ? a.w : 0.0f;
-                    g[kH + u] = okc ? c.x : 0.0f;
-                    g[kH + u + 1] = okc ? c.y : 0.0f;
-                    g[kH + u + 2] = okc ? c.z : 0.0f;
-                    g[kH + u + 3] = okc ? c.w : 0.0f;
+                    const bool in = u < lim;                    // lim is a multiple of 4
+                    const int off = in ? k0 + u : -kH * (t & 1);   // else the row's start
+                    const float4 a = *reinterpret_cast<const float4*>(pq + off);
+                    const float4 c = *reinterpret_cast<const float4*>(pc + off);
+                    const bool iq = okq && in, ic = okc && in;
+                    g[u] = iq ? a.x : 0.0f;
+                    g[u + 1] = iq ? a.y : 0.0f;
+                    g[u + 2] = iq ? a.z : 0.0f;
+                    g[u + 3] = iq ? a.w : 0.0f;
+                    g[kH + u] = ic ? c.x : 0.0f;
+                    g[kH + u + 1] = ic ? c.y : 0.0f;
+                    g[kH + u + 2] = ic ? c.z : 0.0f;
+                    g[kH + u + 3] = ic ? c.w : 0.0f;
                 }
             } else {
                 const int lim = D - k0 - kH * (t & 1);          // elements left in the row
@@ -801,7 +805,7 @@ hipError_t knn_typed(const X* Xm, int64_t n, int32_t D, int32_t k, int32_t* idx,
     } else {
         bool vec = false;
         if constexpr (std::is_same<X, float>::value)
-            vec = D % kKC == 0 && ((uintptr_t)Xm & 15) == 0;
+            vec = D % 4 == 0 && ((uintptr_t)Xm & 15) == 0;
         if (vec)
             k_knn_candidates<float, true><<<dim3((unsigned)ceil_div(n, kQB)), 256, 0, s>>>(
                 (const float*)Xm, n, D, nrm, kp, cand, ccnt, cthr);

@@ -243,13 +243,17 @@ def test_two_points(psne, prec):
 # --------------------------------------------------------------------------
 # setup: kNN, perplexity, P
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dtype", ["f64", "f32", "u8"])
-def test_knn_parity(psne, dtype):
+@pytest.mark.parametrize("dtype,D", [("f64", 50), ("f32", 50), ("u8", 100),
+                                     # FP32 rows with D a multiple of 4 take 16-byte loads:
+                                     # chunks of 32 dimensions whole, cut, or shorter
+                                     ("f32", 4), ("f32", 36), ("f32", 100), ("f32", 128)])
+def test_knn_parity(psne, dtype, D):
     if dtype == "u8":
-        X, _ = datagen.uint8_mixture(n=3001, D=100)
+        X, _ = datagen.uint8_mixture(n=3001, D=D)
         k = 40
     else:
-        X, _ = datagen.small_mixture(n=2000, dtype=np.float64 if dtype == "f64" else np.float32)
+        X, _ = datagen.small_mixture(n=2000 if D != 4 else 1500, D=D,
+                                     dtype=np.float64 if dtype == "f64" else np.float32)
         k = 90
     idx, d2 = psne.knn(torch.as_tensor(X).cuda(), k)
     oi, od = oracle.knn(X.astype(np.float64), k)
