@@ -115,8 +115,10 @@ typedef struct {
                                  more slowly the later it is made. */
     int32_t opening_fp64;     /* PSNE_FP32 path only.  0: the Barnes-Hut opening test of
                                  Eq. 11 and the distances run in FP32, operands rounded to
-                                 FP32 and each operation rounded in the order
-                                 (w*w)*(b1+b2) < th2*((b1*dx)*dx + (b2*dy)*dy), no fused
+                                 FP32, each axis scaled by r_d = sqrt(b_d) rounded to FP32,
+                                 and each operation rounded in the order
+                                 (w*w)*(b1+b2) < th2*(dx*dx + dy*dy) with
+                                 dx = z1*r1 - c1*r1, dy = z2*r2 - c2*r2, no fused
                                  multiply-add [0].  1: the test and the distances in FP64
                                  (the FP64 path always does this). */
     int32_t tree;             /* PSNE_TREE_PIXEL | PSNE_TREE_DATA [PIXEL] */

@@ -749,8 +749,10 @@ int orc_sorted_order(const double* z, int64_t n, int32_t r, uint32_t* key_sorted
 /*   a leaf is always used; an inner cell is used iff                    */
 /*   diag2 < theta^2 * d2  (diagonal / distance < theta), else recurse.  */
 /* predicate 0 evaluates that test in FP64; predicate 1 in FP32: z_i, c, */
-/* w, beta and theta^2 rounded to FP32, then                             */
-/*   (w*w)*(b1+b2) < th2*((b1*dx)*dx + (b2*dy)*dy),  dx = z_i - c,       */
+/* w, beta and theta^2 rounded to FP32, each axis scaled by             */
+/* r_d = sqrt(beta_d) rounded to FP32, then                              */
+/*   (w*w)*(b1+b2) < th2*(dx*dx + dy*dy),                                */
+/*   dx = z_i1*r_1 - c_1*r_1,  dy = z_i2*r_2 - c_2*r_2,                  */
 /* each operation rounded to FP32 in that order (no fused multiply-add;  */
 /* the library's FP32 path takes the same decision).  The forces of a    */
 /* used cell are FP64 either way.                                        */
@@ -775,6 +777,7 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
     const double b1 = beta[0], b2 = beta[1], th2 = theta * theta;
     /* single-precision operands of the FP32 opening test */
     const float b1f = (float)b1, b2f = (float)b2, th2f = (float)th2, bsf = b1f + b2f;
+    const float r1f = (float)sqrt(b1), r2f = (float)sqrt(b2);
     if (!rows) nrows = t->n;
     int64_t q;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -823,10 +826,12 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
                 use = diag2 < th2 * d2;
             } else {
                 /* the same test in single precision: operands rounded to
-                 * FP32, every operation rounded to FP32 in this order */
-                float dxf = (float)zx - (float)cx, dyf = (float)zy - (float)cy;
+                 * FP32, the axes scaled by sqrt(beta) in FP32, every
+                 * operation rounded to FP32 in this order */
+                float dxf = (float)zx * r1f - (float)cx * r1f;
+                float dyf = (float)zy * r2f - (float)cy * r2f;
                 float wf = (float)w;
-                float d2f = (b1f * dxf) * dxf + (b2f * dyf) * dyf;
+                float d2f = dxf * dxf + dyf * dyf;
                 float diag2f = (wf * wf) * bsf;
                 use = diag2f < th2f * d2f;
             }

@@ -51,13 +51,19 @@ struct alignas(32) Node {
 };
 
 // The traversal's copy of a cell for the FP32 path (16 bytes): the
-// representative point and the point count rounded to FP32 (the mass the FP32
-// force terms use), and child as in Node.
+// representative point rounded to FP32 and multiplied by the axis scale of
+// cell_scale (so that the beta-weighted squared distance is a plain sum of
+// squares), the point count rounded to FP32 (the mass the FP32 force terms
+// use), and child as in Node.
 struct alignas(16) CellF {
     float cx, cy;
     float mass;
     uint32_t child;
 };
+
+// The FP32 traversal's scale of axis d: sqrt(beta_d) rounded to FP32, with
+// beta_d = s_d^2 the Eq. (12) metric weight of the current frame.
+__device__ __forceinline__ float cell_scale(double s) { return (float)sqrt(s * s); }
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };

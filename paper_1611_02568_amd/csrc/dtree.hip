@@ -281,14 +281,15 @@ __global__ __launch_bounds__(kBlock) void k_dtree_nodes(
 
 __device__ __forceinline__ void put_cell(Node* __restrict__ nodes, CellF* __restrict__ c32,
                                          double2* __restrict__ nsum, uint32_t g, double sx,
-                                         double sy, uint32_t count, uint32_t child) {
+                                         double sy, uint32_t count, uint32_t child, float rs0,
+                                         float rs1) {
     const double cx = sx / (double)count, cy = sy / (double)count;
     nodes[g].cx = cx;
     nodes[g].cy = cy;
     nodes[g].count = count;
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
-    if (c32) c32[g] = CellF{(float)cx, (float)cy, (float)count, child};
+    if (c32) c32[g] = CellF{(float)cx * rs0, (float)cy * rs1, (float)count, child};
 }
 
 // Leaves: a run head sums its run's positions in order (FP64).
@@ -298,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_dtree_leaves(const uint64_t* __restr
                                                          const uint32_t* __restrict__ leaf_of,
                                                          Node* __restrict__ nodes,
                                                          CellF* __restrict__ c32,
-                                                         double2* __restrict__ nsum) {
+                                                         double2* __restrict__ nsum,
+                                                         const DevScalars* __restrict__ sc) {
     using V = v2_t<T>;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n || first_new_level64(keys, s) > kDLevels) return;
@@ -311,7 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_dtree_leaves(const uint64_t* __restr
         sy += (double)p.y;
         q++;
     } while (q < n && keys[q] == k);
-    put_cell(nodes, c32, nsum, leaf_of[s], sx, sy, (uint32_t)(q - s), 0u);
+    put_cell(nodes, c32, nsum, leaf_of[s], sx, sy, (uint32_t)(q - s), 0u, cell_scale(sc->s[0]),
+             cell_scale(sc->s[1]));
 }
 
 // One cell of level l: its children are [cursor[g], cursor[g + 1]) (the end
@@ -320,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_dtree_leaves(const uint64_t* __restr
 __device__ __forceinline__ void dtree_inner(int l, const DevScalars* __restrict__ sc,
                                             const uint32_t* __restrict__ cursor,
                                             Node* __restrict__ nodes, CellF* __restrict__ c32,
-                                            double2* __restrict__ nsum, uint32_t t, uint32_t m) {
+                                            double2* __restrict__ nsum, uint32_t t, uint32_t m,
+                                            float rs0, float rs1) {
     const uint32_t g = sc->level_base[l] + t;
     const uint32_t fc = cursor[g];
     const uint32_t lc = (t + 1 < m) ? cursor[g + 1] : sc->level_base[l + 1] + sc->level_size[l + 1];
@@ -333,7 +337,7 @@ __device__ __forceinline__ void dtree_inner(int l, const DevScalars* __restrict_
         ay += v.y;
         c += nodes[q].count;
     }
-    put_cell(nodes, c32, nsum, g, ax, ay, c, fc | ((lc - fc - 1) << 30));
+    put_cell(nodes, c32, nsum, g, ax, ay, c, fc | ((lc - fc - 1) << 30), rs0, rs1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dtree_level(int l, const DevScalars* __restrict__ sc,
@@ -344,7 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_dtree_level(int l, const DevScalars*
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint32_t m = sc->level_size[l];
     if (t >= m) return;
-    dtree_inner(l, sc, cursor, nodes, c32, nsum, (uint32_t)t, m);
+    dtree_inner(l, sc, cursor, nodes, c32, nsum, (uint32_t)t, m, cell_scale(sc->s[0]),
+                cell_scale(sc->s[1]));
 }
 
 // levels top..0 in one block (a level l holds at most 4^l cells)
@@ -354,10 +359,11 @@ __global__ __launch_bounds__(kTopThreads) void k_dtree_top(int top,
                                                            Node* __restrict__ nodes,
                                                            CellF* __restrict__ c32,
                                                            double2* __restrict__ nsum) {
+    const float rs0 = cell_scale(sc->s[0]), rs1 = cell_scale(sc->s[1]);
     for (int l = top; l >= 0; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t t = threadIdx.x; t < m; t += kTopThreads)
-            dtree_inner(l, sc, cursor, nodes, c32, nsum, t, m);
+            dtree_inner(l, sc, cursor, nodes, c32, nsum, t, m, rs0, rs1);
         __syncthreads();
     }
 }
@@ -425,13 +431,13 @@ hipError_t run_tree_dtree(pixelsne_ctx* c) {
             keys, perm, (const double*)c->z, c->n, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc,
             tb.nodes, tb.cursor, tb.leaf_of, (double*)tb.zs);
         k_dtree_leaves<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, (const double*)tb.zs, c->n, tb.leaf_of, tb.nodes, tb.cells32, tb.nsum);
+            keys, (const double*)tb.zs, c->n, tb.leaf_of, tb.nodes, tb.cells32, tb.nsum, c->sc);
     } else {
         k_dtree_nodes<float><<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
             keys, perm, (const float*)c->z, c->n, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc,
             tb.nodes, tb.cursor, tb.leaf_of, (float*)tb.zs);
         k_dtree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, (const float*)tb.zs, c->n, tb.leaf_of, tb.nodes, tb.cells32, tb.nsum);
+            keys, (const float*)tb.zs, c->n, tb.leaf_of, tb.nodes, tb.cells32, tb.nsum, c->sc);
     }
     for (int l = kDLevels - 1; l > kTopLevel; l--) {
         const int64_t cap = l < 31 ? (int64_t)1 << (2 * l) : c->n;

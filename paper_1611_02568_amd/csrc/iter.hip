@@ -317,7 +317,7 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __re
                                            double2* __restrict__ nsum,
                                            uint32_t g, int level, int L, double sx, double sy,
                                            uint32_t count, uint32_t child, uint32_t key0,
-                                           int com_mode) {
+                                           int com_mode, float rs0, float rs1) {
     double cx, cy;
     if (com_mode == PSNE_COM_CELL_CENTER) {
         const int sh = L - level;
@@ -334,7 +334,7 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __re
     nodes[g].count = count;
     nodes[g].child = child;
     nsum[g] = double2{sx, sy};
-    if (c32) c32[g] = CellF{(float)cx, (float)cy, (float)count, child};
+    if (c32) c32[g] = CellF{(float)cx * rs0, (float)cy * rs1, (float)count, child};
 }
 
 // Leaf sums, part 2 (one thread per leaf): a leaf that spans several waves
@@ -400,7 +400,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
         sx = (wlast[wa].x + sx) + wfirst[wb].x;
         sy = (wlast[wa].y + sy) + wfirst[wb].y;
     }
-    write_node(nodes, c32, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode);
+    write_node(nodes, c32, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode,
+               cell_scale(sc->s[0]), cell_scale(sc->s[1]));
 }
 
 // One inner cell: count and sums of its children (consecutive in the next
@@ -409,7 +410,8 @@ __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, in
                                            int com_mode, const DevScalars* __restrict__ sc,
                                            const uint32_t* __restrict__ first_child,
                                            Node* __restrict__ nodes, CellF* __restrict__ c32,
-                                           double2* __restrict__ nsum, uint32_t t, uint32_t m) {
+                                           double2* __restrict__ nsum, uint32_t t, uint32_t m,
+                                           float rs0, float rs1) {
     const uint32_t g = sc->level_base[l] + t;
     const uint32_t fc = first_child[g];
     const uint32_t lc = (t + 1 < m) ? first_child[g + 1] : sc->level_base[l + 1] + sc->level_size[l + 1];
@@ -422,7 +424,7 @@ __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, in
         c += nodes[q].count;
     }
     write_node(nodes, c32, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30),
-               keys[nodes[g].start], com_mode);
+               keys[nodes[g].start], com_mode, rs0, rs1);
 }
 
 // Up to kGroupLevels consecutive levels of inner cells in one launch.  Block
@@ -445,6 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_group(const uint32_t* __restric
                                                        double2* __restrict__ nsum) {
     __shared__ uint32_t lo[kGroupLevels], hi[kGroupLevels];
     const int t = threadIdx.x;
+    const float rs0 = cell_scale(sc->s[0]), rs1 = cell_scale(sc->s[1]);
     const uint32_t mtop = sc->level_size[ltop];
     const uint32_t a0 = blockIdx.x * K;
     if (a0 >= mtop) return;
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_group(const uint32_t* __restric
     for (int l = lbot; l >= ltop; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t x = lo[l - ltop] + t; x < hi[l - ltop]; x += kBlock)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, x, m);
+            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, x, m, rs0, rs1);
         __syncthreads();
     }
 }
@@ -484,10 +487,11 @@ __global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __rest
                                                           Node* __restrict__ nodes,
                                                           CellF* __restrict__ c32,
                                                           double2* __restrict__ nsum) {
+    const float rs0 = cell_scale(sc->s[0]), rs1 = cell_scale(sc->s[1]);
     for (int l = top; l >= 0; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t t = threadIdx.x; t < m; t += kTopThreads)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, t, m);
+            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, t, m, rs0, rs1);
         __syncthreads();
     }
 }
@@ -541,11 +545,12 @@ __device__ __forceinline__ double add_nc(double a, double b) {
     return a + b;
 }
 
-// the same distance and product in FP32, each operation rounded separately
-__device__ __forceinline__ float dist2f(float b1, float b2, float dx, float dy) {
+// the FP32 distance on axis-scaled coordinates (cell_scale): dx*dx + dy*dy,
+// each operation rounded separately
+__device__ __forceinline__ float dist2s(float dx, float dy) {
 #pragma clang fp contract(off)
-    const float a = (b1 * dx) * dx;
-    const float b = (b2 * dy) * dy;
+    const float a = dx * dx;
+    const float b = dy * dy;
     return a + b;
 }
 __device__ __forceinline__ float mulf_nc(float a, float b) {
@@ -605,8 +610,10 @@ struct alignas(16) CellF4 { CellF c[4]; };
 struct alignas(32) Node4 { Node n[4]; };
 
 // F32T (FP32 path only): the opening test and the distances in FP32 on the
-// cells' FP32 copies (cells32), operands and operations rounded as the FP64
-// test's expression written in single precision; otherwise in FP64 on nodes.
+// cells' FP32 copies (cells32), whose coordinates are scaled by cell_scale so
+// that the beta-weighted squared distance is dx*dx + dy*dy of the scaled
+// differences, every operation rounded separately; the force sums run on the
+// scaled axes and are scaled back at the end.  Otherwise in FP64 on nodes.
 template <typename T, bool COUNT, bool F32T, bool DEEP>
 __global__ __launch_bounds__(kBlock) void k_traverse(
     const Node* __restrict__ nodes, const CellF* __restrict__ cells32,
@@ -627,10 +634,12 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     const uint32_t own = valid ? leaf_of[s] : 0xFFFFFFFFu;
     const double s0 = sc->s[0], s1 = sc->s[1];
     const double b1 = mul_nc(s0, s0), b2 = mul_nc(s1, s1), bsum = add_nc(b1, b2);
-    // single-precision operands of the FP32 test: beta and theta^2 rounded
+    // single-precision operands of the FP32 test: beta and theta^2 rounded,
+    // the point on the cells' scaled axes
     const float b1f = (float)b1, b2f = (float)b2, th2f = (float)th2;
     const float bsumf = b1f + b2f;
-    const float zxf = (float)zp.x, zyf = (float)zp.y;
+    const float rs0 = cell_scale(s0), rs1 = cell_scale(s1);
+    const float xs = (float)zp.x * rs0, ys = (float)zp.y * rs1;
 
     double zacc = 0.0;
     T rx = T(0), ry = T(0);
@@ -672,9 +681,9 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                 float dx, dy, qq, mq;
                 bool use;
                 if (nd.child != 0u) {
-                    dx = zxf - nd.cx;
-                    dy = zyf - nd.cy;
-                    const float d2 = dist2f(b1f, b2f, dx, dy);
+                    dx = xs - nd.cx;
+                    dy = ys - nd.cy;
+                    const float d2 = dist2s(dx, dy);
                     const uint64_t near = ballot64(!(diag2f < mulf_nc(th2f, d2)));
                     om = near & mask;
                     use = __builtin_amdgcn_inverse_ballot_w64(mask & ~near);
@@ -696,14 +705,14 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
                         if (others > 0u && com_mode != PSNE_COM_CELL_CENTER) {
                             const double2 sm = nsum[c];
                             const double inv = 1.0 / (double)others;
-                            cx = (float)((sm.x - zx) * inv);
-                            cy = (float)((sm.y - zy) * inv);
+                            cx = (float)((sm.x - zx) * inv) * rs0;
+                            cy = (float)((sm.y - zy) * inv) * rs1;
                         }
                         use = act && others > 0u;
                     }
-                    dx = zxf - cx;
-                    dy = zyf - cy;
-                    qq = __builtin_amdgcn_rcpf(1.0f + dist2f(b1f, b2f, dx, dy));
+                    dx = xs - cx;
+                    dy = ys - cy;
+                    qq = __builtin_amdgcn_rcpf(1.0f + dist2s(dx, dy));
                     mq = qq * m;
                     if (COUNT) {
                         nuse += use ? 1u : 0u;
@@ -792,7 +801,12 @@ __global__ __launch_bounds__(kBlock) void k_traverse(
     }
     if (valid) {
         const uint32_t i = perm[s];
-        reinterpret_cast<V*>(R)[i] = V{rx, ry};
+        if constexpr (F32T) {
+            // the FP32 sums ran on the scaled axes: back to pixel units
+            reinterpret_cast<V*>(R)[i] = V{rx / rs0, ry / rs1};
+        } else {
+            reinterpret_cast<V*>(R)[i] = V{rx, ry};
+        }
         if (Zi_out) Zi_out[orig[i]] = zacc;
         if (visits_out) visits_out[orig[i]] = nvis;
         if (used_out) used_out[orig[i]] = nuse;

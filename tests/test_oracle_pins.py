@@ -183,12 +183,14 @@ def test_tree_against_bruteforce(orc, gen):
 # Barnes-Hut traversal against a pure-Python brute force (tiny inputs)
 # --------------------------------------------------------------------------
 def _opens_fp32(zi, c, w, b1, b2, theta):
-    """The opening test in single precision: every operand rounded to FP32
-    and every product and sum rounded to FP32 in the written order."""
+    """The opening test in single precision: every operand rounded to FP32,
+    each axis scaled by sqrt(beta) rounded to FP32, and every product and sum
+    rounded to FP32 in the written order."""
     f = np.float32
-    dx = f(zi[0]) - f(c[0])
-    dy = f(zi[1]) - f(c[1])
-    d2 = (f(b1) * dx) * dx + (f(b2) * dy) * dy
+    r1, r2 = f(math.sqrt(b1)), f(math.sqrt(b2))
+    dx = f(zi[0]) * r1 - f(c[0]) * r1
+    dy = f(zi[1]) * r2 - f(c[1]) * r2
+    d2 = dx * dx + dy * dy
     return not ((f(w) * f(w)) * (f(b1) + f(b2)) < f(theta * theta) * d2)
 
 
