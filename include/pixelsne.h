@@ -137,7 +137,17 @@ typedef struct {
                                  second stream has not started, 0..16 [3]; 0: no helper.
                                  At least one of the two is >= 1.  Results are identical
                                  for every setting. */
+    int32_t attract_fork;     /* where the row sums fork onto the second stream:
+                                 PSNE_FORK_SNAP after the snap pass (beside the sort, the
+                                 cells and the walk), PSNE_FORK_CELLS after the cells (beside
+                                 the walk only), PSNE_FORK_AUTO after the cells during the
+                                 early exaggeration (iterations t < exag_iters, when the
+                                 walk of the compressed layout is the longer stream) and
+                                 after the snap pass from then on [AUTO].  Results are
+                                 identical for every setting. */
 } pixelsne_params;
+
+enum { PSNE_FORK_SNAP = 0, PSNE_FORK_CELLS = 1, PSNE_FORK_AUTO = 2 };
 
 /* Fill *p with the defaults shown in brackets above. */
 void pixelsne_default_params(pixelsne_params* p);

@@ -74,6 +74,9 @@ psne_status check_params(const pixelsne_params* p) {
         return invalid("attract_help_blocks_per_cu must be in [0, 16]");
     if (p->attract_blocks_per_cu == 0 && p->attract_help_blocks_per_cu == 0)
         return invalid("attract_blocks_per_cu and attract_help_blocks_per_cu are both 0");
+    if (p->attract_fork != PSNE_FORK_SNAP && p->attract_fork != PSNE_FORK_CELLS &&
+        p->attract_fork != PSNE_FORK_AUTO)
+        return invalid("unknown attract_fork");
     if (p->tree == PSNE_TREE_DATA && p->com_mode != PSNE_COM_MASS) {
         set_error("the data-driven tree takes centres of mass only (PSNE_COM_MASS)");
         return PSNE_E_UNSUPPORTED;
@@ -199,8 +202,9 @@ void free_ctx(pixelsne_ctx* c) {
     // the second stream's work is joined into the context's stream, except
     // after an error between the fork and the join
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (hipGraphExec_t& g : c->gexec)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& gp : c->gexec)
+        for (hipGraphExec_t& g : gp)
+            if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -228,11 +232,19 @@ hipError_t capture_iteration(pixelsne_ctx* c, hipGraphExec_t* out) {
     return e;
 }
 
+// The fork point of the next iteration (PSNE_FORK_AUTO: after the cells
+// during the early exaggeration).
+void set_fork(pixelsne_ctx* c) {
+    const int32_t f = c->prm.attract_fork;
+    c->fork_late = f == PSNE_FORK_CELLS || (f == PSNE_FORK_AUTO && c->t_host < c->prm.exag_iters);
+}
+
 hipError_t step_one(pixelsne_ctx* c) {
     hipError_t e = hipSuccess;
     bool done = false;
+    set_fork(c);
     if (c->prm.graphs && !c->graph_failed) {
-        hipGraphExec_t& ge = c->gexec[c->parity];
+        hipGraphExec_t& ge = c->gexec[c->parity][c->fork_late ? 1 : 0];
         if (!ge && capture_iteration(c, &ge) != hipSuccess) {
             // capture unavailable: launch the kernels directly from now on
             (void)hipGetLastError();
@@ -246,6 +258,7 @@ hipError_t step_one(pixelsne_ctx* c) {
         }
     }
     if (!done) e = run_iteration_passes(c);
+    if (e == hipSuccess) c->t_host++;
     if (e == hipSuccess) e = run_scheduled_reorder(c);
     return e;
 }
@@ -322,6 +335,7 @@ void pixelsne_default_params(pixelsne_params* p) {
     p->knn_explore = 1;
     p->attract_blocks_per_cu = 2;
     p->attract_help_blocks_per_cu = 3;
+    p->attract_fork = PSNE_FORK_AUTO;
 }
 
 pixelsne_ctx* pixelsne_init_ex(const void* X, int64_t n, int32_t D, double perplexity,
@@ -475,8 +489,11 @@ psne_status pixelsne_step_profiled(pixelsne_ctx* c, int32_t n_iter, pixelsne_pas
     size_t made = 0;
     for (; made < ev.size() && e == hipSuccess; made++) e = hipEventCreate(&ev[made]);
     if (e != hipSuccess) made--;
-    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
+    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++) {
+        set_fork(c);
         e = run_iteration_timed(c, &ev[(size_t)kEv * it]);
+        if (e == hipSuccess) c->t_host++;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     double* acc[8] = {&out->snap_ms, &out->sort_ms, &out->tree_ms, &out->traverse_ms,
                       &out->zsum_ms, &out->attract_ms, &out->finalize_ms, &out->reorder_ms};
@@ -556,6 +573,7 @@ psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, co
     h.uscale[0] = h.uscale[1] = 1.0;
     h.t = iteration;
     h.nonfinite = 0;
+    c->t_host = iteration;
     e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = run_set_state(c, z, u, g);
     // the renumbering schedule as it stands after `iteration` iterations (the

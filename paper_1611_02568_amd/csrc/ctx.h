@@ -108,8 +108,11 @@ struct pixelsne_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t side_blocks = 0;
     int64_t help_blocks = 0;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // [parity][fork after the cells]
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int32_t parity = 0;
+    int32_t t_host = 0;                      // iterations done, as the host counts them
+    bool fork_late = false;                  // this iteration forks after the cells
     bool graph_failed = false;
 
     std::vector<void*> allocs;

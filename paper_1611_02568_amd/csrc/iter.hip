@@ -1653,10 +1653,11 @@ hipError_t run_finalize(pixelsne_ctx* c, int advance) {
     return hipGetLastError();
 }
 
-// One iteration.  After the snap pass the attraction's row sums are forked
-// onto the second stream (they need only the snapped positions and P) and
-// run while this stream sorts, builds the tree, walks it and reduces Z; the
-// update joins them.  EV, when given, receives the pass boundaries: [0..5]
+// One iteration.  The attraction's row sums need only the snapped positions
+// and P: they are forked onto the second stream after the snap pass (and run
+// while this stream sorts, builds the tree, walks it and reduces Z) or, when
+// c->fork_late, after the tree (beside the walk only); the update joins them.
+// EV, when given, receives the pass boundaries: [0..5]
 // before snap, sort, tree, traverse, Z and after Z on this stream, [6] after
 // the join, [7] after update and scaling, [8] after a scheduled renumbering,
 // [9] and [10] around the row sums on the second stream.
@@ -1665,19 +1666,24 @@ static hipError_t iteration(pixelsne_ctx* c, hipEvent_t* ev) {
     auto mark = [&](int k, hipStream_t s) {
         return ev ? hipEventRecord(ev[k], s) : hipSuccess;
     };
+    auto fork = [&]() {
+        hipError_t f;
+        if ((f = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return f;
+        if ((f = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return f;
+        if ((f = mark(9, c->side)) != hipSuccess) return f;
+        if ((f = run_attract_sums(c, false)) != hipSuccess) return f;
+        if ((f = mark(10, c->side)) != hipSuccess) return f;
+        return hipEventRecord(c->ev_join, c->side);
+    };
     if ((e = mark(0, c->stream)) != hipSuccess) return e;
     if ((e = run_snap(c)) != hipSuccess) return e;
     if ((e = mark(1, c->stream)) != hipSuccess) return e;
-    if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
-    if ((e = mark(9, c->side)) != hipSuccess) return e;
-    if ((e = run_attract_sums(c, false)) != hipSuccess) return e;
-    if ((e = mark(10, c->side)) != hipSuccess) return e;
-    if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
+    if (!c->fork_late && (e = fork()) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
     if ((e = mark(2, c->stream)) != hipSuccess) return e;
     if ((e = run_tree(c)) != hipSuccess) return e;
     if ((e = mark(3, c->stream)) != hipSuccess) return e;
+    if (c->fork_late && (e = fork()) != hipSuccess) return e;
     if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
     if ((e = mark(4, c->stream)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;

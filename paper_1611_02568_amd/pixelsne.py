@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpixelsne.so")
 PSNE_OK, PSNE_E_INVAL, PSNE_E_NOMEM, PSNE_E_DEVICE = 0, -1, -2, -3
 PSNE_E_NUMERIC, PSNE_E_STATE, PSNE_E_UNSUPPORTED = -4, -5, -6
 FP32, FP64 = 0, 1
+FORK_SNAP, FORK_CELLS, FORK_AUTO = 0, 1, 2
 COM_MASS, COM_CELL_CENTER = 0, 1
 X_F32, X_F64, X_U8 = 0, 1, 2
 TREE_PIXEL, TREE_DATA = 0, 1
@@ -52,6 +53,7 @@ class Params(C.Structure):
         ("knn_explore", C.c_int32),
         ("attract_blocks_per_cu", C.c_int32),
         ("attract_help_blocks_per_cu", C.c_int32),
+        ("attract_fork", C.c_int32),
     ]
 
 

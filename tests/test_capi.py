@@ -73,7 +73,8 @@ def test_init_validation(psne, args, frag):
                                      ({"attract_help_blocks_per_cu": -1},
                                       "attract_help_blocks_per_cu"),
                                      ({"attract_blocks_per_cu": 0,
-                                       "attract_help_blocks_per_cu": 0}, "both 0")])
+                                       "attract_help_blocks_per_cu": 0}, "both 0"),
+                                     ({"attract_fork": 3}, "attract_fork")])
 def test_params_validation(psne, kw, frag):
     X = np.zeros((10, 4), np.float32)
     assert not _init(psne, X.ctypes.data, 10, 4, 3.0, 512, 512, **kw)

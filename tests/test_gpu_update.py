@@ -125,29 +125,32 @@ def test_update_from_zero_velocity(psne, near_switch, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_attraction_work_split_changes_nothing(psne, near_switch, prec):
     """The attraction's row chunks come from one queue shared by the second
-    stream's blocks and the helper that joins after Z; who takes a chunk must
-    not change a bit.  (0, h) puts every chunk on the helper, (b, 0) every
-    chunk on the second stream; the helper-only run is also held to the
-    oracle's bar."""
+    stream's blocks and the helper that joins after Z; who takes a chunk, and
+    where the second stream forks (after the snap pass, after the cells, or
+    switching at the end of the early exaggeration, which the 5 steps from
+    t = 247 cross), must not change a bit.  (0, h) puts every chunk on the
+    helper, (b, 0) every chunk on the second stream; the helper-only run is
+    also held to the oracle's bar."""
     P, st = near_switch
     dt = np.float64 if prec == 1 else np.float32
     o = _rounded_state(st, dt)
     got = {}
-    for side, help_ in [(2, 3), (0, 1), (0, 16), (2, 0), (1, 16), (16, 16)]:
+    for side, help_, fork in [(2, 3, 2), (0, 1, 2), (0, 16, 0), (2, 0, 1), (1, 16, 2),
+                              (16, 16, 0), (2, 3, 0), (2, 3, 1)]:
         ctx = psne.Context.from_P(*P, screen=R, precision=prec, reorder_every=2,
                                   reorder_growth=1.0, attract_blocks_per_cu=side,
-                                  attract_help_blocks_per_cu=help_,
+                                  attract_help_blocks_per_cu=help_, attract_fork=fork,
                                   Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=5)))
         ctx.set_state(o.z.astype(dt), o.s, u=o.u.astype(dt), g=o.g.astype(dt), iteration=o.t)
         ctx.step(5)
         s = ctx.get_state()
-        got[(side, help_)] = [s[k].cpu().numpy() for k in ("z", "u", "g")]
-    ref = got[(2, 3)]
+        got[(side, help_, fork)] = [s[k].cpu().numpy() for k in ("z", "u", "g")]
+    ref = got[(2, 3, 2)]
     for key, v in got.items():
         for a, b in zip(ref, v):
             assert np.array_equal(a, b), key
     oracle.iterate(o, oracle.params(R, predicate=1 - prec), P, 5)
-    z = got[(0, 1)][0].astype(np.float64)
+    z = got[(0, 1, 2)][0].astype(np.float64)
     if prec == 1:
         assert np.max(np.abs(z - o.z)) <= 1e-9 * R
     else:
