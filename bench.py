@@ -44,9 +44,10 @@ def log(msg):
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if there is none or a source the kernel's traffic depends on (its
-    own, and the layout it reads) changed since."""
+    """HBM bytes per iteration of `kernel`'s launches (the entry's note says
+    which launches are added) from the committed counter summary, or None if
+    there is none or a source the kernel's traffic depends on (its own, and
+    the layout it reads) changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             entry = json.load(f)["kernels"].get(kernel)

@@ -140,11 +140,11 @@ typedef struct {
     int32_t attract_fork;     /* where the row sums fork onto the second stream:
                                  PSNE_FORK_SNAP after the snap pass (beside the sort, the
                                  cells and the walk), PSNE_FORK_CELLS after the cells (beside
-                                 the walk only), PSNE_FORK_AUTO after the cells during the
-                                 early exaggeration (iterations t < exag_iters, when the
-                                 walk of the compressed layout is the longer stream) and
-                                 after the snap pass from then on [AUTO].  Results are
-                                 identical for every setting. */
+                                 the walk only), PSNE_FORK_AUTO chosen on the device from
+                                 measured iteration times: it starts after the cells, runs
+                                 one iteration in 16 at the other point and keeps the
+                                 faster of the last two [AUTO].  Results are identical for
+                                 every setting. */
 } pixelsne_params;
 
 enum { PSNE_FORK_SNAP = 0, PSNE_FORK_CELLS = 1, PSNE_FORK_AUTO = 2 };
@@ -209,7 +209,9 @@ typedef struct {
     double tree_ms;       /* cell numbering, counts and FP64 sums */
     double traverse_ms;   /* Barnes-Hut repulsion */
     double zsum_ms;       /* Z reduction */
-    double attract_ms;    /* attraction row sums (second stream, overlapping the above) */
+    double attract_ms;    /* attraction row sums on the second stream, overlapping the
+                             above (its launches after the snap pass and after the cells
+                             added; one of them leaves at once) */
     double finalize_ms;   /* gains/momentum step and screen scaling factors, after the
                              attraction has finished */
     double reorder_ms;    /* internal renumbering (on the params.reorder_every /

@@ -122,6 +122,7 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &c->A, v2)) != hipSuccess) return e;
     if ((e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&c->ev_cells, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) return e;
     int cus = 0;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device)) !=
@@ -202,12 +203,12 @@ void free_ctx(pixelsne_ctx* c) {
     // the second stream's work is joined into the context's stream, except
     // after an error between the fork and the join
     if (c->side) (void)hipStreamSynchronize(c->side);
-    for (auto& gp : c->gexec)
-        for (hipGraphExec_t& g : gp)
-            if (g) (void)hipGraphExecDestroy(g);
+    for (hipGraphExec_t& g : c->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_cells) (void)hipEventDestroy(c->ev_cells);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
@@ -232,19 +233,11 @@ hipError_t capture_iteration(pixelsne_ctx* c, hipGraphExec_t* out) {
     return e;
 }
 
-// The fork point of the next iteration (PSNE_FORK_AUTO: after the cells
-// during the early exaggeration).
-void set_fork(pixelsne_ctx* c) {
-    const int32_t f = c->prm.attract_fork;
-    c->fork_late = f == PSNE_FORK_CELLS || (f == PSNE_FORK_AUTO && c->t_host < c->prm.exag_iters);
-}
-
 hipError_t step_one(pixelsne_ctx* c) {
     hipError_t e = hipSuccess;
     bool done = false;
-    set_fork(c);
     if (c->prm.graphs && !c->graph_failed) {
-        hipGraphExec_t& ge = c->gexec[c->parity][c->fork_late ? 1 : 0];
+        hipGraphExec_t& ge = c->gexec[c->parity];
         if (!ge && capture_iteration(c, &ge) != hipSuccess) {
             // capture unavailable: launch the kernels directly from now on
             (void)hipGetLastError();
@@ -258,7 +251,6 @@ hipError_t step_one(pixelsne_ctx* c) {
         }
     }
     if (!done) e = run_iteration_passes(c);
-    if (e == hipSuccess) c->t_host++;
     if (e == hipSuccess) e = run_scheduled_reorder(c);
     return e;
 }
@@ -483,29 +475,29 @@ psne_status pixelsne_step_profiled(pixelsne_ctx* c, int32_t n_iter, pixelsne_pas
     if (c->poisoned) { set_error("context unusable after a device error"); return PSNE_E_STATE; }
     if (n_iter < 0) return invalid("n_iter must be >= 0");
     memset(out, 0, sizeof(*out));
-    constexpr int kEv = 11;     // pass boundaries of one iteration (see run_iteration_timed)
+    constexpr int kEv = 13;     // pass boundaries of one iteration (see run_iteration_timed)
     std::vector<hipEvent_t> ev((size_t)n_iter * kEv);
     hipError_t e = hipSuccess;
     size_t made = 0;
     for (; made < ev.size() && e == hipSuccess; made++) e = hipEventCreate(&ev[made]);
     if (e != hipSuccess) made--;
-    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++) {
-        set_fork(c);
+    for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
         e = run_iteration_timed(c, &ev[(size_t)kEv * it]);
-        if (e == hipSuccess) c->t_host++;
-    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     double* acc[8] = {&out->snap_ms, &out->sort_ms, &out->tree_ms, &out->traverse_ms,
                       &out->zsum_ms, &out->attract_ms, &out->finalize_ms, &out->reorder_ms};
-    // (from, to) event of each pass: main-stream passes, the row sums on the
-    // second stream, update + scaling from the join, renumbering
-    const int span[8][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {9, 10}, {6, 7}, {7, 8}};
+    // (from, to) events of each pass: main-stream passes, the row sums on
+    // the second stream (its two launches: one of them leaves at once),
+    // update + scaling from the join, renumbering
+    const int span[9][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {9, 10}, {6, 7}, {7, 8},
+                            {11, 12}};
+    const int into[9] = {0, 1, 2, 3, 4, 5, 6, 7, 5};
     for (int32_t it = 0; it < n_iter && e == hipSuccess; it++)
-        for (int p = 0; p < 8 && e == hipSuccess; p++) {
+        for (int p = 0; p < 9 && e == hipSuccess; p++) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, ev[(size_t)kEv * it + span[p][0]],
                                     ev[(size_t)kEv * it + span[p][1]]);
-            *acc[p] += ms;
+            *acc[into[p]] += ms;
         }
     for (size_t i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess) return device_error(c, e, "step_profiled");
@@ -573,7 +565,7 @@ psne_status pixelsne_set_state(pixelsne_ctx* c, const void* z, const void* u, co
     h.uscale[0] = h.uscale[1] = 1.0;
     h.t = iteration;
     h.nonfinite = 0;
-    c->t_host = iteration;
+    reset_fork_tuner(h, c->prm.attract_fork);
     e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = run_set_state(c, z, u, g);
     // the renumbering schedule as it stands after `iteration` iterations (the

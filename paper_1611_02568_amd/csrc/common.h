@@ -35,10 +35,33 @@ struct DevScalars {
     int64_t n_nodes;    // occupied cells of the last tree
     int64_t n_chunks;   // row chunks of the attraction's copy of P
     uint32_t att_next;  // the attraction's work queue: next row chunk to take
-    uint32_t att_pad;
+    int32_t fork_late;  // this iteration's row sums start after the cells (else after snap)
+    uint64_t t_begin;   // wall clock (device ticks) when the second stream's first launch starts
+    float fork_ticks[2]; // moving average of the iteration time with each fork point
+                         // (ticks); 0: not measured yet
+    int32_t fork_count; // iterations since the last probe; < 0: probing (-left)
+    int32_t fork_gap;   // iterations from one probe to the next
     uint32_t level_size[kMaxLevelsAll];
     uint32_t level_base[kMaxLevelsAll + 1];
 };
+
+// The fork-point tuner (PSNE_FORK_AUTO): iterations between two probes of
+// the other fork point (the bounds of the gap), iterations per probe, and the
+// weight of a new time in a fork point's moving average.
+constexpr int kForkGapMin = 16;
+constexpr int kForkGapMax = 64;
+constexpr int kForkProbeLen = 2;
+constexpr float kForkWeight = 0.25f;
+
+// The fork-point tuner's starting state: the automatic choice starts after
+// the cells, the better point while the layout is compressed.
+inline void reset_fork_tuner(DevScalars& h, int32_t fork) {
+    h.fork_late = fork != PSNE_FORK_SNAP;
+    h.fork_ticks[0] = h.fork_ticks[1] = 0.f;
+    h.fork_count = 0;
+    h.fork_gap = kForkGapMin;
+    h.t_begin = 0;
+}
 
 // One quadtree cell as the traversal reads it (32 bytes, one scalar load).
 // child: index of the first child cell | (number of children - 1) << 30.

@@ -98,21 +98,18 @@ struct pixelsne_ctx {
     hipStream_t cap_stream = nullptr;
 
     // The attraction's row sums (A, internal order, state type [n][2]) run on
-    // a second stream, forked after the snap pass and joined before the
-    // update, so that the memory-bound sums share the GPU with the sort, tree
+    // a second stream, forked after the snap pass or after the cells (the
+    // device chooses each iteration) and joined before the update, so that the memory-bound sums share the GPU with the sort, tree
     // and the ALU-bound traversal.  side_blocks: its persistent grid, sized
     // to leave most of each CU to the traversal.  help_blocks: the grid of
     // the helper that joins the sums on the main stream after Z.
     void* A = nullptr;
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_cells = nullptr, ev_join = nullptr;
     int64_t side_blocks = 0;
     int64_t help_blocks = 0;
-    // [parity][fork after the cells]
-    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int32_t parity = 0;
-    int32_t t_host = 0;                      // iterations done, as the host counts them
-    bool fork_late = false;                  // this iteration forks after the cells
     bool graph_failed = false;
 
     std::vector<void*> allocs;

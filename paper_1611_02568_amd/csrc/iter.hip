@@ -1001,8 +1001,15 @@ __global__ __launch_bounds__(kBlock) void k_attract(
     const uint32_t* __restrict__ ch_row, const int64_t* __restrict__ rp_int,
     const uint32_t* __restrict__ pk, const T* __restrict__ val, const T* __restrict__ z,
     const T* __restrict__ R, DevScalars* __restrict__ sc, double alpha,
-    const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout) {
+    const uint32_t* __restrict__ orig, T* __restrict__ Aout, T* __restrict__ Bout, int early) {
     using V = v2_t<T>;
+    if (MODE == 0 && early) {
+        // the launch right after the snap pass: it stamps the clock for the
+        // fork-point tuner and leaves at once when this iteration forks after
+        // the cells (or, EARLY = 2, when the second stream has no blocks)
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->t_begin = wall_clock64();
+        if (early > 1 || sc->fork_late) return;
+    }
     __shared__ T acc[4][kChunkRows][2];
     __shared__ V zrow[kChunkRows + 1];   // entry kChunkRows: 0 for lanes past the end
     __shared__ uint32_t s_next;
@@ -1191,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const T* __restrict__ zh, int
 // screen-driven scaling: gamma = max - min + eps per axis (Section 4.2)
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ mm_part,
                                                      int64_t m, DevScalars* __restrict__ sc,
-                                                     int r, double eps, int advance) {
+                                                     int r, double eps, int advance, int fork) {
     __shared__ double red[4][kBlock];
     double mn0 = INFINITY, mn1 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY;
     for (int64_t i = threadIdx.x; i < m; i += kBlock) {
@@ -1222,7 +1229,41 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
             sc->uscale[d] = (double)r / gamma;
             sc->s[d] = sc->s[d] * (gamma / (double)r);
         }
-        if (advance) sc->t += 1;
+        if (advance) {
+            sc->t += 1;
+            // The fork-point tuner.  The time from the snap pass to here is
+            // the iteration's (the snap pass and the renumbering take the
+            // same time at either fork point); it is averaged, as single
+            // iterations vary by about as much as the two points differ.
+            // Automatic: after fork_gap iterations at one point (whose times
+            // feed a moving average), kForkProbeLen run at the other (their
+            // plain mean: older probes are out of date), and the next takes
+            // the point with the smaller average.  The gap doubles (to
+            // kForkGapMax) while the probes confirm the choice and falls back
+            // to kForkGapMin when they change it.
+            const int cur = sc->fork_late;
+            const float ticks = (float)(wall_clock64() - sc->t_begin);
+            const float avg = sc->fork_ticks[cur];
+            const int k = sc->fork_count + kForkProbeLen;  // sample of this probe
+            if (fork == PSNE_FORK_AUTO && sc->fork_count < 0)
+                sc->fork_ticks[cur] = k == 0 ? ticks : avg + (ticks - avg) / (float)(k + 1);
+            else
+                sc->fork_ticks[cur] = avg > 0.f ? avg + kForkWeight * (ticks - avg) : ticks;
+            int next = cur;
+            if (fork != PSNE_FORK_AUTO) {
+                next = fork == PSNE_FORK_CELLS;
+            } else if (sc->fork_count < 0) {
+                // a probe: go on with it, or take the decision after its last
+                if (++sc->fork_count == 0) {
+                    next = sc->fork_ticks[1] < sc->fork_ticks[0];
+                    sc->fork_gap = next == cur ? kForkGapMin : min(2 * sc->fork_gap, kForkGapMax);
+                }
+            } else if (++sc->fork_count >= sc->fork_gap) {
+                next = 1 - cur;
+                sc->fork_count = -kForkProbeLen;
+            }
+            sc->fork_late = next;
+        }
         sc->att_next = 0;
     }
 }
@@ -1602,35 +1643,39 @@ hipError_t run_attract(pixelsne_ctx* c, double alpha, void* A, void* B) {
     if (fp64(c))
         k_attract<double, 1><<<grid, kBlock, 0, c->stream>>>(
             c->ch_row, c->rp_int, c->pk, (const double*)c->vch, (const double*)c->z,
-            (const double*)c->R, c->sc, alpha, c->orig, (double*)A, (double*)B);
+            (const double*)c->R, c->sc, alpha, c->orig, (double*)A, (double*)B, 0);
     else
         k_attract<float, 1><<<grid, kBlock, 0, c->stream>>>(
             c->ch_row, c->rp_int, c->pk, (const float*)c->vch, (const float*)c->z,
-            (const float*)c->R, c->sc, alpha, c->orig, (float*)A, (float*)B);
+            (const float*)c->R, c->sc, alpha, c->orig, (float*)A, (float*)B, 0);
     return hipGetLastError();
 }
 
 // The iteration's attraction row sums into c->A: MODE 0 on the second
-// stream, or (HELP) the MODE 2 helper on the main stream, both taking chunks
+// stream (launched right after the snap pass, EARLY, and again after the
+// cells), or (HELP) the MODE 2 helper on the main stream, all taking chunks
 // from the same queue.
 template <int MODE>
-static hipError_t launch_attract_sums(pixelsne_ctx* c, const dim3 grid, hipStream_t s) {
+static hipError_t launch_attract_sums(pixelsne_ctx* c, const dim3 grid, hipStream_t s,
+                                      int early) {
     if (fp64(c))
         k_attract<double, MODE><<<grid, kBlock, 0, s>>>(
             c->ch_row, c->rp_int, c->pk, (const double*)c->vch, (const double*)c->z, nullptr,
-            c->sc, 0.0, c->orig, (double*)c->A, nullptr);
+            c->sc, 0.0, c->orig, (double*)c->A, nullptr, early);
     else
         k_attract<float, MODE><<<grid, kBlock, 0, s>>>(
             c->ch_row, c->rp_int, c->pk, (const float*)c->vch, (const float*)c->z, nullptr,
-            c->sc, 0.0, c->orig, (float*)c->A, nullptr);
+            c->sc, 0.0, c->orig, (float*)c->A, nullptr, early);
     return hipGetLastError();
 }
 
-static hipError_t run_attract_sums(pixelsne_ctx* c, bool help) {
+static hipError_t run_attract_sums(pixelsne_ctx* c, bool help, bool early = false) {
     const int64_t blocks = help ? c->help_blocks : c->side_blocks;
+    // the early launch always runs: it stamps the tuner's clock
+    if (early && blocks == 0) return launch_attract_sums<0>(c, dim3(1), c->side, 2);
     if (blocks == 0) return hipSuccess;
-    if (!help) return launch_attract_sums<0>(c, dim3((unsigned)blocks), c->side);
-    return launch_attract_sums<2>(c, dim3((unsigned)blocks), c->stream);
+    if (help) return launch_attract_sums<2>(c, dim3((unsigned)blocks), c->stream, 0);
+    return launch_attract_sums<0>(c, dim3((unsigned)blocks), c->side, early ? 1 : 0);
 }
 
 static hipError_t run_update(pixelsne_ctx* c) {
@@ -1649,41 +1694,48 @@ static hipError_t run_update(pixelsne_ctx* c) {
 
 hipError_t run_finalize(pixelsne_ctx* c, int advance) {
     k_finalize<<<1, kBlock, 0, c->stream>>>(c->mm_part, attract_blocks(c->n), c->sc, c->r,
-                                            c->prm.eps, advance);
+                                            c->prm.eps, advance, c->prm.attract_fork);
     return hipGetLastError();
 }
 
 // One iteration.  The attraction's row sums need only the snapped positions
-// and P: they are forked onto the second stream after the snap pass (and run
-// while this stream sorts, builds the tree, walks it and reduces Z) or, when
-// c->fork_late, after the tree (beside the walk only); the update joins them.
-// EV, when given, receives the pass boundaries: [0..5]
-// before snap, sort, tree, traverse, Z and after Z on this stream, [6] after
-// the join, [7] after update and scaling, [8] after a scheduled renumbering,
-// [9] and [10] around the row sums on the second stream.
+// and P: the second stream takes them up either after the snap pass (beside
+// the sort, the tree, the walk and Z) or after the tree (beside the walk and
+// Z only), as DevScalars::fork_late says; both points are in every
+// iteration's launch sequence, and the launch at the point not chosen leaves
+// at once (the early one) or finds the queue empty (the late one).  The
+// helper on this stream takes what is left after Z, and the update joins.
+// EV, when given, receives the pass boundaries: [0..5] before snap, sort,
+// tree, traverse, Z and after Z on this stream, [6] after the join, [7] after
+// update and scaling, [8] after a scheduled renumbering, [9] and [10] around
+// the second stream's launch after the snap pass, [11] and [12] around its
+// launch after the cells.
 static hipError_t iteration(pixelsne_ctx* c, hipEvent_t* ev) {
     hipError_t e;
     auto mark = [&](int k, hipStream_t s) {
         return ev ? hipEventRecord(ev[k], s) : hipSuccess;
     };
-    auto fork = [&]() {
+    auto join_at = [&](hipEvent_t at) {
         hipError_t f;
-        if ((f = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return f;
-        if ((f = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return f;
-        if ((f = mark(9, c->side)) != hipSuccess) return f;
-        if ((f = run_attract_sums(c, false)) != hipSuccess) return f;
-        if ((f = mark(10, c->side)) != hipSuccess) return f;
-        return hipEventRecord(c->ev_join, c->side);
+        if ((f = hipEventRecord(at, c->stream)) != hipSuccess) return f;
+        return hipStreamWaitEvent(c->side, at, 0);
     };
     if ((e = mark(0, c->stream)) != hipSuccess) return e;
     if ((e = run_snap(c)) != hipSuccess) return e;
     if ((e = mark(1, c->stream)) != hipSuccess) return e;
-    if (!c->fork_late && (e = fork()) != hipSuccess) return e;
+    if ((e = join_at(c->ev_fork)) != hipSuccess) return e;
+    if ((e = mark(9, c->side)) != hipSuccess) return e;
+    if ((e = run_attract_sums(c, false, true)) != hipSuccess) return e;
+    if ((e = mark(10, c->side)) != hipSuccess) return e;
     if ((e = run_sort(c)) != hipSuccess) return e;
     if ((e = mark(2, c->stream)) != hipSuccess) return e;
     if ((e = run_tree(c)) != hipSuccess) return e;
     if ((e = mark(3, c->stream)) != hipSuccess) return e;
-    if (c->fork_late && (e = fork()) != hipSuccess) return e;
+    if ((e = join_at(c->ev_cells)) != hipSuccess) return e;
+    if ((e = mark(11, c->side)) != hipSuccess) return e;
+    if ((e = run_attract_sums(c, false)) != hipSuccess) return e;
+    if ((e = mark(12, c->side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
     if ((e = run_traverse(c, nullptr, nullptr, nullptr)) != hipSuccess) return e;
     if ((e = mark(4, c->stream)) != hipSuccess) return e;
     if ((e = run_zsum(c)) != hipSuccess) return e;
@@ -1708,6 +1760,7 @@ hipError_t run_init_state(pixelsne_ctx* c, const double* Y, uint64_t seed, doubl
     h.s[0] = h.s[1] = 1.0;            // the initial frame is y itself
     h.scale[0] = h.scale[1] = 1.0;
     h.uscale[0] = h.uscale[1] = 1.0;
+    reset_fork_tuner(h, c->prm.attract_fork);
     hipError_t e = hipMemcpyAsync(c->sc, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return e;
     const int64_t nb = attract_blocks(c->n);

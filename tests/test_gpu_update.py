@@ -127,10 +127,11 @@ def test_attraction_work_split_changes_nothing(psne, near_switch, prec):
     """The attraction's row chunks come from one queue shared by the second
     stream's blocks and the helper that joins after Z; who takes a chunk, and
     where the second stream forks (after the snap pass, after the cells, or
-    switching at the end of the early exaggeration, which the 5 steps from
-    t = 247 cross), must not change a bit.  (0, h) puts every chunk on the
-    helper, (b, 0) every chunk on the second stream; the helper-only run is
-    also held to the oracle's bar."""
+    as the device-side tuner picks, which probes the other point after 16
+    iterations: the 20 steps cross its first probe), must not change a bit.
+    (0, h) puts every chunk on the helper, (b, 0) every chunk on the second
+    stream; the helper-only run is also held to the oracle's bar after 5
+    steps."""
     P, st = near_switch
     dt = np.float64 if prec == 1 else np.float32
     o = _rounded_state(st, dt)
@@ -145,6 +146,9 @@ def test_attraction_work_split_changes_nothing(psne, near_switch, prec):
         ctx.step(5)
         s = ctx.get_state()
         got[(side, help_, fork)] = [s[k].cpu().numpy() for k in ("z", "u", "g")]
+        ctx.step(15)
+        s = ctx.get_state()
+        got[(side, help_, fork)] += [s[k].cpu().numpy() for k in ("z", "u", "g")]
     ref = got[(2, 3, 2)]
     for key, v in got.items():
         for a, b in zip(ref, v):
