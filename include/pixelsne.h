@@ -241,6 +241,14 @@ typedef struct {
     double Z;                 /* last Barnes-Hut normaliser */
     int64_t level_size[17];   /* occupied cells per level 0..L of the last tree */
     int32_t renumberings;     /* scheduled internal renumberings so far */
+    int32_t fork_cells;       /* where the next iteration's row sums fork (attract_fork):
+                                 1 after the cells, 0 after the snap pass */
+    double fork_ms[2];        /* the fork-point tuner's iteration times, from the second
+                                 stream's first launch to the end of the update, in ms:
+                                 [0] forked after the snap pass, [1] after the cells
+                                 (a moving average; under PSNE_FORK_AUTO the point not
+                                 in use holds its last probe's mean); 0 = not measured
+                                 since the context's start or the last set_state */
 } pixelsne_stats;
 
 /* Synchronises the stream. */

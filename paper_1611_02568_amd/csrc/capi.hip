@@ -543,6 +543,12 @@ psne_status pixelsne_get_stats(const pixelsne_ctx* c, pixelsne_stats* out) {
     out->Z = h.Z;
     for (int l = 0; l <= c->L && l < 17; l++) out->level_size[l] = h.level_size[l];
     out->renumberings = c->scheduled_reorders;
+    out->fork_cells = h.fork_late;
+    int khz = 0;   // the device wall clock's rate
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device);
+    if (e != hipSuccess) return device_error(const_cast<pixelsne_ctx*>(c), e, "get_stats");
+    if (khz > 0)
+        for (int k = 0; k < 2; k++) out->fork_ms[k] = (double)h.fork_ticks[k] / (double)khz;
     return PSNE_OK;
 }
 

@@ -63,7 +63,8 @@ class Stats(C.Structure):
         ("r", C.c_int32), ("L", C.c_int32), ("k", C.c_int32),
         ("precision", C.c_int32), ("com_mode", C.c_int32), ("iteration", C.c_int32),
         ("s", C.c_double * 2), ("Z", C.c_double), ("level_size", C.c_int64 * 17),
-        ("renumberings", C.c_int32),
+        ("renumberings", C.c_int32), ("fork_cells", C.c_int32),
+        ("fork_ms", C.c_double * 2),
     ]
 
 

@@ -122,3 +122,36 @@ def test_init3_validation(psne, kw, r, n, frag):
                                           r, C.byref(p))
     assert not h
     assert frag in psne.load().pixelsne_last_error().decode()
+
+
+def test_struct_layouts_match_header(psne, tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets, as a C compiler lays them out (gcc on the header itself)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [("pixelsne_params", psne.Params), ("pixelsne_stats", psne.Stats),
+               ("pixelsne_pass_times", psne.PassTimes),
+               ("pixelsne_refine_result", psne.RefineResult)]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", f'#include "{HEADER}"',
+             "int main(void) {"]
+    for cname, cls in structs:
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        name, key, val = line.split()
+        got[(name, key)] = int(val)
+    for cname, cls in structs:
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)

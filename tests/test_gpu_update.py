@@ -159,3 +159,34 @@ def test_attraction_work_split_changes_nothing(psne, near_switch, prec):
         assert np.max(np.abs(z - o.z)) <= 1e-9 * R
     else:
         assert np.median(np.abs(z - o.z)) <= 5 * 2.0 ** -20 * R
+
+
+def test_fork_tuner_state(psne, near_switch):
+    """The fork-point tuner's state as pixelsne_get_stats reports it: a fixed
+    setting keeps its point and measures only that one; the automatic one
+    starts after the cells and, past its first probe (after 16 iterations,
+    two at the other point), has measured both; set_state clears the
+    measurements.  Times are positive and below a second per iteration."""
+    P, _ = near_switch
+    for fork in (psne.FORK_SNAP, psne.FORK_CELLS, psne.FORK_AUTO):
+        ctx = psne.Context.from_P(*P, screen=R, precision=0, attract_fork=fork,
+                                  Y_init=torch.as_tensor(datagen.initial_embedding(2000, seed=5)))
+        st = ctx.stats()
+        assert st.fork_cells == (0 if fork == psne.FORK_SNAP else 1)
+        assert list(st.fork_ms) == [0.0, 0.0]
+        ctx.step(20)
+        st = ctx.stats()
+        ms = list(st.fork_ms)
+        assert all(0.0 <= t < 1000.0 for t in ms), ms
+        if fork == psne.FORK_SNAP:
+            assert st.fork_cells == 0 and ms[0] > 0.0 and ms[1] == 0.0
+        elif fork == psne.FORK_CELLS:
+            assert st.fork_cells == 1 and ms[1] > 0.0 and ms[0] == 0.0
+        else:
+            assert st.fork_cells in (0, 1) and ms[0] > 0.0 and ms[1] > 0.0
+        s = ctx.get_state()
+        ctx.set_state(s["z"], s["s"], u=s["u"], g=s["g"], iteration=s["iteration"])
+        st = ctx.stats()
+        assert list(st.fork_ms) == [0.0, 0.0]
+        assert st.fork_cells == (0 if fork == psne.FORK_SNAP else 1)
+        del ctx
