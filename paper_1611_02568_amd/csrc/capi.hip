@@ -166,6 +166,7 @@ hipError_t alloc_iteration_buffers(pixelsne_ctx* c) {
     if ((e = dalloc(c, &tb.wfirst, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.wlast, sizeof(double2) * (size_t)ceil_div(n, 64))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.first_child, 4 * (size_t)mx)) != hipSuccess) return e;
+    if (!dtree && (e = dalloc(c, &tb.cell_start, 4 * (size_t)mx)) != hipSuccess) return e;
     // + 3: the traversal loads a sibling group as four records at once
     if ((e = dalloc(c, &tb.nodes, sizeof(Node) * (size_t)(mx + 3))) != hipSuccess) return e;
     if ((e = dalloc(c, &tb.nsum, sizeof(double2) * (size_t)mx)) != hipSuccess) return e;

@@ -24,6 +24,7 @@ struct TreeBufs {
     double2* wfirst = nullptr;               // [n / 64] per-wave partial leaf sums
     double2* wlast = nullptr;
     uint32_t* first_child = nullptr;         // [max_nodes]
+    uint32_t* cell_start = nullptr;          // [max_nodes] first sorted position (pixel tree)
     Node* nodes = nullptr;                   // [max_nodes]
     CellF* cells32 = nullptr;                // [max_nodes] FP32 copy (FP32 opening test)
     double2* nsum = nullptr;                 // [max_nodes] coordinate sums (FP64)

@@ -213,7 +213,10 @@ __global__ __launch_bounds__(kBlock) void k_tree_count(const uint32_t* __restric
 
 // Number each cell: for every level, the rank of the cell holding sorted
 // position s.  Positions that open a cell write its start and first
-// child (children of a cell are consecutive in the next level).
+// child (children of a cell are consecutive in the next level) into dense
+// per-cell arrays; the cell record itself is written whole, once, by the
+// pass that sums the cell (a part of a record written here would cost a read
+// of the rest of its memory line).
 // Then the leaf sums, part 1: gather the position into sorted order and run a
 // segmented inclusive scan over each wave's 64 positions (segments = leaves,
 // fixed shuffle pattern, FP64).  A leaf that starts and ends inside the wave
@@ -224,7 +227,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tree_nodes(
     const uint32_t* __restrict__ keys, int64_t n, int L, const uint32_t* __restrict__ off,
     int64_t nb, const uint32_t* __restrict__ ltot, DevScalars* __restrict__ sc,
-    uint32_t* __restrict__ first_child, Node* __restrict__ nodes,
+    uint32_t* __restrict__ first_child, uint32_t* __restrict__ cell_start,
     uint32_t* __restrict__ leaf_of, const uint32_t* __restrict__ perm, const T* __restrict__ z,
     double2* __restrict__ nsum, T* __restrict__ zs, double2* __restrict__ wfirst,
     double2* __restrict__ wlast) {
@@ -281,8 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
         for (int l = 0; l < kMaxLevels; l++) {
             if (l <= L && l0 <= l) {
                 const uint32_t gid = lbase[l] + rank[l];
-                nodes[gid].start = (uint32_t)s;
-                nodes[gid].level = (uint32_t)l;
+                cell_start[gid] = (uint32_t)s;
                 first_child[gid] = l < L ? lbase[l < L ? l + 1 : L] + rank[l < L ? l + 1 : L] : 0u;
             }
         }
@@ -316,8 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_nodes(
 __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __restrict__ c32,
                                            double2* __restrict__ nsum,
                                            uint32_t g, int level, int L, double sx, double sy,
-                                           uint32_t count, uint32_t child, uint32_t key0,
-                                           int com_mode, float rs0, float rs1) {
+                                           uint32_t count, uint32_t child, uint32_t start,
+                                           uint32_t key0, int com_mode, float rs0, float rs1) {
     double cx, cy;
     if (com_mode == PSNE_COM_CELL_CENTER) {
         const int sh = L - level;
@@ -329,10 +331,14 @@ __device__ __forceinline__ void write_node(Node* __restrict__ nodes, CellF* __re
         cx = sx / (double)count;
         cy = sy / (double)count;
     }
-    nodes[g].cx = cx;
-    nodes[g].cy = cy;
-    nodes[g].count = count;
-    nodes[g].child = child;
+    Node nd;
+    nd.cx = cx;
+    nd.cy = cy;
+    nd.count = count;
+    nd.child = child;
+    nd.start = start;
+    nd.level = (uint32_t)level;
+    nodes[g] = nd;
     nsum[g] = double2{sx, sy};
     if (c32) c32[g] = CellF{(float)cx * rs0, (float)cy * rs1, (float)count, child};
 }
@@ -350,7 +356,8 @@ constexpr uint32_t kLeafSerial = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tree_leaves(
     const uint32_t* __restrict__ keys, int64_t n, int L, int com_mode,
-    const DevScalars* __restrict__ sc, Node* __restrict__ nodes, CellF* __restrict__ c32,
+    const DevScalars* __restrict__ sc, const uint32_t* __restrict__ cell_start,
+    Node* __restrict__ nodes, CellF* __restrict__ c32,
     double2* __restrict__ nsum, const double2* __restrict__ wfirst,
     const double2* __restrict__ wlast) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -361,8 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
     if ((t & ~(int64_t)(kWave - 1)) >= (int64_t)nleaf) return;
     const bool valid = t < (int64_t)nleaf;
     const uint32_t gid = sc->level_base[L] + (uint32_t)(valid ? t : 0);
-    const uint32_t start = valid ? nodes[gid].start : 0u;
-    const uint32_t end = !valid ? 1u : (t + 1 < nleaf) ? nodes[gid + 1].start : (uint32_t)n;
+    const uint32_t start = valid ? cell_start[gid] : 0u;
+    const uint32_t end = !valid ? 1u : (t + 1 < nleaf) ? cell_start[gid + 1] : (uint32_t)n;
     const uint32_t wa = start / kWave, wb = (end - 1) / kWave;
     double sx = 0.0, sy = 0.0;
     const bool spans = valid && wa != wb;
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
         sx = (wlast[wa].x + sx) + wfirst[wb].x;
         sy = (wlast[wa].y + sy) + wfirst[wb].y;
     }
-    write_node(nodes, c32, nsum, gid, L, L, sx, sy, end - start, 0u, keys[start], com_mode,
+    write_node(nodes, c32, nsum, gid, L, L, sx, sy, end - start, 0u, start, keys[start], com_mode,
                cell_scale(sc->s[0]), cell_scale(sc->s[1]));
 }
 
@@ -409,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_leaves(
 __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, int l, int L,
                                            int com_mode, const DevScalars* __restrict__ sc,
                                            const uint32_t* __restrict__ first_child,
+                                           const uint32_t* __restrict__ cell_start,
                                            Node* __restrict__ nodes, CellF* __restrict__ c32,
                                            double2* __restrict__ nsum, uint32_t t, uint32_t m,
                                            float rs0, float rs1) {
@@ -423,8 +431,9 @@ __device__ __forceinline__ void inner_cell(const uint32_t* __restrict__ keys, in
         ay += v.y;
         c += nodes[q].count;
     }
-    write_node(nodes, c32, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30),
-               keys[nodes[g].start], com_mode, rs0, rs1);
+    const uint32_t st = cell_start[g];
+    write_node(nodes, c32, nsum, g, l, L, ax, ay, c, fc | ((lc - fc - 1) << 30), st, keys[st],
+               com_mode, rs0, rs1);
 }
 
 // Up to kGroupLevels consecutive levels of inner cells in one launch.  Block
@@ -442,6 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_group(const uint32_t* __restric
                                                        uint32_t K,
                                                        const DevScalars* __restrict__ sc,
                                                        const uint32_t* __restrict__ first_child,
+                                                       const uint32_t* __restrict__ cell_start,
                                                        Node* __restrict__ nodes,
                                                        CellF* __restrict__ c32,
                                                        double2* __restrict__ nsum) {
@@ -469,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_tree_group(const uint32_t* __restric
     for (int l = lbot; l >= ltop; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t x = lo[l - ltop] + t; x < hi[l - ltop]; x += kBlock)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, x, m, rs0, rs1);
+            inner_cell(keys, l, L, com_mode, sc, first_child, cell_start, nodes, c32, nsum, x, m,
+                       rs0, rs1);
         __syncthreads();
     }
 }
@@ -484,6 +495,7 @@ __global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __rest
                                                           int top, int L, int com_mode,
                                                           const DevScalars* __restrict__ sc,
                                                           const uint32_t* __restrict__ first_child,
+                                                          const uint32_t* __restrict__ cell_start,
                                                           Node* __restrict__ nodes,
                                                           CellF* __restrict__ c32,
                                                           double2* __restrict__ nsum) {
@@ -491,7 +503,8 @@ __global__ __launch_bounds__(kTopThreads) void k_tree_top(const uint32_t* __rest
     for (int l = top; l >= 0; l--) {
         const uint32_t m = sc->level_size[l];
         for (uint32_t t = threadIdx.x; t < m; t += kTopThreads)
-            inner_cell(keys, l, L, com_mode, sc, first_child, nodes, c32, nsum, t, m, rs0, rs1);
+            inner_cell(keys, l, L, com_mode, sc, first_child, cell_start, nodes, c32, nsum, t, m,
+                       rs0, rs1);
         __syncthreads();
     }
 }
@@ -1570,19 +1583,19 @@ hipError_t run_tree(pixelsne_ctx* c) {
     if (fp64(c)) {
         k_tree_nodes<double><<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
             keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child,
-            tb.nodes, tb.leaf_of, perm, (const double*)c->z, tb.nsum, (double*)tb.zs, tb.wfirst,
-            tb.wlast);
+            tb.cell_start, tb.leaf_of, perm, (const double*)c->z, tb.nsum, (double*)tb.zs,
+            tb.wfirst, tb.wlast);
         k_tree_leaves<double><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
-            tb.wlast);
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.cell_start, tb.nodes, tb.cells32,
+            tb.nsum, tb.wfirst, tb.wlast);
     } else {
         k_tree_nodes<float><<<dim3((unsigned)tb.tree_blocks), kBlock, 0, c->stream>>>(
             keys, c->n, c->L, tb.lvl_cnt, tb.tree_blocks, tb.ltot, c->sc, tb.first_child,
-            tb.nodes, tb.leaf_of, perm, (const float*)c->z, tb.nsum, (float*)tb.zs, tb.wfirst,
-            tb.wlast);
+            tb.cell_start, tb.leaf_of, perm, (const float*)c->z, tb.nsum, (float*)tb.zs,
+            tb.wfirst, tb.wlast);
         k_tree_leaves<float><<<grid_for(c->n), kBlock, 0, c->stream>>>(
-            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.nodes, tb.cells32, tb.nsum, tb.wfirst,
-            tb.wlast);
+            keys, c->n, c->L, c->prm.com_mode, c->sc, tb.cell_start, tb.nodes, tb.cells32,
+            tb.nsum, tb.wfirst, tb.wlast);
     }
     const int top = c->L - 1 < kTopLevel ? c->L - 1 : kTopLevel;
     for (int lbot = c->L - 1; lbot > top; lbot -= kGroupLevels) {
@@ -1591,12 +1604,13 @@ hipError_t run_tree(pixelsne_ctx* c) {
         const int64_t cap = ltop < 31 ? std::min((int64_t)1 << (2 * ltop), c->n) : c->n;
         const int64_t K = ceil_div(cap, kGroupBlocks);
         k_tree_group<<<dim3((unsigned)ceil_div(cap, K)), kBlock, 0, c->stream>>>(
-            keys, ltop, lbot, c->L, c->prm.com_mode, (uint32_t)K, c->sc, tb.first_child, tb.nodes,
-            tb.cells32, tb.nsum);
+            keys, ltop, lbot, c->L, c->prm.com_mode, (uint32_t)K, c->sc, tb.first_child,
+            tb.cell_start, tb.nodes, tb.cells32, tb.nsum);
     }
     if (top >= 0)
         k_tree_top<<<1, kTopThreads, 0, c->stream>>>(keys, top, c->L, c->prm.com_mode, c->sc,
-                                                     tb.first_child, tb.nodes, tb.cells32, tb.nsum);
+                                                     tb.first_child, tb.cell_start, tb.nodes,
+                                                     tb.cells32, tb.nsum);
     return hipGetLastError();
 }
 
