@@ -4,16 +4,18 @@
 //   sort        stable LSD radix sort of (key, index), 8-bit digits, LDS ranking
 //   tree        P-Quadtree (Section 4.1) as a linear tree: one node per occupied
 //               (level, Morton prefix); counts and FP64 coordinate sums (Eq. 8)
-//               reduced bottom-up in one pass
+//               reduced bottom-up, up to five levels per launch
 //   traverse    Barnes-Hut repulsion (Eq. 5, 11, 12): one wavefront walks the
 //               union of the interaction lists of 64 Morton-consecutive points,
 //               each stack entry carrying the mask of lanes still descending
 //   zsum        Z = sum_i Z_i in FP64, fixed order
 //   attract     row sums of the sparse attraction over CSR P (Eq. 5), on a
-//               second stream beside sort, tree, traversal and Z
+//               second stream beside the traversal and Z (and beside sort and
+//               tree too, when the fork-point tuner finds that faster)
 //   update      B = alpha A - R / Z, gains/momentum step, new positions and
 //               per-block min/max of them
-//   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++
+//   finalize    screen scaling factors, scale bookkeeping (Eq. 13), iteration++,
+//               the fork-point tuner
 #include <math.h>
 
 #include <algorithm>
