@@ -981,9 +981,6 @@ template <> __device__ __forceinline__ uint32_t stream_load<uint32_t>(__amdgpu_b
                                                                       int i) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kStreamPolicy);
 }
-template <> __device__ __forceinline__ float stream_load<float>(__amdgpu_buffer_rsrc_t r, int i) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kStreamPolicy));
-}
 template <> __device__ __forceinline__ double stream_load<double>(__amdgpu_buffer_rsrc_t r, int i) {
     return __longlong_as_double(
         (long long)__builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kStreamPolicy));

@@ -62,22 +62,6 @@ __device__ __forceinline__ bool knn_less(double da, int32_t ja, double db, int32
     return da < db || (da == db && ja < jb);
 }
 
-// keep the best k of a sorted list (ascending by (d, j)), distinct entries
-__device__ __forceinline__ void list_insert(double* __restrict__ ld, int32_t* __restrict__ lj,
-                                            int32_t& m, int32_t k, double d, int32_t j) {
-    if (m == k && !knn_less(d, j, ld[k - 1], lj[k - 1])) return;
-    for (int32_t q = 0; q < m; q++)
-        if (lj[q] == j) return;
-    int32_t pos = m < k ? m : k - 1;
-    while (pos > 0 && knn_less(d, j, ld[pos - 1], lj[pos - 1])) {
-        ld[pos] = ld[pos - 1];
-        lj[pos] = lj[pos - 1];
-        pos--;
-    }
-    ld[pos] = d;
-    lj[pos] = j;
-    if (m < k) m++;
-}
 
 __global__ __launch_bounds__(kBlock) void k_rp_init(uint32_t* __restrict__ perm,
                                                     uint32_t* __restrict__ sa,
