@@ -838,10 +838,10 @@ int orc_repulsion_rows(const void* h, const double* z, const double* beta, doubl
             if (use) {
                 double dx = zx - cx, dy = zy - cy;
                 double d2 = b1 * dx * dx + b2 * dy * dy;
-                double q = 1.0 / (1.0 + d2);
-                zsum += m * q;
-                rx += m * q * q * dx;
-                ry += m * q * q * dy;
+                double qij = 1.0 / (1.0 + d2);
+                zsum += m * qij;
+                rx += m * qij * qij * dx;
+                ry += m * qij * qij * dy;
             } else {
                 for (int ch = 3; ch >= 0; ch--)
                     if (nd->child[ch] >= 0) stack[sp++] = nd->child[ch];
@@ -884,9 +884,9 @@ int orc_attraction_rows(const double* z, int64_t n, const double* beta, const in
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
             int32_t j = col[e];
             double dx = z[2 * i] - z[2 * (int64_t)j], dy = z[2 * i + 1] - z[2 * (int64_t)j + 1];
-            double q = 1.0 / (1.0 + b1 * dx * dx + b2 * dy * dy);
-            ax += val[e] * q * dx;
-            ay += val[e] * q * dy;
+            double qij = 1.0 / (1.0 + b1 * dx * dx + b2 * dy * dy);
+            ax += val[e] * qij * dx;
+            ay += val[e] * qij * dy;
         }
         A[2 * q] = ax; A[2 * q + 1] = ay;
     }
