@@ -13,7 +13,6 @@ saves the early phase, not the slow final descent both runs share.  At
 An untrained network's placement takes the fallback: the refinement budget
 passes and the plain iterations continue.
 """
-import numpy as np
 import pytest
 import torch
 

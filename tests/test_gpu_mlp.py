@@ -13,7 +13,6 @@ import torch
 
 import oracle
 from oracle import mlp as omlp
-from paper_1611_02568_amd import datagen
 
 pytestmark = pytest.mark.gpu
 

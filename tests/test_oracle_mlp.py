@@ -1,6 +1,5 @@
 """Pins of the FP64 MLP reference: finite differences, GELU against the normal
 CDF, bfloat16 rounding against torch's conversion."""
-import math
 
 import numpy as np
 import torch
