@@ -155,3 +155,17 @@ def test_struct_layouts_match_header(psne, tmp_path):
         assert got[(cname, "size")] == C.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+def test_enum_constants_match_header(psne):
+    """Every PSNE_* enumerator of the header has the value the binding uses
+    (the binding's name drops the prefix, except for the status codes)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {}
+    for body in re.findall(r"\benum\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(PSNE_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            values[name] = int(val)
+    assert len(values) >= 20
+    for name, val in values.items():
+        py = name if name.startswith(("PSNE_OK", "PSNE_E_")) else name[len("PSNE_"):]
+        assert getattr(psne, py) == val, (name, getattr(psne, py, None), val)
