@@ -169,3 +169,40 @@ def test_enum_constants_match_header(psne):
     for name, val in values.items():
         py = name if name.startswith(("PSNE_OK", "PSNE_E_")) else name[len("PSNE_"):]
         assert getattr(psne, py) == val, (name, getattr(psne, py, None), val)
+
+
+def _c_kind(decl):
+    """The ABI kind of a C declaration ("const double* s" -> "ptr")."""
+    decl = decl.strip()
+    if "*" in decl:
+        return "ptr"
+    words = [w for w in decl.replace("const ", "").split() if w]
+    base = words[0]
+    return {"int32_t": "i32", "int64_t": "i64", "uint64_t": "u64", "double": "f64",
+            "float": "f32", "int": "i32", "psne_status": "i32", "void": "void"}[base]
+
+
+def _py_kind(t):
+    if t is None:
+        return "void"
+    if t in (C.c_void_p, C.c_char_p) or (isinstance(t, type) and issubclass(t, C._Pointer)):
+        return "ptr"
+    return {C.c_int32: "i32", C.c_int: "i32", C.c_int64: "i64", C.c_uint64: "u64",
+            C.c_double: "f64", C.c_float: "f32"}[t]
+
+
+def test_signatures_match_header(psne):
+    """Each declared function's return and parameter kinds (pointer, 32/64-bit
+    integer, float, double) equal the binding's restype and argtypes."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = re.findall(r"([A-Za-z_][\w\s\*]*?)\b(pixelsne3?_\w+)\s*\(([^)]*)\)\s*;", src)
+    seen = set()
+    for ret, name, params in protos:
+        params = params.strip()
+        args = [] if params in ("", "void") else [p for p in params.split(",")]
+        restype, argtypes = psne.SIGNATURES[name]
+        ret_kind = "ptr" if "*" in ret else _c_kind(ret.split()[-1])
+        assert _py_kind(restype) == ret_kind, (name, "return")
+        assert [_c_kind(a) for a in args] == [_py_kind(t) for t in argtypes], name
+        seen.add(name)
+    assert seen == set(psne.SIGNATURES)
