@@ -206,3 +206,33 @@ def test_signatures_match_header(psne):
         assert [_c_kind(a) for a in args] == [_py_kind(t) for t in argtypes], name
         seen.add(name)
     assert seen == set(psne.SIGNATURES)
+
+
+def test_c_program_links_and_calls(psne, tmp_path):
+    """A C program built against the header and linked with the library (no
+    Python in between) reads the defaults and gets a clean refusal for a bad
+    call, which does no device work."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        f'#include "{HEADER}"\n'
+        "#include <stdio.h>\n"
+        "int main(void) {\n"
+        "    pixelsne_params p;\n"
+        "    pixelsne_default_params(&p);\n"
+        "    pixelsne_ctx* c = pixelsne_init(NULL, 1, 4, 3.0, 512, 512);\n"
+        '    printf("%g %d %d %s\\n", p.theta, p.exag_iters, c == NULL,\n'
+        "           pixelsne_last_error());\n"
+        "    return 0;\n"
+        "}\n")
+    lib = os.path.dirname(psne.LIB_PATH)
+    exe = tmp_path / "use"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src), f"-L{lib}", "-lpixelsne",
+                    f"-Wl,-rpath,{lib}"], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert out[:3] == ["0.5", "250", "1"]
+    assert " ".join(out[3:]).startswith("n must be")
